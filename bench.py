@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Throughput of the free-energy search on one MI355X.
+
+One step = one pass of the whole path over the paper-scale workload: the
+Omega grid of Eq. (5) over a 1024 x 1024 lattice, 256 Delta in [0, 0.6], 64
+pair momenta Q = (j pi/512, 0), both bands, at h = 0.1, T = 0.002, followed by
+the per-row and global searches of Algorithm 1 (omega_argmin).  Inputs are
+resident on the GPU before the timed region; outputs and workspace are
+allocated once.
+
+The metric is k-point x parameter evaluations per second: one evaluation is
+one (k, Delta, Q, band) term of Eq. (5), counted on the full grid.  Prints one
+JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic operations of one evaluation of Eq. (4)-(5), with the (k, Q)
+# quantities hoisted as Algorithm 1 does (band energies generated per q):
+#   |Delta_k|^2 = Delta^2 eta^2 (1), s^2 + |Delta_k|^2 (1), sqrt (1),
+#   E+- = d +- R (2), -E/T (2), exp (2), 1 + exp (2), ln (2),
+#   sum of the two logs and the factor -T (2), accumulation over k (1).
+# Elementary functions count as one operation each.
+OPS_PER_EVAL = 16
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
+    ap.add_argument("--workload", default="paper")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-rows", type=int, default=4,
+                    help="Q rows per band in the CPU oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(cfg, rows_per_band):
+    """The FP64 oracle on a bounded sample of the same workload: both bands,
+    `rows_per_band` Q rows spread over the Q range, every Delta, full lattice."""
+    import numpy as np
+
+    import oracle
+    from paper_1412_8754_amd import workloads as W
+
+    oracle.build(force=False)
+    q = cfg["q"]
+    sel = np.unique(np.linspace(0, len(q) - 1, rows_per_band).round().astype(int))
+    pts = cfg["pts"]
+    t0 = time.perf_counter()
+    oracle.omega_grid(W.DEFAULT_MODEL, pts, cfg["delta"], q[sel], cfg["bands"])
+    dt = time.perf_counter() - t0
+    n_k = pts[0][2] * pts[0][3]
+    nb = 2 if cfg["bands"] == 3 else 1
+    evals = n_k * len(cfg["delta"]) * len(sel) * nb
+    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"{nb} bands x {len(sel)} of {len(q)} Q rows x {len(cfg['delta'])} Delta "
+                      f"at L={pts[0][2]} ({evals:.3e} evals, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
+              "supported (the work shards by independent (point, band, Q) units; see "
+              "the design notes)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1412_8754_amd import _abi, api
+    from paper_1412_8754_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = _abi.load()
+
+    cfg = W.config(args.workload)
+    pts = cfg["pts"]
+    prec = api.OMEGA_FP64 if args.precision == "fp64" else api.OMEGA_FP32_COMP
+    bands = cfg["bands"]
+    nb = _abi.n_bands(bands)
+    delta = torch.as_tensor(cfg["delta"], dtype=torch.float64, device=dev)
+    q = torch.as_tensor(cfg["q"], dtype=torch.float64, device=dev).contiguous()
+    n_d, n_q = delta.numel(), q.shape[0]
+    n_pts = len(pts)
+    ws_bytes = api.workspace_bytes(pts, n_d, n_q, bands, prec)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    idx = torch.empty((n_pts, nb, 2), dtype=torch.int32, device=dev)
+    omin = torch.empty((n_pts, nb), dtype=torch.float64, device=dev)
+    rows = torch.empty((n_pts, nb, n_q), dtype=torch.int32, device=dev)
+    om = torch.empty((n_pts, nb, n_q, n_d), dtype=torch.float64, device=dev)
+    m = _abi.make_model(W.DEFAULT_MODEL)
+    p = _abi.make_points(pts)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        rc = L.omega_argmin(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d, q.data_ptr(),
+                            n_q, bands, prec, 1e-11, ws.data_ptr(), ws_bytes, idx.data_ptr(),
+                            omin.data_ptr(), rows.data_ptr(), om.data_ptr(), stream.cuda_stream)
+        if rc != 0:
+            raise _abi.OmegaError(rc, "omega_argmin")
+
+    print(f"bench: workload={args.workload} precision={args.precision} steps={args.steps} "
+          f"warmup={args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # events around the sweep kernel of every timed step (same stream as the launch)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        L.omega_set_sweep_events(ev[i][0].cuda_event, ev[i][1].cuda_event)
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    L.omega_set_sweep_events(None, None)
+
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    sweep_ms = [a.elapsed_time(b) for a, b in ev]
+    sweep_avg = sum(sweep_ms) / len(sweep_ms)
+    evals_step = sum(pt[2] * pt[3] for pt in pts) * n_d * n_q * nb
+    value = evals_step / (ms_step * 1e-3)
+    achieved = OPS_PER_EVAL * evals_step / (sweep_avg * 1e-3) / 1e12
+    peak = PEAK_TFLOPS["f64" if args.precision == "fp64" else "f32"]
+    print(f"bench: {ms_step:.3f} ms/step, sweep kernel {sweep_avg:.3f} ms avg "
+          f"(min {min(sweep_ms):.3f}, max {max(sweep_ms):.3f}); argmin "
+          f"{idx.cpu().numpy().tolist()}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "k-point*param evals/s (Omega grid + argmin, Eq. (5) / Algorithm 1)",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: L={pts[0][2]}x{pts[0][3]}, {n_d} Delta in "
+                               f"[0,0.6], {n_q} Q=(j pi/512,0), {nb} bands, h={pts[0][0]}, "
+                               f"T={pts[0][1]}, full grid + argmin",
+                   "precision": args.precision, "evals_per_step": evals_step},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "sweep_%s_kernel<32>" % ("f64" if args.precision == "fp64"
+                                                        else "f32c"),
+                     "kernel_ms": sweep_avg, "ops_per_eval": OPS_PER_EVAL},
+    }
+    if not args.no_cpu:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cb = cpu_baseline(cfg, args.cpu_rows)
+        out["cpu_baseline"] = cb
+        print(f"bench: cpu {cb['value']:.3e} evals/s on {cb['cores']} threads; "
+              f"GPU/CPU = {value / cb['value']:.1f}x", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,155 @@
+/*
+ * omega.h -- C interface of libomega, the gfx950 (MI355X) implementation of
+ * the free-energy search of Januszewski, Ptok, Crivelli & Gardas, "GPU-based
+ * acceleration of free energy calculations in solid state physics".
+ *
+ * What is computed (all in the paper's notation, k_B = 1):
+ *   band energies    E_{eps,k}: App. A, Eqs. (A.1)-(A.4) (two-band model,
+ *                    eps = - hole-like, eps = + electron-like);
+ *   spin shift       E_{eps,k,sigma} = E_{eps,k} - (mu + sigma h), sigma = +1
+ *                    for spin up (Sec. 2, Eq. (1) and the text below it);
+ *   quasiparticles   Sec. 2, Eq. (4), pairs (k up, -k+Q down), gap
+ *                    Delta_{eps,k} = Delta cos kx cos ky (s+- form factor);
+ *   free energy      Sec. 2, Eq. (5):
+ *                    Omega_eps = -T sum_{+-,k} ln(1 + exp(-E^{+-}_{eps,k}/T))
+ *                                + sum_k (E_{eps,k,down} - 2 Delta^2 / V_eps)
+ *                    over the Lx x Ly momenta kx = 2 pi i/Lx, ky = 2 pi j/Ly;
+ *   search           Sec. 3.2, Algorithm 1 (Delta minimum per Q row, then the
+ *                    global minimum; bands are minimised separately).
+ *
+ * Conventions shared by every entry point
+ *   - Units: energies in |t1|.  T >= 0; T = 0 is the zero-temperature limit
+ *     (-T ln(1 + exp(-E/T)) -> min(E, 0)).  V_eps < 0 is attractive.
+ *   - Ownership: the caller owns every buffer.  "_dev" pointers are device
+ *     memory on the current HIP device; "_host" / plain struct pointers are
+ *     host memory read during the call only.  The library allocates no device
+ *     memory; scratch comes from the caller's workspace (ws_dev, ws_bytes),
+ *     sized by omega_workspace_bytes().
+ *   - Asynchrony: work is enqueued on `stream` (a hipStream_t; NULL = the null
+ *     stream) and the call returns without synchronising.  Outputs are valid
+ *     once the stream has reached the enqueued work.  Host arguments are
+ *     consumed before the call returns.  Calls sharing one workspace must be
+ *     ordered (same stream or explicit events).
+ *   - Errors: arguments are validated on the host before anything is
+ *     enqueued; an invalid call returns a negative OMEGA_E_* code and enqueues
+ *     nothing.  A HIP launch failure returns OMEGA_E_HIP.  Device arrays are
+ *     not validated: NaN in delta_dev or q_dev propagates into Omega.
+ *   - Determinism: for fixed inputs and workspace the results are bitwise
+ *     reproducible (fixed-order reductions, no atomics).
+ */
+#ifndef OMEGA_H
+#define OMEGA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Model constants.  t1..t4: hoppings of App. A, Eqs. (A.1)-(A.3) (the paper's
+ * values are t1=-1, t2=1.3, t3=t4=-0.85); mu: chemical potential (1.54 gives
+ * two electrons per site); V[0], V[1]: pairing strength V_eps of Eq. (5) for
+ * the E_- and E_+ band.  All finite, V[i] != 0. */
+typedef struct {
+    double t1, t2, t3, t4;
+    double mu;
+    double V[2];
+} omega_model;
+
+/* One (h, T) point of a phase diagram on an Lx x Ly lattice.
+ * h: Zeeman field of Eq. (1) (any finite sign); T: temperature, 0 or a normal
+ * positive double; 2 <= Lx, Ly <= 16384 and Lx*Ly <= 2^26. */
+typedef struct {
+    double h;
+    double T;
+    int32_t Lx, Ly;
+} omega_point;
+
+/* Band selection mask; with both, outputs hold E_- first, then E_+. */
+enum { OMEGA_BAND_MINUS = 1, OMEGA_BAND_PLUS = 2, OMEGA_BAND_BOTH = 3 };
+
+/* Arithmetic of the Delta-dependent sweep.  OMEGA_FP64: everything in FP64.
+ * OMEGA_FP32_COMP: the Delta-dependent part of each term in FP32 with
+ * compensated accumulation; band energies, the Delta-independent part, all
+ * cross-block sums and the argmin stay FP64. */
+enum { OMEGA_FP64 = 0, OMEGA_FP32_COMP = 1 };
+
+enum {
+    OMEGA_OK = 0,
+    OMEGA_E_INVAL = -1,       /* an argument is out of range or NULL        */
+    OMEGA_E_WORKSPACE = -2,   /* ws_bytes smaller than required             */
+    OMEGA_E_HIP = -3,         /* a HIP runtime call or launch failed        */
+    OMEGA_E_UNSUPPORTED = -4  /* valid request this build does not provide  */
+};
+
+/* Bytes of device workspace that omega_grid / omega_argmin (grad = 0) or
+ * omega_grad (grad = 1, n_delta and n_q ignored) need for these sizes.
+ * Returns 0 if the arguments are invalid. */
+size_t omega_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
+                             int n_q, int bands, int precision, int grad);
+
+/* Omega grid, Eq. (5), for every point, selected band, Q and Delta
+ * (Algorithm 1's two loops, all at once).
+ *   pts        host array [n_pts]
+ *   delta_dev  device [n_delta] Delta values (any real; Delta >= 0 physical)
+ *   q_dev      device [n_q][2] pair momenta Q = (qx, qy), any real values
+ *   omega_dev  device output [n_pts][nb][n_q][n_delta], Delta fastest,
+ *              nb = number of bands in `bands`; total Omega (not per site). */
+int omega_grid(const omega_model *model, const omega_point *pts, int n_pts,
+               const double *delta_dev, int n_delta, const double *q_dev,
+               int n_q, int bands, int precision, void *ws_dev,
+               size_t ws_bytes, double *omega_dev, void *stream);
+
+/* Omega grid plus the searches of Algorithm 1 (per-Q Delta minimum, then the
+ * global minimum), with a tie rule: among grid points with
+ * Omega <= Omega_min + tie_rel*|Omega_min| the lexicographically smallest
+ * (iDelta, iq) is chosen; per row the smallest iDelta.  Comparisons in FP64;
+ * NaN is never chosen; an all-NaN set gives index -1 and Omega NaN.
+ *   tie_rel      >= 0 (1e-11 recommended: grid points of one physical state,
+ *                e.g. the Delta = 0 row over lattice Q, agree only to rounding)
+ *   idx_dev      device output [n_pts][nb][2] = (iDelta, iq)
+ *   omin_dev     device output [n_pts][nb], Omega at the chosen point
+ *   row_idx_dev  device output [n_pts][nb][n_q] or NULL
+ *   omega_dev    device output as in omega_grid, or NULL (grid then lives in
+ *                the workspace). */
+int omega_argmin(const omega_model *model, const omega_point *pts, int n_pts,
+                 const double *delta_dev, int n_delta, const double *q_dev,
+                 int n_q, int bands, int precision, double tie_rel,
+                 void *ws_dev, size_t ws_bytes, int32_t *idx_dev,
+                 double *omin_dev, int32_t *row_idx_dev, double *omega_dev,
+                 void *stream);
+
+/* Omega and its first derivatives at one (Delta, Q) per point and band,
+ * obtained by differentiating Eqs. (4)-(5) by hand (dOmega/dE = Fermi
+ * function; at R = sqrt(s^2 + Delta^2 eta^2) = 0 and at band-touching points
+ * the non-smooth factors are given the symmetric value 0).  FP64 only.
+ *   delta_dev  device [n_pts][nb]; q_dev device [n_pts][nb][2]
+ *   outputs    device omega_dev, dDelta_dev, dmu_dev [n_pts][nb];
+ *              dq_dev [n_pts][nb][2] (d/dqx, d/dqy).  dOmega/dmu = -n_eps. */
+int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
+               const double *delta_dev, const double *q_dev, int bands,
+               void *ws_dev, size_t ws_bytes, double *omega_dev,
+               double *dDelta_dev, double *dq_dev, double *dmu_dev,
+               void *stream);
+
+/* Static description of an OMEGA_* code (never NULL). */
+const char *omega_strerror(int code);
+
+/* Library interface version, currently 1. */
+int omega_version(void);
+
+/* Timing hook for benchmarks (the paper times the computation part only,
+ * Sec. 3.3).  While set, every Delta-sweep kernel the process enqueues is
+ * bracketed by hipEventRecord(start_event) and hipEventRecord(stop_event) on
+ * the call's stream; start_event and stop_event are hipEvent_t handles owned
+ * by the caller.  Passing NULL for both clears the hook.  Process-wide, not
+ * thread-safe: set it only while a single thread drives the library.
+ * Returns OMEGA_E_INVAL if exactly one of the two is NULL. */
+int omega_set_sweep_events(void *start_event, void *stop_event);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OMEGA_H */

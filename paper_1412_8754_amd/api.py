@@ -1,0 +1,126 @@
+"""Torch-facing binding of libomega: argument marshalling only.
+
+Every function allocates its outputs (and, unless given, the workspace) as
+torch CUDA tensors, passes raw device pointers and the current HIP stream to
+the C interface, and returns without synchronising.  All arithmetic runs in
+the library's kernels; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _abi
+from ._abi import (OMEGA_BAND_BOTH, OMEGA_FP32_COMP, OMEGA_FP64, OmegaError,  # noqa: F401
+                   make_model, make_points, n_bands)
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_f64(x, device, shape=None) -> torch.Tensor:
+    t = torch.as_tensor(x, dtype=torch.float64, device=device)
+    if shape is not None:
+        t = t.reshape(shape)
+    return t.contiguous()
+
+
+def _check(rc: int, what: str):
+    if rc != _abi.OMEGA_OK:
+        raise OmegaError(rc, what)
+
+
+def workspace_bytes(pts, n_delta: int, n_q: int, bands: int = OMEGA_BAND_BOTH,
+                    precision: int = OMEGA_FP64, grad: bool = False) -> int:
+    L = _abi.load()
+    p = make_points(pts)
+    n = L.omega_workspace_bytes(p, len(pts), int(n_delta), int(n_q), int(bands),
+                                int(precision), int(bool(grad)))
+    if n == 0:
+        raise OmegaError(_abi.OMEGA_E_INVAL, "omega_workspace_bytes")
+    return int(n)
+
+
+def _workspace(nbytes: int, device, workspace):
+    if workspace is not None:
+        if workspace.numel() * workspace.element_size() < nbytes:
+            raise OmegaError(_abi.OMEGA_E_WORKSPACE, "workspace")
+        return workspace
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def grid(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = OMEGA_FP64,
+         device="cuda", out=None, workspace=None, stream=None) -> torch.Tensor:
+    """Omega grid [n_pts][n_bands][n_q][n_delta] (Eq. (5), Algorithm 1 loops)."""
+    L = _abi.load()
+    d = _dev_f64(delta, device, (-1,))
+    qq = _dev_f64(q, device, (-1, 2))
+    nb = n_bands(bands)
+    shape = (len(pts), nb, qq.shape[0], d.numel())
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=device)
+    assert out.is_contiguous() and tuple(out.shape) == shape and out.dtype == torch.float64
+    ws = _workspace(workspace_bytes(pts, d.numel(), qq.shape[0], bands, precision), device,
+                    workspace)
+    m = make_model(model)
+    p = make_points(pts)
+    rc = L.omega_grid(ctypes.byref(m), p, len(pts), d.data_ptr(), d.numel(), qq.data_ptr(),
+                      qq.shape[0], int(bands), int(precision), ws.data_ptr(),
+                      ws.numel() * ws.element_size(), out.data_ptr(), _stream_ptr(stream))
+    _check(rc, "omega_grid")
+    return out
+
+
+def argmin(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = OMEGA_FP64,
+           tie_rel: float = 1e-11, keep_grid: bool = True, rows: bool = True, device="cuda",
+           workspace=None, stream=None):
+    """Grid plus the searches of Algorithm 1.
+
+    Returns (idx [n_pts][nb][2] int32 (iDelta, iq), omin [n_pts][nb],
+    row_idx [n_pts][nb][n_q] or None, omega grid or None)."""
+    L = _abi.load()
+    d = _dev_f64(delta, device, (-1,))
+    qq = _dev_f64(q, device, (-1, 2))
+    nb = n_bands(bands)
+    n_pts, n_q, n_d = len(pts), qq.shape[0], d.numel()
+    idx = torch.empty((n_pts, nb, 2), dtype=torch.int32, device=device)
+    omin = torch.empty((n_pts, nb), dtype=torch.float64, device=device)
+    row_idx = torch.empty((n_pts, nb, n_q), dtype=torch.int32, device=device) if rows else None
+    om = torch.empty((n_pts, nb, n_q, n_d), dtype=torch.float64, device=device) if keep_grid else None
+    ws = _workspace(workspace_bytes(pts, n_d, n_q, bands, precision), device, workspace)
+    m = make_model(model)
+    p = make_points(pts)
+    rc = L.omega_argmin(ctypes.byref(m), p, n_pts, d.data_ptr(), n_d, qq.data_ptr(), n_q,
+                        int(bands), int(precision), float(tie_rel), ws.data_ptr(),
+                        ws.numel() * ws.element_size(), idx.data_ptr(), omin.data_ptr(),
+                        row_idx.data_ptr() if row_idx is not None else None,
+                        om.data_ptr() if om is not None else None, _stream_ptr(stream))
+    _check(rc, "omega_argmin")
+    return idx, omin, row_idx, om
+
+
+def grad(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, device="cuda", workspace=None,
+         stream=None):
+    """Omega and dOmega/dDelta, dOmega/dq (2), dOmega/dmu at one (Delta, Q) per point and
+    band.  delta: [n_pts][nb]; q: [n_pts][nb][2].  Returns four tensors
+    ([n_pts][nb], [n_pts][nb], [n_pts][nb][2], [n_pts][nb])."""
+    L = _abi.load()
+    nb = n_bands(bands)
+    n = len(pts)
+    d = _dev_f64(delta, device, (n, nb))
+    qq = _dev_f64(q, device, (n, nb, 2))
+    om = torch.empty((n, nb), dtype=torch.float64, device=device)
+    gd = torch.empty((n, nb), dtype=torch.float64, device=device)
+    gq = torch.empty((n, nb, 2), dtype=torch.float64, device=device)
+    gm = torch.empty((n, nb), dtype=torch.float64, device=device)
+    ws = _workspace(workspace_bytes(pts, 1, 1, bands, OMEGA_FP64, grad=True), device, workspace)
+    m = make_model(model)
+    p = make_points(pts)
+    rc = L.omega_grad(ctypes.byref(m), p, n, d.data_ptr(), qq.data_ptr(), int(bands),
+                      ws.data_ptr(), ws.numel() * ws.element_size(), om.data_ptr(),
+                      gd.data_ptr(), gq.data_ptr(), gm.data_ptr(), _stream_ptr(stream))
+    _check(rc, "omega_grad")
+    return om, gd, gq, gm

@@ -1,0 +1,108 @@
+// Internal declarations shared by the kernels and the C entry points of
+// libomega.  Not installed; the public interface is include/omega.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace omega {
+
+// Two-band energies of App. A, Eqs. (A.1)-(A.4), regrouped as
+//   (T11 + T22)/2 = tA (cx + cy) + tB cx cy,  tA = -(t1 + t2), tB = -4 t3
+//   (T11 - T22)/2 = tD (cx - cy),             tD = -(t1 - t2)
+//   T12           = tC sx sy,                 tC = -4 t4
+// and E_eps = (T11 + T22)/2 + eps sqrt(((T11 - T22)/2)^2 + T12^2).
+struct Hop {
+    double tA, tB, tD, tC;
+};
+
+// Skip threshold of the thermal term: where |E|/T exceeds this,
+// T ln(1 + exp(-|E|/T)) < T * 2.4e-16 and the term is dropped.
+constexpr double kCutFp64 = 36.0;
+// Same for the FP32 sweep: exp(-17) = 4.1e-8 is below the FP32 resolution of
+// the terms it would be added to.
+constexpr float kCutFp32 = 17.0f;
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
+
+// Arguments of one Delta-sweep launch (one point, all bands and Q).
+struct SweepArgs {
+    Hop hop;
+    double eps[2];       // band sign per output slot (-1: E_-, +1: E_+)
+    double mu_up;        // mu + h  (spin up: E - mu - h)
+    double mu_dn;        // mu - h  (spin down: E - mu + h)
+    double T, invT, cutT;
+    float Tf, invTf, cutTf;
+    int Lx, Ly;
+    int TY;              // tiles along y (ceil(Ly / 8))
+    int n_tiles;         // ceil(Lx/8) * ceil(Ly/8)
+    int tiles_per_wg;    // tiles per workgroup (multiple of 4)
+    int n_chunks;        // ceil(n_tiles / tiles_per_wg)
+    int n_q;
+    int n_delta_pad;     // n_delta rounded up to the Delta tile
+    const double *d2;    // [n_delta_pad] Delta^2 (padding repeats the last)
+    const double *q;     // [n_q][2]
+    const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
+    double *part;        // [nb*n_q][n_chunks][n_delta_pad] sums of Delta parts
+    double *base_part;   // [nb*n_q][n_chunks] sums of Delta-independent parts
+};
+
+// Arguments of the per-row reduction / epilogue / row search (one point).
+struct RowArgs {
+    const double *part;
+    const double *base_part;
+    const double *delta;   // [n_delta]
+    const double *q;       // [n_q][2]
+    double Vs[2];          // V per output slot
+    double n_k;            // Lx * Ly
+    double tie_rel;
+    int n_chunks, n_delta, n_delta_pad, n_q;
+    double *omega;         // [nb][n_q][n_delta] of this point
+    int32_t *row_idx;      // [nb][n_q] of this point, or nullptr
+};
+
+struct ArgminArgs {
+    const double *omega;   // [n_set][n_q][n_delta]
+    int n_q, n_delta;
+    double tie_rel;
+    int32_t *idx;          // [n_set][2]
+    double *omin;          // [n_set]
+};
+
+// Gradient sweep: one point, one (Delta, Q) per band slot.
+struct GradArgs {
+    Hop hop;
+    double eps[2];
+    double mu_up, mu_dn;
+    double T, invT;
+    int Lx, Ly, TY, n_tiles, tiles_per_wg, n_chunks;
+    const double *delta;   // [nb] for this point
+    const double *q;       // [nb][2] for this point
+    const double *trig;
+    double *part;          // [nb][n_chunks][5]
+};
+
+struct GradFinishArgs {
+    const double *part;
+    const double *delta;
+    double Vs[2];
+    double n_k;
+    int n_chunks;
+    double *omega, *dDelta, *dq, *dmu;   // this point's outputs, [nb] ([nb][2])
+};
+
+hipError_t launch_prep(int Lx, int Ly, double *trig, const double *delta,
+                       int n_delta, int n_delta_pad, double *d2,
+                       hipStream_t s);
+hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int nbq,
+                            hipStream_t s);
+hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int nbq,
+                             hipStream_t s);
+hipError_t launch_rows(const RowArgs &a, int nbq, hipStream_t s);
+hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s);
+hipError_t launch_grad(const GradArgs &a, int nb, hipStream_t s);
+hipError_t launch_grad_finish(const GradFinishArgs &a, int nb, hipStream_t s);
+
+}  // namespace omega

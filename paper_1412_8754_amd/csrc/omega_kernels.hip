@@ -1,0 +1,737 @@
+// Device code of libomega: the Delta sweep of Eq. (4)-(5), the fixed-order
+// reductions, the searches of Algorithm 1 and the hand-derived gradient sweep.
+//
+// Work decomposition of the sweep (one point per launch):
+//   blockIdx.z  = (band slot, Q) pair
+//   blockIdx.y  = tile of TD consecutive Delta values (held in registers)
+//   blockIdx.x  = chunk of 8x8 momentum tiles (one tile per wavefront pass)
+// Every thread owns one momentum k at a time; it evaluates the band energies
+// for (k, Q) once and reuses them for its TD Delta values.  Per Delta only
+// the Delta-dependent remainder of the term is evaluated; the remainder is a
+// sum of non-negative pieces, so plain FP64 accumulation is well conditioned.
+// The Delta-independent piece carries the cancellation of Eq. (5) and is
+// summed once per (k, Q) with Neumaier compensation.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "omega_internal.h"
+
+namespace omega {
+
+// ------------------------------------------------------------------ math
+
+// Band energy of App. A, (A.4), from cos/sin of the two momentum components.
+__device__ __forceinline__ double band_energy(const Hop &t, double eps,
+                                              double cx, double sx, double cy,
+                                              double sy)
+{
+    double A = fma(t.tB * cx, cy, t.tA * (cx + cy));
+    double D = t.tD * (cx - cy);
+    double C = t.tC * sx * sy;
+    return fma(eps, sqrt(fma(D, D, C * C)), A);
+}
+
+// Neumaier (improved Kahan) accumulation step.
+__device__ __forceinline__ void neumaier(double &s, double &c, double x)
+{
+    double t = s + x;
+    double e = (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    c += e;
+    s = t;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int N>
+struct Log2 {
+    static constexpr int value = 1 + Log2<N / 2>::value;
+};
+template <>
+struct Log2<1> {
+    static constexpr int value = 0;
+};
+
+// Sum TD per-lane accumulators over the 64 lanes of a wavefront by recursive
+// halving: at each exchange a lane keeps one half of its values and receives
+// the partner's copy of that half.  Afterwards acc[0] of lane l holds the
+// wave-wide sum for Delta index (l >> (6 - log2 TD)) & (TD - 1).  The order
+// of additions is fixed, so the result is bitwise reproducible.
+template <int TD>
+__device__ __forceinline__ void wave_reduce_halving(double (&acc)[TD], int lane)
+{
+    constexpr int LOG = Log2<TD>::value;
+    static_assert(LOG <= 6, "Delta tile larger than a wavefront");
+#pragma unroll
+    for (int s = 0; s < LOG; ++s) {
+        const int off = 32 >> s;
+        const int half = TD >> (s + 1);
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int t = 0; t < half; ++t) {
+            double lo = acc[t], hi = acc[t + half];
+            double send = upper ? lo : hi;
+            double keep = upper ? hi : lo;
+            acc[t] = keep + __shfl_xor(send, off, 64);
+        }
+    }
+#pragma unroll
+    for (int off = 32 >> LOG; off >= 1; off >>= 1)
+        acc[0] += __shfl_xor(acc[0], off, 64);
+}
+
+// ------------------------------------------------------------------ prep
+
+// cos/sin of the lattice momenta 2 pi i / L and the squared Delta values.
+__global__ void prep_kernel(int Lx, int Ly, double *trig, const double *delta,
+                            int n_delta, int n_delta_pad, double *d2)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    double s, c;
+    if (t < Lx) {
+        sincospi(2.0 * t / Lx, &s, &c);
+        trig[t] = c;
+        trig[Lx + t] = s;
+    }
+    if (t < Ly) {
+        sincospi(2.0 * t / Ly, &s, &c);
+        trig[2 * Lx + t] = c;
+        trig[2 * Lx + Ly + t] = s;
+    }
+    if (t < n_delta_pad) {
+        double D = delta[t < n_delta ? t : n_delta - 1];
+        d2[t] = D * D;
+    }
+}
+
+hipError_t launch_prep(int Lx, int Ly, double *trig, const double *delta,
+                       int n_delta, int n_delta_pad, double *d2, hipStream_t s)
+{
+    int n = Lx > Ly ? Lx : Ly;
+    if (n_delta_pad > n)
+        n = n_delta_pad;
+    hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Lx,
+                       Ly, trig, delta, n_delta, n_delta_pad, d2);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ sweep
+
+// Per (k, Q) invariants of one band, shared by the sweep kernels.
+struct KQ {
+    double s2;     // ((a + b)/2)^2
+    double m;      // |(a - b)/2|
+    double eta2;   // (cos kx cos ky)^2
+    double base;   // Delta-independent part of the term
+};
+
+// a = E(k) - mu - h (k up), b = E(Q - k) - mu + h (-k+Q down); Eq. (4) reads
+// E^+- = d +- R with s = (a+b)/2, d = (a-b)/2, R = sqrt(s^2 + Delta^2 eta^2).
+// Using min(E,0) - T ln(1 + exp(-|E|/T)) for each branch and
+// {|d+R|, |d-R|} = {|R - |d||, R + |d|}, the term of Eq. (5) is
+//   2 min(d, 0) + E_{k down}                     (Delta-independent)
+//   - max(R - |d|, 0) - T ln[(1 + u1)(1 + u2)]   (Delta-dependent)
+// with u1 = exp(-|R - |d||/T), u2 = exp(-(R + |d|)/T).
+__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
+                                       double cqx, double sqx, double cqy,
+                                       double sqy, double cx, double sx,
+                                       double cy, double sy)
+{
+    double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
+    // cos/sin of (Q - k) by angle subtraction
+    double cpx = fma(cqx, cx, sqx * sx);
+    double spx = fma(sqx, cx, -(cqx * sx));
+    double cpy = fma(cqy, cy, sqy * sy);
+    double spy = fma(sqy, cy, -(cqy * sy));
+    double Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
+    double up = Ek - a.mu_up;
+    double dn = Eq - a.mu_dn;
+    double s = 0.5 * (up + dn);
+    double d = 0.5 * (up - dn);
+    double eta = cx * cy;
+    KQ r;
+    r.s2 = s * s;
+    r.m = fabs(d);
+    r.eta2 = eta * eta;
+    r.base = 2.0 * fmin(d, 0.0) + (Ek - a.mu_dn);
+    return r;
+}
+
+template <int TD>
+__global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
+{
+    const int chunk = blockIdx.x;
+    const int dtile = blockIdx.y;
+    const int bq = blockIdx.z;
+    const int slot = bq / a.n_q;
+    const int iq = bq - slot * a.n_q;
+    const double eps = slot ? a.eps[1] : a.eps[0];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+
+    double sqx, cqx, sqy, cqy;
+    sincos(a.q[2 * iq], &sqx, &cqx);
+    sincos(a.q[2 * iq + 1], &sqy, &cqy);
+
+    double d2[TD];
+#pragma unroll
+    for (int t = 0; t < TD; ++t)
+        d2[t] = a.d2[dtile * TD + t];
+
+    const double *cxt = a.trig;
+    const double *sxt = a.trig + a.Lx;
+    const double *cyt = a.trig + 2 * a.Lx;
+    const double *syt = cyt + a.Ly;
+
+    double acc[TD];
+#pragma unroll
+    for (int t = 0; t < TD; ++t)
+        acc[t] = 0.0;
+    double bs = 0.0, bc = 0.0;
+    const bool do_base = (dtile == 0);
+
+    const int li = lane >> 3, lj = lane & 7;
+    const int tile_begin = chunk * a.tiles_per_wg;
+    int tile_end = tile_begin + a.tiles_per_wg;
+    if (tile_end > a.n_tiles)
+        tile_end = a.n_tiles;
+
+    for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
+        const int ti = tile / a.TY;
+        const int tj = tile - ti * a.TY;
+        const int i = ti * kTileEdge + li;
+        const int j = tj * kTileEdge + lj;
+        if (i < a.Lx && j < a.Ly) {
+            KQ r = kq_setup(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i], cyt[j],
+                            syt[j]);
+            if (do_base)
+                neumaier(bs, bc, r.base);
+#pragma unroll
+            for (int t = 0; t < TD; ++t) {
+                double R = sqrt(fma(d2[t], r.eta2, r.s2));
+                double x = R - r.m;
+                acc[t] += fmax(x, 0.0);
+                double ax = fabs(x);
+                if (ax < a.cutT) {
+                    double u1 = exp(-ax * a.invT);
+                    double y = R + r.m;
+                    double u2 = (y < a.cutT) ? exp(-y * a.invT) : 0.0;
+                    acc[t] += a.T * log1p(u1 + u2 + u1 * u2);
+                }
+            }
+        }
+    }
+
+    __shared__ double red[4][64];
+    __shared__ double bred[4];
+    wave_reduce_halving<TD>(acc, lane);
+    red[wave][lane] = acc[0];
+    if (do_base) {
+        double bv = wave_sum(bs + bc);
+        if (lane == 0)
+            bred[wave] = bv;
+    }
+    __syncthreads();
+    constexpr int SHIFT = 6 - Log2<TD>::value;
+    if (threadIdx.x < TD) {
+        const int src = threadIdx.x << SHIFT;
+        double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+        a.part[((size_t)bq * a.n_chunks + chunk) * a.n_delta_pad +
+               dtile * TD + threadIdx.x] = v;
+    }
+    if (do_base && threadIdx.x == 0)
+        a.base_part[(size_t)bq * a.n_chunks + chunk] =
+            ((bred[0] + bred[1]) + bred[2]) + bred[3];
+}
+
+hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int nbq,
+                            hipStream_t s)
+{
+    dim3 grid(a.n_chunks, n_dtiles, nbq);
+    switch (td) {
+    case 16:
+        hipLaunchKernelGGL(sweep_f64_kernel<16>, grid, dim3(kBlock), 0, s, a);
+        break;
+    case 32:
+        hipLaunchKernelGGL(sweep_f64_kernel<32>, grid, dim3(kBlock), 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// FP32-compensated sweep.  The term is split as
+//   [2 min(d,0) + E_{k down} - max(|s| - |d|, 0)]                 FP64, once per (k, Q)
+//   - [max(R - |d|, 0) - max(|s| - |d|, 0) + T ln((1+u1)(1+u2))]   FP32, per Delta
+// With A0 = |s| - |d| and delta = R - |s| = Delta^2 eta^2 / (R + |s|) (no
+// cancellation), the FP32 difference is delta when A0 >= 0 and
+// max(A0 + delta, 0) otherwise; it is small where the term is large, so its
+// FP32 rounding is small against Omega.  Each thread sums at most
+// tiles_per_wg/4 momenta per Delta in FP32 before the FP64 reduction tree.
+struct KQf {
+    float s2, as, m, eta2, A0;
+    double base;
+};
+
+__device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
+                                            double cqx, double sqx, double cqy,
+                                            double sqy, double cx, double sx,
+                                            double cy, double sy)
+{
+    double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
+    double cpx = fma(cqx, cx, sqx * sx);
+    double spx = fma(sqx, cx, -(cqx * sx));
+    double cpy = fma(cqy, cy, sqy * sy);
+    double spy = fma(sqy, cy, -(cqy * sy));
+    double Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
+    double up = Ek - a.mu_up;
+    double dn = Eq - a.mu_dn;
+    double s = 0.5 * (up + dn);
+    double d = 0.5 * (up - dn);
+    double eta = cx * cy;
+    double as = fabs(s), m = fabs(d);
+    double A0 = as - m;
+    KQf r;
+    r.s2 = (float)(s * s);
+    r.as = (float)as;
+    r.m = (float)m;
+    r.eta2 = (float)(eta * eta);
+    r.A0 = (float)A0;
+    r.base = (2.0 * fmin(d, 0.0) + (Ek - a.mu_dn)) - fmax(A0, 0.0);
+    return r;
+}
+
+template <int TD>
+__global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
+{
+    const int chunk = blockIdx.x;
+    const int dtile = blockIdx.y;
+    const int bq = blockIdx.z;
+    const int slot = bq / a.n_q;
+    const int iq = bq - slot * a.n_q;
+    const double eps = slot ? a.eps[1] : a.eps[0];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+
+    double sqx, cqx, sqy, cqy;
+    sincos(a.q[2 * iq], &sqx, &cqx);
+    sincos(a.q[2 * iq + 1], &sqy, &cqy);
+
+    float d2[TD];
+#pragma unroll
+    for (int t = 0; t < TD; ++t)
+        d2[t] = (float)a.d2[dtile * TD + t];
+
+    const double *cxt = a.trig;
+    const double *sxt = a.trig + a.Lx;
+    const double *cyt = a.trig + 2 * a.Lx;
+    const double *syt = cyt + a.Ly;
+
+    float acc[TD];
+#pragma unroll
+    for (int t = 0; t < TD; ++t)
+        acc[t] = 0.0f;
+    double bs = 0.0, bc = 0.0;
+    const bool do_base = (dtile == 0);
+    const float Tf = a.Tf, invTf = a.invTf, cutTf = a.cutTf;
+
+    const int li = lane >> 3, lj = lane & 7;
+    const int tile_begin = chunk * a.tiles_per_wg;
+    int tile_end = tile_begin + a.tiles_per_wg;
+    if (tile_end > a.n_tiles)
+        tile_end = a.n_tiles;
+
+    for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
+        const int ti = tile / a.TY;
+        const int tj = tile - ti * a.TY;
+        const int i = ti * kTileEdge + li;
+        const int j = tj * kTileEdge + lj;
+        if (i < a.Lx && j < a.Ly) {
+            KQf r = kq_setup_f32(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i],
+                                 cyt[j], syt[j]);
+            if (do_base)
+                neumaier(bs, bc, r.base);
+            const bool pos = r.A0 >= 0.0f;
+#pragma unroll
+            for (int t = 0; t < TD; ++t) {
+                float g2 = d2[t] * r.eta2;
+                float R = __builtin_amdgcn_sqrtf(r.s2 + g2);
+                float del = g2 * __builtin_amdgcn_rcpf(R + r.as);
+                float x = r.A0 + del;
+                acc[t] += pos ? del : fmaxf(x, 0.0f);
+                float ax = fabsf(x);
+                if (ax < cutTf) {
+                    float u1 = __expf(-ax * invTf);
+                    float y = R + r.m;
+                    float u2 = (y < cutTf) ? __expf(-y * invTf) : 0.0f;
+                    acc[t] += Tf * __logf(1.0f + (u1 + u2 + u1 * u2));
+                }
+            }
+        }
+    }
+
+    double accd[TD];
+#pragma unroll
+    for (int t = 0; t < TD; ++t)
+        accd[t] = (double)acc[t];
+    __shared__ double red[4][64];
+    __shared__ double bred[4];
+    wave_reduce_halving<TD>(accd, lane);
+    red[wave][lane] = accd[0];
+    if (do_base) {
+        double bv = wave_sum(bs + bc);
+        if (lane == 0)
+            bred[wave] = bv;
+    }
+    __syncthreads();
+    constexpr int SHIFT = 6 - Log2<TD>::value;
+    if (threadIdx.x < TD) {
+        const int src = threadIdx.x << SHIFT;
+        double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+        a.part[((size_t)bq * a.n_chunks + chunk) * a.n_delta_pad +
+               dtile * TD + threadIdx.x] = v;
+    }
+    if (do_base && threadIdx.x == 0)
+        a.base_part[(size_t)bq * a.n_chunks + chunk] =
+            ((bred[0] + bred[1]) + bred[2]) + bred[3];
+}
+
+hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int nbq,
+                             hipStream_t s)
+{
+    dim3 grid(a.n_chunks, n_dtiles, nbq);
+    switch (td) {
+    case 16:
+        hipLaunchKernelGGL(sweep_f32c_kernel<16>, grid, dim3(kBlock), 0, s, a);
+        break;
+    case 32:
+        hipLaunchKernelGGL(sweep_f32c_kernel<32>, grid, dim3(kBlock), 0, s, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ rows
+
+__device__ __forceinline__ double nan_min(double x, double y)
+{
+    if (x != x)
+        return y;
+    if (y != y)
+        return x;
+    return y < x ? y : x;
+}
+
+// Block-wide min over 256 threads (NaN ignored unless all are NaN).
+__device__ double block_nan_min(double v, double *sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = nan_min(v, __shfl_xor(v, off, 64));
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        sh[wave] = v;
+    __syncthreads();
+    return nan_min(nan_min(sh[0], sh[1]), nan_min(sh[2], sh[3]));
+}
+
+__device__ int block_int_min(int v, int *sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        int o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        sh[wave] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int w = 1; w < 4; ++w)
+        r = sh[w] < r ? sh[w] : r;
+    return r;
+}
+
+// tie threshold, rounded exactly as written (no fused multiply-add)
+__device__ __forceinline__ double tie_threshold(double best, double tie_rel)
+{
+    return __dadd_rn(best, __dmul_rn(tie_rel, fabs(best)));
+}
+
+// One workgroup per (band slot, Q) row: fixed-order chunk sums, the
+// epilogue of Eq. (5) (+ N (-2 Delta^2 / V)), and the row search of
+// Algorithm 1 ("find and save Delta for this q").
+__global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
+{
+    const int bq = blockIdx.x;
+    const int slot = bq / r.n_q;
+    const int iq = bq - slot * r.n_q;
+    __shared__ double sh_base;
+    __shared__ double shd[4];
+    __shared__ int shi[4];
+    if (threadIdx.x == 0) {
+        double s = 0.0, c = 0.0;
+        const double *bp = r.base_part + (size_t)bq * r.n_chunks;
+        for (int ch = 0; ch < r.n_chunks; ++ch)
+            neumaier(s, c, bp[ch]);
+        sh_base = s + c;
+    }
+    __syncthreads();
+    const double base = sh_base;
+    // 0 * q is 0 for finite q and NaN for NaN q: a NaN momentum poisons the row
+    const double qpoison = 0.0 * r.q[2 * iq] + 0.0 * r.q[2 * iq + 1];
+    const double V = slot ? r.Vs[1] : r.Vs[0];
+    double *out = r.omega + (size_t)bq * r.n_delta;
+    const double *pp = r.part + (size_t)bq * r.n_chunks * r.n_delta_pad;
+
+    double best = __longlong_as_double(0x7ff8000000000000LL);
+    for (int id = threadIdx.x; id < r.n_delta; id += kBlock) {
+        double s = 0.0, c = 0.0;
+        for (int ch = 0; ch < r.n_chunks; ++ch)
+            neumaier(s, c, pp[(size_t)ch * r.n_delta_pad + id]);
+        const double D = r.delta[id];
+        const double om = (base - (s + c)) + r.n_k * (-2.0 * D * D / V) + qpoison;
+        out[id] = om;
+        best = nan_min(best, om);
+    }
+    if (!r.row_idx)
+        return;
+    best = block_nan_min(best, shd);
+    int pick = 0x7fffffff;
+    if (best == best) {
+        const double thr = tie_threshold(best, r.tie_rel);
+        for (int id = threadIdx.x; id < r.n_delta; id += kBlock) {
+            const double v = out[id];
+            if (v <= thr) {
+                pick = id;
+                break;
+            }
+        }
+    }
+    pick = block_int_min(pick, shi);
+    if (threadIdx.x == 0)
+        r.row_idx[bq] = pick == 0x7fffffff ? -1 : pick;
+}
+
+hipError_t launch_rows(const RowArgs &a, int nbq, hipStream_t s)
+{
+    hipLaunchKernelGGL(rows_kernel, dim3(nbq), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ argmin
+
+// One workgroup per (point, band) set: global search of Algorithm 1 with the
+// tie rule (lexicographically smallest (iDelta, iq) within the tie band).
+__global__ __launch_bounds__(kBlock) void argmin_kernel(const ArgminArgs a)
+{
+    const size_t set = blockIdx.x;
+    const int n = a.n_q * a.n_delta;
+    const double *g = a.omega + set * (size_t)n;
+    __shared__ double shd[4];
+    __shared__ int shi[4];
+    double best = __longlong_as_double(0x7ff8000000000000LL);
+    for (int t = threadIdx.x; t < n; t += kBlock)
+        best = nan_min(best, g[t]);
+    best = block_nan_min(best, shd);
+    int key = 0x7fffffff;
+    if (best == best) {
+        const double thr = tie_threshold(best, a.tie_rel);
+        for (int t = threadIdx.x; t < n; t += kBlock) {
+            const double v = g[t];
+            if (v <= thr) {
+                const int iq = t / a.n_delta;
+                const int id = t - iq * a.n_delta;
+                const int k = id * a.n_q + iq;
+                key = k < key ? k : key;
+            }
+        }
+    }
+    key = block_int_min(key, shi);
+    if (threadIdx.x == 0) {
+        if (key == 0x7fffffff) {
+            a.idx[2 * set] = -1;
+            a.idx[2 * set + 1] = -1;
+            a.omin[set] = __longlong_as_double(0x7ff8000000000000LL);
+        } else {
+            const int id = key / a.n_q;
+            const int iq = key - id * a.n_q;
+            a.idx[2 * set] = id;
+            a.idx[2 * set + 1] = iq;
+            a.omin[set] = g[(size_t)iq * a.n_delta + id];
+        }
+    }
+}
+
+hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s)
+{
+    hipLaunchKernelGGL(argmin_kernel, dim3(n_set), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ gradient
+
+// Gradient of (A.4) at p from cos/sin of its components; the non-smooth part
+// is 0 where the two bands touch.
+__device__ __forceinline__ void band_grad(const Hop &t, double eps, double cx,
+                                          double sx, double cy, double sy,
+                                          double &E, double &gx, double &gy)
+{
+    double A = fma(t.tB * cx, cy, t.tA * (cx + cy));
+    double D = t.tD * (cx - cy);
+    double C = t.tC * sx * sy;
+    double rho = sqrt(fma(D, D, C * C));
+    E = fma(eps, rho, A);
+    double Ax = -sx * fma(t.tB, cy, t.tA);
+    double Ay = -sy * fma(t.tB, cx, t.tA);
+    double Dx = -t.tD * sx, Dy = t.tD * sy;
+    double Cx = t.tC * cx * sy, Cy = t.tC * sx * cy;
+    if (rho > 0.0) {
+        double er = eps / rho;
+        gx = fma(er, fma(D, Dx, C * Cx), Ax);
+        gy = fma(er, fma(D, Dy, C * Cy), Ay);
+    } else {
+        gx = Ax;
+        gy = Ay;
+    }
+}
+
+__device__ __forceinline__ double fermi(double E, double T, double invT)
+{
+    if (T == 0.0)
+        return E < 0.0 ? 1.0 : (E > 0.0 ? 0.0 : 0.5);
+    if (E > 0.0) {
+        double e = exp(-E * invT);
+        return e / (1.0 + e);
+    }
+    return 1.0 / (1.0 + exp(E * invT));
+}
+
+__device__ __forceinline__ double softplus_neg(double E, double T, double invT)
+{
+    double lo = fmin(E, 0.0);
+    if (T == 0.0)
+        return lo;
+    return lo - T * log1p(exp(-fabs(E) * invT));
+}
+
+// Per k: the term of Eq. (5) and its derivatives with respect to Delta,
+// qx, qy and mu; 5 compensated sums per thread, fixed-order block reduction.
+__global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
+{
+    const int chunk = blockIdx.x;
+    const int slot = blockIdx.y;
+    const double eps = slot ? a.eps[1] : a.eps[0];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const double D = a.delta[slot];
+    double sqx, cqx, sqy, cqy;
+    sincos(a.q[2 * slot], &sqx, &cqx);
+    sincos(a.q[2 * slot + 1], &sqy, &cqy);
+    const double *cxt = a.trig, *sxt = a.trig + a.Lx;
+    const double *cyt = a.trig + 2 * a.Lx, *syt = cyt + a.Ly;
+    double s_[5] = {0, 0, 0, 0, 0}, c_[5] = {0, 0, 0, 0, 0};
+    const int li = lane >> 3, lj = lane & 7;
+    const int tile_begin = chunk * a.tiles_per_wg;
+    int tile_end = tile_begin + a.tiles_per_wg;
+    if (tile_end > a.n_tiles)
+        tile_end = a.n_tiles;
+    for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
+        const int ti = tile / a.TY;
+        const int tj = tile - ti * a.TY;
+        const int i = ti * kTileEdge + li;
+        const int j = tj * kTileEdge + lj;
+        if (i < a.Lx && j < a.Ly) {
+            const double cx = cxt[i], sx = sxt[i], cy = cyt[j], sy = syt[j];
+            double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
+            double cpx = fma(cqx, cx, sqx * sx), spx = fma(sqx, cx, -(cqx * sx));
+            double cpy = fma(cqy, cy, sqy * sy), spy = fma(sqy, cy, -(cqy * sy));
+            double Eq, bx, by;
+            band_grad(a.hop, eps, cpx, spx, cpy, spy, Eq, bx, by);
+            double up = Ek - a.mu_up, dn = Eq - a.mu_dn;
+            double s = 0.5 * (up + dn), d = 0.5 * (up - dn);
+            double eta = cx * cy;
+            double g = D * eta;
+            double R = sqrt(fma(s, s, g * g));
+            double Ep = d + R, Em = d - R;
+            double fp = fermi(Ep, a.T, a.invT), fm = fermi(Em, a.T, a.invT);
+            double sr = R > 0.0 ? s / R : 0.0;
+            double dr = R > 0.0 ? g * eta / R : 0.0;
+            double w = 0.5 * fp * (sr - 1.0) - 0.5 * fm * (sr + 1.0);
+            neumaier(s_[0], c_[0],
+                     (softplus_neg(Ep, a.T, a.invT) + softplus_neg(Em, a.T, a.invT)) +
+                         (Ek - a.mu_dn));
+            neumaier(s_[1], c_[1], dr * (fp - fm));
+            neumaier(s_[2], c_[2], bx * w);
+            neumaier(s_[3], c_[3], by * w);
+            neumaier(s_[4], c_[4], sr * (fm - fp));
+        }
+    }
+    __shared__ double red[5][4];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        double v = wave_sum(s_[c] + c_[c]);
+        if (lane == 0)
+            red[c][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int c = threadIdx.x;
+        a.part[((size_t)slot * a.n_chunks + chunk) * 5 + c] =
+            ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
+    }
+}
+
+hipError_t launch_grad(const GradArgs &a, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(grad_kernel, dim3(a.n_chunks, nb), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void grad_finish_kernel(const GradFinishArgs a)
+{
+    const int slot = blockIdx.x;
+    const int c = threadIdx.x;
+    if (c >= 5)
+        return;
+    double s = 0.0, e = 0.0;
+    for (int ch = 0; ch < a.n_chunks; ++ch)
+        neumaier(s, e, a.part[((size_t)slot * a.n_chunks + ch) * 5 + c]);
+    double v = s + e;
+    const double D = a.delta[slot];
+    const double V = slot ? a.Vs[1] : a.Vs[0];
+    switch (c) {
+    case 0:
+        a.omega[slot] = v + a.n_k * (-2.0 * D * D / V);
+        break;
+    case 1:
+        a.dDelta[slot] = v - 4.0 * a.n_k * D / V;
+        break;
+    case 2:
+        a.dq[2 * slot] = v;
+        break;
+    case 3:
+        a.dq[2 * slot + 1] = v;
+        break;
+    default:
+        a.dmu[slot] = v - a.n_k;
+        break;
+    }
+}
+
+hipError_t launch_grad_finish(const GradFinishArgs &a, int nb, hipStream_t s)
+{
+    hipLaunchKernelGGL(grad_finish_kernel, dim3(nb), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace omega

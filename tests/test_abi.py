@@ -1,0 +1,133 @@
+"""C interface checks that need no GPU: the library loads, exports every
+function the public header declares, and rejects invalid calls on the host
+before anything is enqueued."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1412_8754_amd import _abi
+from paper_1412_8754_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "omega.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(omega_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    assert set(header_functions()) == set(_abi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.load()
+    for name in header_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_version():
+    assert _abi.strerror(_abi.OMEGA_OK) == "success"
+    assert _abi.strerror(_abi.OMEGA_E_WORKSPACE) == "workspace too small"
+    assert _abi.strerror(12345) == "unknown error code"
+    assert _abi.load().omega_version() == 1
+
+
+def _ws(pts, nd=8, nq=3, bands=3, prec=0, grad=0):
+    return _abi.load().omega_workspace_bytes(_abi.make_points(pts), len(pts), nd, nq, bands,
+                                             prec, grad)
+
+
+def test_workspace_bytes_sizes():
+    small = _ws([(0.0, 0.01, 16, 16)])
+    big = _ws([(0.0, 0.01, 256, 256)])
+    assert 0 < small < big
+    # largest point dominates the per-point scratch; the grid part grows with n_pts
+    two = _ws([(0.0, 0.01, 16, 16), (0.0, 0.01, 256, 256)])
+    assert two > big
+    assert _ws([(0.0, 0.01, 64, 64)], grad=1) > 0
+
+
+@pytest.mark.parametrize("pt", [(0.0, -1e-3, 16, 16), (float("nan"), 0.01, 16, 16),
+                                (0.0, float("inf"), 16, 16), (0.0, 1e-310, 16, 16),
+                                (0.0, 0.01, 1, 16), (0.0, 0.01, 16, 20000),
+                                (0.0, 0.01, 16384, 16384)])
+def test_workspace_rejects_bad_points(pt):
+    assert _ws([pt]) == 0
+
+
+def test_workspace_rejects_bad_sizes():
+    pts = [(0.0, 0.01, 16, 16)]
+    assert _ws(pts, nd=0) == 0
+    assert _ws(pts, nq=0) == 0
+    assert _ws(pts, bands=0) == 0
+    assert _ws(pts, bands=4) == 0
+    assert _ws(pts, prec=2) == 0
+    assert _abi.load().omega_workspace_bytes(None, 1, 8, 3, 3, 0, 0) == 0
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
+
+
+def _grid(model=None, pts=None, n_pts=None, delta=FAKE, nd=8, q=FAKE, nq=3, bands=3, prec=0,
+          ws=FAKE, ws_bytes=1 << 40, out=FAKE):
+    L = _abi.load()
+    m = _abi.make_model(model or W.DEFAULT_MODEL)
+    pts = pts if pts is not None else [(0.0, 0.01, 16, 16)]
+    p = _abi.make_points(pts)
+    return L.omega_grid(ctypes.byref(m), p, len(pts) if n_pts is None else n_pts, delta, nd, q,
+                        nq, bands, prec, ws, ws_bytes, out, None)
+
+
+def test_grid_validation_errors():
+    E = _abi.OMEGA_E_INVAL
+    assert _grid(model=dict(W.DEFAULT_MODEL, V=(0.0, -1.0))) == E
+    assert _grid(model=dict(W.DEFAULT_MODEL, mu=float("nan"))) == E
+    assert _grid(pts=[(0.0, -0.1, 16, 16)]) == E
+    assert _grid(n_pts=0) == E
+    assert _grid(delta=None) == E
+    assert _grid(q=None) == E
+    assert _grid(out=None) == E
+    assert _grid(ws=None) == E
+    assert _grid(nd=0) == E
+    assert _grid(nq=-1) == E
+    assert _grid(bands=0) == E
+    assert _grid(prec=7) == E
+    assert _grid(ws_bytes=16) == _abi.OMEGA_E_WORKSPACE
+
+
+def test_argmin_and_grad_validation_errors():
+    L = _abi.load()
+    m = _abi.make_model(W.DEFAULT_MODEL)
+    pts = [(0.0, 0.01, 16, 16)]
+    p = _abi.make_points(pts)
+    big = 1 << 40
+    # negative / NaN tie tolerance
+    for tie in (-1.0, float("nan")):
+        assert L.omega_argmin(ctypes.byref(m), p, 1, FAKE, 8, FAKE, 3, 3, 0, tie, FAKE, big,
+                              FAKE, FAKE, None, None, None) == _abi.OMEGA_E_INVAL
+    # missing idx output
+    assert L.omega_argmin(ctypes.byref(m), p, 1, FAKE, 8, FAKE, 3, 3, 0, 1e-11, FAKE, big,
+                          None, FAKE, None, None, None) == _abi.OMEGA_E_INVAL
+    # no omega output: the grid needs workspace room too
+    need = L.omega_workspace_bytes(p, 1, 8, 3, 3, 0, 0)
+    assert L.omega_argmin(ctypes.byref(m), p, 1, FAKE, 8, FAKE, 3, 3, 0, 1e-11, FAKE, 64,
+                          FAKE, FAKE, None, None, None) == _abi.OMEGA_E_WORKSPACE
+    assert need > 64
+    # grad: bad band mask, missing outputs, small workspace
+    assert L.omega_grad(ctypes.byref(m), p, 1, FAKE, FAKE, 0, FAKE, big, FAKE, FAKE, FAKE,
+                        FAKE, None) == _abi.OMEGA_E_INVAL
+    assert L.omega_grad(ctypes.byref(m), p, 1, FAKE, FAKE, 3, FAKE, big, FAKE, None, FAKE,
+                        FAKE, None) == _abi.OMEGA_E_INVAL
+    assert L.omega_grad(ctypes.byref(m), p, 1, FAKE, FAKE, 3, FAKE, 8, FAKE, FAKE, FAKE,
+                        FAKE, None) == _abi.OMEGA_E_WORKSPACE
+
+
+def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(_abi, "_lib", None)
+    monkeypatch.setattr(_abi, "LIB_PATH", tmp_path / "missing.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        _abi.load()

@@ -1,0 +1,234 @@
+"""GPU parity: libomega (through its C interface) against the FP64 oracle.
+
+Tolerances: FP64 path |dOmega| <= 1e-12 |Omega| + 1e-13 N (N = Lx*Ly; the
+floor only matters where Omega passes through zero), FP32-compensated path
+1e-7 relative with the same kind of floor scaled by 1e5; argmin indices
+identical under the tie rule.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1412_8754_amd import OMEGA_FP32_COMP, OMEGA_FP64, api  # noqa: E402
+from paper_1412_8754_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+M = W.DEFAULT_MODEL
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def n_sites(pts):
+    return np.array([p[2] * p[3] for p in pts], dtype=np.float64)
+
+
+def assert_close(got, ref, pts, rel=1e-12, floor=1e-13):
+    N = n_sites(pts).reshape((-1,) + (1,) * (ref.ndim - 1))
+    err = np.abs(got - ref)
+    tol = rel * np.abs(ref) + floor * N
+    bad = err > tol
+    worst = np.max(err / (np.abs(ref) + 1e-300))
+    assert not bad.any(), f"{bad.sum()} mismatches, worst rel {worst:.3e}"
+    return worst
+
+
+def brute_argmin(g, tie):
+    """Tie rule of Algorithm 1's search, written out in numpy (test-side)."""
+    ok = ~np.isnan(g)
+    if not ok.any():
+        return (-1, -1)
+    best = np.min(g[ok])
+    thr = best + tie * abs(best)
+    cand = [(idl, iq) for iq in range(g.shape[0]) for idl in range(g.shape[1])
+            if ok[iq, idl] and g[iq, idl] <= thr]
+    return min(cand)
+
+
+def run_argmin(pts, delta, q, bands, precision=OMEGA_FP64):
+    say(f"case: pts={pts} n_delta={len(delta)} n_q={len(q)} bands={bands} prec={precision}")
+    idx, omin, rows, om = api.argmin(M, pts, delta, q, bands, precision)
+    torch.cuda.synchronize()
+    return idx.cpu().numpy(), omin.cpu().numpy(), rows.cpu().numpy(), om.cpu().numpy()
+
+
+# ------------------------------------------------------------------ FP64
+
+def test_small_workload_full_grid_and_argmin():
+    c = W.config("small")
+    idx, omin, rows, om = run_argmin(c["pts"], c["delta"], c["q"], c["bands"])
+    ref, ridx, romin, rrows = oracle.omega_argmin(M, c["pts"], c["delta"], c["q"], c["bands"])
+    worst = assert_close(om, ref, c["pts"])
+    say(f"small: worst rel {worst:.3e}")
+    np.testing.assert_array_equal(idx, ridx)
+    np.testing.assert_array_equal(rows, rrows)
+    np.testing.assert_array_equal(omin, om[0, [0, 1], ridx[0, :, 1], ridx[0, :, 0]][None])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_ragged_cases(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n_pts = [1, 2, 3, 1, 2, 1][seed]
+    pts = []
+    for p in range(n_pts):
+        Lx, Ly = (int(rng.integers(2, 41)), int(rng.integers(2, 41)))
+        T = [0.0, 0.002, 0.03, 0.2][int(rng.integers(0, 4))]
+        pts.append((float(rng.uniform(-0.3, 0.3)), T, Lx, Ly))
+    nd = [37, 5, 64, 1, 33, 100][seed]
+    delta = np.sort(rng.uniform(0.0, 0.6, nd))
+    delta[0] = 0.0
+    nq = [3, 1, 4, 2, 5, 2][seed]
+    q = rng.uniform(-0.7, 0.7, size=(nq, 2))
+    if seed % 2 == 0:
+        q[0] = 0.0
+    bands = [3, 1, 2, 3, 3, 1][seed]
+    idx, omin, rows, om = run_argmin(pts, delta, q, bands)
+    ref, ridx, romin, rrows = oracle.omega_argmin(M, pts, delta, q, bands)
+    worst = assert_close(om, ref, pts)
+    say(f"seed {seed}: worst rel {worst:.3e}")
+    # indices: identical unless the oracle itself has a near-tie at the rule's edge
+    for p in range(len(pts)):
+        for b in range(idx.shape[1]):
+            assert tuple(idx[p, b]) == brute_argmin(om[p, b], 1e-11)
+            if tuple(idx[p, b]) != tuple(ridx[p, b]):
+                g = ref[p, b]
+                best = np.nanmin(g)
+                v = g[idx[p, b, 1], idx[p, b, 0]]
+                assert abs(v - (best + 1e-11 * abs(best))) <= 1e-12 * abs(best)
+    np.testing.assert_array_equal(rows, rrows)
+
+
+def test_deterministic_bitwise():
+    c = W.config("small")
+    a = run_argmin(c["pts"], c["delta"], c["q"], c["bands"])[3]
+    b = run_argmin(c["pts"], c["delta"], c["q"], c["bands"])[3]
+    assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+
+
+def test_edge_cases_min_lattice_single_delta_zero_T():
+    pts = [(0.1, 0.0, 2, 2), (0.0, 0.0, 2, 3)]
+    delta = np.array([0.3])
+    q = np.array([[0.0, 0.0]])
+    idx, omin, rows, om = run_argmin(pts, delta, q, 3)
+    ref = oracle.omega_grid(M, pts, delta, q, 3)
+    assert_close(om, ref, pts)
+    assert (idx == 0).all() and (rows == 0).all()
+
+
+def test_nan_inputs_propagate_and_all_nan_gives_minus_one():
+    pts = [(0.0, 0.01, 12, 12)]
+    delta = np.array([np.nan, 0.1, np.nan])
+    q = np.array([[0.0, 0.0], [np.nan, 0.0]])
+    idx, omin, rows, om = run_argmin(pts, delta, q, 3)
+    assert np.isnan(om[:, :, :, 0]).all() and np.isnan(om[:, :, :, 2]).all()
+    assert np.isnan(om[:, :, 1, :]).all()
+    assert np.isfinite(om[:, :, 0, 1]).all()
+    assert (idx[0, :, 0] == 1).all() and (idx[0, :, 1] == 0).all()
+    assert list(rows[0, 0]) == [1, -1]
+    idx, omin, rows, om = run_argmin(pts, np.array([np.nan, np.nan]), q[:1], 2)
+    assert tuple(idx[0, 0]) == (-1, -1) and np.isnan(omin[0, 0]) and rows[0, 0, 0] == -1
+
+
+def test_largest_lattice_edge():
+    # Lx at the 16384 limit (Ly small so the oracle stays quick)
+    pts = [(0.05, 0.003, 16384, 6)]
+    delta = np.array([0.0, 0.2, 0.45])
+    q = np.array([[0.0, 0.0], [2 * np.pi * 7 / 16384, 0.0]])
+    idx, omin, rows, om = run_argmin(pts, delta, q, 3)
+    ref = oracle.omega_grid(M, pts, delta, q, 3)
+    assert_close(om, ref, pts)
+
+
+def test_paper_scale_sampled_against_oracle():
+    """L = 1024, 256 Delta x 64 q x 2 bands, the launch the benchmark times;
+    the oracle recomputes sampled entries, the chosen minima and their
+    neighbourhoods."""
+    c = W.config("paper")
+    pts, delta, q = c["pts"], c["delta"], c["q"]
+    idx, omin, rows, om = run_argmin(pts, delta, q, c["bands"])
+    assert np.isfinite(om).all()
+    rng = np.random.default_rng(4)
+    checks = []  # (band, iq, [iDelta...])
+    for b in range(2):
+        iq0 = int(rng.integers(0, len(q)))
+        checks.append((b, iq0, sorted(set(rng.integers(0, len(delta), 4).tolist()))))
+        d0, q0 = idx[0, b]
+        assert (d0, q0) == brute_argmin(om[0, b], 1e-11)
+        for qi in {max(q0 - 1, 0), q0, min(q0 + 1, len(q) - 1)}:
+            checks.append((b, qi, sorted({max(d0 - 1, 0), d0, min(d0 + 1, len(delta) - 1)})))
+    oracle.set_threads(os.cpu_count() or 1)
+    worst = 0.0
+    for b, qi, dl in checks:
+        ref = oracle.omega_grid(M, pts, delta[dl], q[qi:qi + 1], 1 << b)[0, 0, 0]
+        got = om[0, b, qi, dl]
+        worst = max(worst, assert_close(got[None], ref[None], pts))
+    say(f"paper-scale sampled worst rel {worst:.3e}")
+    # the chosen point is no worse than its oracle-evaluated neighbours
+    for b in range(2):
+        d0, q0 = idx[0, b]
+        qs = sorted({max(q0 - 1, 0), q0, min(q0 + 1, len(q) - 1)})
+        ds = sorted({max(d0 - 1, 0), d0, min(d0 + 1, len(delta) - 1)})
+        ref = oracle.omega_grid(M, pts, delta[ds], q[qs], 1 << b)[0, 0]
+        centre = ref[qs.index(q0), ds.index(d0)]
+        assert centre <= ref.min() + 1e-11 * abs(ref.min())
+
+
+# ------------------------------------------------------------------ FP32-comp
+
+def test_fp32_compensated_small_workload():
+    c = W.config("small")
+    idx, omin, rows, om = run_argmin(c["pts"], c["delta"], c["q"], c["bands"], OMEGA_FP32_COMP)
+    ref, ridx, _, rrows = oracle.omega_argmin(M, c["pts"], c["delta"], c["q"], c["bands"])
+    worst = assert_close(om, ref, c["pts"], rel=1e-7, floor=1e-8)
+    say(f"fp32c small: worst rel {worst:.3e}")
+    np.testing.assert_array_equal(idx, ridx)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_fp32_compensated_random(seed):
+    rng = np.random.default_rng(2000 + seed)
+    pts = [(float(rng.uniform(-0.3, 0.3)), [0.0, 0.004, 0.05][seed], int(rng.integers(5, 50)),
+            int(rng.integers(5, 50)))]
+    delta = np.linspace(0, 0.6, [40, 7, 65][seed])
+    q = rng.uniform(-0.5, 0.5, size=(3, 2))
+    idx, omin, rows, om = run_argmin(pts, delta, q, 3, OMEGA_FP32_COMP)
+    ref = oracle.omega_grid(M, pts, delta, q, 3)
+    worst = assert_close(om, ref, pts, rel=1e-7, floor=1e-8)
+    say(f"fp32c seed {seed}: worst rel {worst:.3e}")
+
+
+# ------------------------------------------------------------------ gradient
+
+@pytest.mark.parametrize("seed", range(3))
+def test_gradient_against_oracle(seed):
+    rng = np.random.default_rng(3000 + seed)
+    n = 5
+    pts = [(float(rng.uniform(-0.2, 0.2)), [0.0, 0.01, 0.05, 0.002, 0.1][i],
+            int(rng.integers(4, 40)), int(rng.integers(4, 40))) for i in range(n)]
+    delta = rng.uniform(0.0, 0.6, size=(n, 2))
+    delta[0] = 0.0
+    q = rng.uniform(-0.5, 0.5, size=(n, 2, 2))
+    say(f"grad case seed {seed}")
+    om, gd, gq, gm = (t.cpu().numpy() for t in api.grad(M, pts, delta, q, 3))
+    torch.cuda.synchronize()
+    for b in range(2):
+        rom, rgd, rgq, rgm = oracle.omega_grad(M, pts, delta[:, b], q[:, b], b)
+        N = n_sites(pts)
+        np.testing.assert_allclose(om[:, b], rom, rtol=1e-12, atol=0)
+        for got, ref in ((gd[:, b], rgd), (gq[:, b, 0], rgq[:, 0]), (gq[:, b, 1], rgq[:, 1]),
+                         (gm[:, b], rgm)):
+            assert (np.abs(got - ref) <= 1e-12 * np.abs(ref) + 1e-13 * N).all(), (got, ref)
