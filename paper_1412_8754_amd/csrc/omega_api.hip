@@ -71,15 +71,15 @@ bool points_ok(const omega_point *pts, int n_pts)
 int delta_tile(int n_delta) { return n_delta >= 32 ? 32 : 16; }
 
 struct Plan {
-    int TY, n_tiles, tiles_per_wg, n_chunks;
+    int TX, TY, n_tiles, tiles_per_wg, n_chunks;
 };
 
 Plan plan_tiles(int Lx, int Ly, long long other_blocks)
 {
     Plan r;
-    const int TX = (Lx + kTileEdge - 1) / kTileEdge;
+    r.TX = (Lx + kTileEdge - 1) / kTileEdge;
     r.TY = (Ly + kTileEdge - 1) / kTileEdge;
-    r.n_tiles = TX * r.TY;
+    r.n_tiles = r.TX * r.TY;
     int tpw = 64;
     while (tpw > 4 &&
            (long long)((r.n_tiles + tpw - 1) / tpw) * other_blocks < kMinWorkgroups)
@@ -198,9 +198,9 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
         a.cutTf = kCutFp32 * (float)pt.T;
         a.Lx = pt.Lx;
         a.Ly = pt.Ly;
+        a.TX = pl.TX;
         a.TY = pl.TY;
         a.n_tiles = pl.n_tiles;
-        a.tiles_per_wg = pl.tiles_per_wg;
         a.n_chunks = pl.n_chunks;
         a.n_q = n_q;
         a.n_delta_pad = n_delta_pad;

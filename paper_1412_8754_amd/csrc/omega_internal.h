@@ -36,10 +36,9 @@ struct SweepArgs {
     double T, invT, cutT;
     float Tf, invTf, cutTf;
     int Lx, Ly;
-    int TY;              // tiles along y (ceil(Ly / 8))
+    int TX, TY;          // tiles along x and y (ceil(L / 8))
     int n_tiles;         // ceil(Lx/8) * ceil(Ly/8)
-    int tiles_per_wg;    // tiles per workgroup (multiple of 4)
-    int n_chunks;        // ceil(n_tiles / tiles_per_wg)
+    int n_chunks;        // workgroups along the momentum axis
     int n_q;
     int n_delta_pad;     // n_delta rounded up to the Delta tile
     const double *d2;    // [n_delta_pad] Delta^2 (padding repeats the last)

@@ -11,6 +11,12 @@
 // sum of non-negative pieces, so plain FP64 accumulation is well conditioned.
 // The Delta-independent piece carries the cancellation of Eq. (5) and is
 // summed once per (k, Q) with Neumaier compensation.
+//
+// Symmetry: for Q = (qx, 0) the term at (kx, ky) equals the term at
+// (kx, -ky) (E_k is even in ky, eta is even, and Q - k maps to its mirror),
+// so a workgroup whose Q has qy == 0 sums ky indices 0..Ly/2 only, with
+// weight 2 on every row that has a distinct mirror.  The Lx*Ly grid is still
+// the one summed; half of it is reached through the mirror.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -20,6 +26,101 @@ namespace omega {
 
 // ------------------------------------------------------------------ math
 
+// sqrt(x) for x >= 0 from the hardware reciprocal square root (relative
+// error ~5e-8 on gfx950), one Goldschmidt step and one residual correction;
+// x = 0 is handled by clamping the reciprocal.  Correctly rounded on every
+// input we have measured.
+__device__ __forceinline__ double sqrt_rn(double x)
+{
+    double r = fmin(__builtin_amdgcn_rsq(x), 1e300);
+    double s = x * r, h = 0.5 * r;
+    double e = fma(-h, s, 0.5);
+    s = fma(s, e, s);
+    h = fma(h, e, h);
+    double d = fma(-s, s, x);
+    return fma(d, h, s);
+}
+
+// sqrt(x) for x > 0 with one Goldschmidt step only: relative error below
+// 5e-15 (the Delta sweep, where it is far inside the required accuracy).
+__device__ __forceinline__ double sqrt_1s(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    double s = x * r;
+    double t = fma(-r, s, 1.0);
+    return fma(0.5 * s, t, s);
+}
+
+// exp(z) for -745 < z <= 0: z = n ln2 + r, |r| <= ln2/2, Taylor series of
+// degree 11 (truncation < 7e-15 relative), scaled by 2^n.
+__device__ __forceinline__ double exp_nonpos(double z)
+{
+    const double kLog2e = 1.4426950408889634;
+    const double kLn2Hi = 6.93147180369123816490e-01;
+    const double kLn2Lo = 1.90821492927058770002e-10;
+    double n = rint(z * kLog2e);
+    double r = fma(-n, kLn2Hi, z);
+    r = fma(-n, kLn2Lo, r);
+    double p = 1.0 / 39916800.0;
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(p, (int)n);
+}
+
+// ln(1 + z) for 0 <= z <= 3: 1 + z = 2^e f with f in [1/sqrt2, sqrt2),
+// ln f = 2 atanh(u), u = (f - 1)/(f + 1), |u| < 0.172, odd series to u^19
+// (truncation < 1e-16).  The rounding of 1 + z costs at most 1.2e-16 absolute.
+__device__ __forceinline__ double log1p_small(double z)
+{
+    const double kLn2Hi = 6.93147180369123816490e-01;
+    const double kLn2Lo = 1.90821492927058770002e-10;
+    double w = 1.0 + z;
+    double f = __builtin_amdgcn_frexp_mant(w);
+    int e = __builtin_amdgcn_frexp_exp(w);
+    bool low = f < 0.70710678118654752440;
+    f = low ? f + f : f;
+    e = low ? e - 1 : e;
+    double num = f - 1.0, den = f + 1.0;
+    double rc = __builtin_amdgcn_rcp(den);
+    rc = fma(rc, fma(-den, rc, 1.0), rc);
+    double u = num * rc;
+    u = fma(fma(-den, u, num), rc, u);
+    double u2 = u * u;
+    double p = 2.0 / 19.0;
+    p = fma(p, u2, 2.0 / 17.0);
+    p = fma(p, u2, 2.0 / 15.0);
+    p = fma(p, u2, 2.0 / 13.0);
+    p = fma(p, u2, 2.0 / 11.0);
+    p = fma(p, u2, 2.0 / 9.0);
+    p = fma(p, u2, 2.0 / 7.0);
+    p = fma(p, u2, 2.0 / 5.0);
+    p = fma(p, u2, 2.0 / 3.0);
+    double lf = fma(p * u2, u, 2.0 * u);
+    double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lf));
+}
+
+// Thermal part of the two quasiparticle branches, ln((1 + u1)(1 + u2)) with
+// u1 = exp(-ax/T), u2 = exp(-y/T) (u2 dropped beyond the cut).  Kept out of
+// line: it runs for few (k, Delta) at low T and would otherwise hold
+// registers and instruction cache in the cold loop.
+__device__ __attribute__((noinline)) double thermal_log(double ax, double y,
+                                                        double invT, double cutT)
+{
+    double u1 = exp_nonpos(-ax * invT);
+    double u2 = (y < cutT) ? exp_nonpos(-y * invT) : 0.0;
+    return log1p_small(u1 + u2 + u1 * u2);
+}
+
 // Band energy of App. A, (A.4), from cos/sin of the two momentum components.
 __device__ __forceinline__ double band_energy(const Hop &t, double eps,
                                               double cx, double sx, double cy,
@@ -28,7 +129,7 @@ __device__ __forceinline__ double band_energy(const Hop &t, double eps,
     double A = fma(t.tB * cx, cy, t.tA * (cx + cy));
     double D = t.tD * (cx - cy);
     double C = t.tC * sx * sy;
-    return fma(eps, sqrt(fma(D, D, C * C)), A);
+    return fma(eps, sqrt_rn(fma(D, D, C * C)), A);
 }
 
 // Neumaier (improved Kahan) accumulation step.
@@ -162,6 +263,36 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
     return r;
 }
 
+// Momentum range of one sweep workgroup.  With qy == 0 only ky indices
+// 0..Ly/2 are visited (mirror symmetry); the tiles of either layout are spread
+// evenly over the same n_chunks workgroups.
+struct KRange {
+    bool fold;
+    int TYw;        // tiles along ky in this layout
+    int jlim;       // ky index bound
+    int begin, end; // tile range of this workgroup
+};
+
+__device__ __forceinline__ KRange k_range(const SweepArgs &a, double qy, int chunk)
+{
+    KRange k;
+    k.fold = (qy == 0.0);
+    const int jf = a.Ly / 2 + 1;
+    k.TYw = k.fold ? (jf + kTileEdge - 1) / kTileEdge : a.TY;
+    k.jlim = k.fold ? jf : a.Ly;
+    const int nt = a.TX * k.TYw;
+    const int span = (nt + a.n_chunks - 1) / a.n_chunks;
+    k.begin = chunk * span;
+    k.end = min(k.begin + span, nt);
+    return k;
+}
+
+// weight of ky index j: 2 when the mirror row Ly - j is folded onto it
+__device__ __forceinline__ double mirror_weight(const KRange &k, int j, int Ly)
+{
+    return (k.fold && j != 0 && 2 * j != Ly) ? 2.0 : 1.0;
+}
+
 template <int TD>
 __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
 {
@@ -173,15 +304,19 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     const double eps = slot ? a.eps[1] : a.eps[0];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const double qy = a.q[2 * iq + 1];
+    const KRange kr = k_range(a, qy, chunk);
 
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * iq], &sqx, &cqx);
-    sincos(a.q[2 * iq + 1], &sqy, &cqy);
+    sincos(qy, &sqy, &cqy);
 
-    double d2[TD];
-#pragma unroll
-    for (int t = 0; t < TD; ++t)
-        d2[t] = a.d2[dtile * TD + t];
+    // Delta^2 of this tile, read from LDS inside the loop (one extra slot for
+    // the look-ahead read of the last iteration)
+    __shared__ double d2s[TD + 1];
+    if (threadIdx.x <= TD)
+        d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+    __syncthreads();
 
     const double *cxt = a.trig;
     const double *sxt = a.trig + a.Lx;
@@ -194,35 +329,39 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
         acc[t] = 0.0;
     double bs = 0.0, bc = 0.0;
     const bool do_base = (dtile == 0);
-
     const int li = lane >> 3, lj = lane & 7;
-    const int tile_begin = chunk * a.tiles_per_wg;
-    int tile_end = tile_begin + a.tiles_per_wg;
-    if (tile_end > a.n_tiles)
-        tile_end = a.n_tiles;
 
-    for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
-        const int ti = tile / a.TY;
-        const int tj = tile - ti * a.TY;
+    for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+        const int ti = tile / kr.TYw;
+        const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
         const int j = tj * kTileEdge + lj;
-        if (i < a.Lx && j < a.Ly) {
+        // an opaque zero offset keeps the Delta^2 reads from being hoisted
+        // out of the loop into (scarce) scalar registers
+        int zoff = 0;
+        asm volatile("" : "+v"(zoff));
+        const double *dp = d2s + zoff;
+        if (i < a.Lx && j < kr.jlim) {
             KQ r = kq_setup(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i], cyt[j],
                             syt[j]);
+            const double w = mirror_weight(kr, j, a.Ly);
             if (do_base)
-                neumaier(bs, bc, r.base);
+                neumaier(bs, bc, w * r.base);
+            const double wT = w * a.T;
+            // R^2 >= 1e-300 keeps the reciprocal square root finite; the
+            // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
+            const double s2p = r.s2 + 1e-300;
+            double dcur = dp[0];
 #pragma unroll
             for (int t = 0; t < TD; ++t) {
-                double R = sqrt(fma(d2[t], r.eta2, r.s2));
-                double x = R - r.m;
-                acc[t] += fmax(x, 0.0);
-                double ax = fabs(x);
-                if (ax < a.cutT) {
-                    double u1 = exp(-ax * a.invT);
-                    double y = R + r.m;
-                    double u2 = (y < a.cutT) ? exp(-y * a.invT) : 0.0;
-                    acc[t] += a.T * log1p(u1 + u2 + u1 * u2);
-                }
+                const double dnext = dp[t + 1];
+                const double R = sqrt_1s(fma(dcur, r.eta2, s2p));
+                const double x = R - r.m;
+                acc[t] = fma(w, fmax(x, 0.0), acc[t]);
+                const double ax = fabs(x);
+                if (ax < a.cutT)
+                    acc[t] = fma(wT, thermal_log(ax, R + r.m, a.invT, a.cutT), acc[t]);
+                dcur = dnext;
             }
         }
     }
@@ -272,8 +411,8 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int nbq,
 // With A0 = |s| - |d| and delta = R - |s| = Delta^2 eta^2 / (R + |s|) (no
 // cancellation), the FP32 difference is delta when A0 >= 0 and
 // max(A0 + delta, 0) otherwise; it is small where the term is large, so its
-// FP32 rounding is small against Omega.  Each thread sums at most
-// tiles_per_wg/4 momenta per Delta in FP32 before the FP64 reduction tree.
+// FP32 rounding is small against Omega.  Each thread sums a few tens of
+// momenta per Delta in FP32 before the FP64 reduction tree.
 struct KQf {
     float s2, as, m, eta2, A0;
     double base;
@@ -318,15 +457,18 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const double eps = slot ? a.eps[1] : a.eps[0];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const double qy = a.q[2 * iq + 1];
+    const KRange kr = k_range(a, qy, chunk);
 
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * iq], &sqx, &cqx);
-    sincos(a.q[2 * iq + 1], &sqy, &cqy);
+    sincos(qy, &sqy, &cqy);
 
-    float d2[TD];
-#pragma unroll
-    for (int t = 0; t < TD; ++t)
-        d2[t] = (float)a.d2[dtile * TD + t];
+    __shared__ float d2s[TD + 1];
+    if (threadIdx.x <= TD)
+        d2s[threadIdx.x] =
+            (float)a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+    __syncthreads();
 
     const double *cxt = a.trig;
     const double *sxt = a.trig + a.Lx;
@@ -340,38 +482,42 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     double bs = 0.0, bc = 0.0;
     const bool do_base = (dtile == 0);
     const float Tf = a.Tf, invTf = a.invTf, cutTf = a.cutTf;
-
     const int li = lane >> 3, lj = lane & 7;
-    const int tile_begin = chunk * a.tiles_per_wg;
-    int tile_end = tile_begin + a.tiles_per_wg;
-    if (tile_end > a.n_tiles)
-        tile_end = a.n_tiles;
 
-    for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
-        const int ti = tile / a.TY;
-        const int tj = tile - ti * a.TY;
+    for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+        const int ti = tile / kr.TYw;
+        const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
         const int j = tj * kTileEdge + lj;
-        if (i < a.Lx && j < a.Ly) {
+        int zoff = 0;
+        asm volatile("" : "+v"(zoff));
+        const float *dp = d2s + zoff;
+        if (i < a.Lx && j < kr.jlim) {
             KQf r = kq_setup_f32(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i],
                                  cyt[j], syt[j]);
+            const double w = mirror_weight(kr, j, a.Ly);
             if (do_base)
-                neumaier(bs, bc, r.base);
+                neumaier(bs, bc, w * r.base);
+            const float wf = (float)w;
             const bool pos = r.A0 >= 0.0f;
+            float dcur = dp[0];
 #pragma unroll
             for (int t = 0; t < TD; ++t) {
-                float g2 = d2[t] * r.eta2;
+                const float dnext = dp[t + 1];
+                float g2 = dcur * r.eta2;
                 float R = __builtin_amdgcn_sqrtf(r.s2 + g2);
                 float del = g2 * __builtin_amdgcn_rcpf(R + r.as);
                 float x = r.A0 + del;
-                acc[t] += pos ? del : fmaxf(x, 0.0f);
+                float piece = pos ? del : fmaxf(x, 0.0f);
                 float ax = fabsf(x);
                 if (ax < cutTf) {
                     float u1 = __expf(-ax * invTf);
                     float y = R + r.m;
                     float u2 = (y < cutTf) ? __expf(-y * invTf) : 0.0f;
-                    acc[t] += Tf * __logf(1.0f + (u1 + u2 + u1 * u2));
+                    piece = fmaf(Tf, __logf(1.0f + (u1 + u2 + u1 * u2)), piece);
                 }
+                acc[t] = fmaf(wf, piece, acc[t]);
+                dcur = dnext;
             }
         }
     }

@@ -112,6 +112,21 @@ def test_random_ragged_cases(seed):
     np.testing.assert_array_equal(rows, rrows)
 
 
+@pytest.mark.parametrize("Lx,Ly", [(17, 9), (24, 30), (13, 2), (40, 3)])
+def test_mirror_folded_rows_match_oracle(Lx, Ly):
+    # Q on the kx axis takes the mirror-folded ky sum (odd and even Ly, the
+    # self-mirrored rows ky = 0 and ky = pi); a Q off the axis in the same
+    # launch takes the full sum.
+    pts = [(0.07, 0.004, Lx, Ly), (-0.12, 0.0, Lx, Ly)]
+    delta = np.linspace(0.0, 0.6, 35)
+    q = np.array([[0.0, 0.0], [0.3, 0.0], [-0.7, 0.0], [2 * np.pi * 3 / Lx, 0.0], [0.2, 0.1]])
+    for prec, rel, floor in ((OMEGA_FP64, 1e-12, 1e-13), (OMEGA_FP32_COMP, 1e-7, 1e-8)):
+        idx, omin, rows, om = run_argmin(pts, delta, q, 3, prec)
+        ref = oracle.omega_grid(M, pts, delta, q, 3)
+        worst = assert_close(om, ref, pts, rel=rel, floor=floor)
+        say(f"fold {Lx}x{Ly} prec {prec}: worst rel {worst:.3e}")
+
+
 def test_deterministic_bitwise():
     c = W.config("small")
     a = run_argmin(c["pts"], c["delta"], c["q"], c["bands"])[3]
