@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-rows", type=int, default=4,
                     help="Q rows per band in the CPU oracle sample")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP32-compensated comparison leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -73,8 +77,24 @@ def cpu_baseline(cfg, rows_per_band):
                       f"at L={pts[0][2]} ({evals:.3e} evals, {dt:.1f} s)"}
 
 
+def calibrate_copy(mib):
+    """A plain device-to-device copy of known size, for scaling the HBM
+    FETCH_SIZE / WRITE_SIZE counters: each copy reads and writes mib MiB."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.arange(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_mib": mib, "ok": bool((y[-1] == x[-1]).item())}))
+    return 0
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        return calibrate_copy(args.calibrate_copy)
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
               "supported (the work shards by independent (point, band, Q) units; see "
@@ -180,6 +200,36 @@ def main():
                                                         else "f32c"),
                      "kernel_ms": sweep_avg, "ops_per_eval": OPS_PER_EVAL},
     }
+    if not args.no_compare and prec == api.OMEGA_FP64:
+        # same workload through the FP32-compensated sweep: time, Omega error
+        # against the FP64 grid just computed, and whether the argmin moved
+        om64 = om.clone()
+        idx64 = idx.clone()
+        prec32 = api.OMEGA_FP32_COMP
+        ws32_bytes = api.workspace_bytes(pts, n_d, n_q, bands, prec32)
+        ws32 = torch.empty(ws32_bytes, dtype=torch.uint8, device=dev)
+
+        def step32():
+            rc = L.omega_argmin(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d,
+                                q.data_ptr(), n_q, bands, prec32, 1e-11, ws32.data_ptr(),
+                                ws32_bytes, idx.data_ptr(), omin.data_ptr(), rows.data_ptr(),
+                                om.data_ptr(), stream.cuda_stream)
+            if rc != 0:
+                raise _abi.OmegaError(rc, "omega_argmin")
+
+        step32()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step32()
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
+        rel = ((om - om64).abs() / om64.abs()).max().item()
+        out["fp32c_compare"] = {"ms_per_step": ms32, "value": evals_step / (ms32 * 1e-3),
+                                "max_rel_omega_vs_fp64": rel,
+                                "argmin_equal": bool(torch.equal(idx, idx64))}
+        print(f"bench: fp32c {ms32:.3f} ms/step, max rel vs fp64 {rel:.2e}, argmin equal "
+              f"{out['fp32c_compare']['argmin_equal']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         cb = cpu_baseline(cfg, args.cpu_rows)

@@ -464,10 +464,15 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     sincos(a.q[2 * iq], &sqx, &cqx);
     sincos(qy, &sqy, &cqy);
 
-    __shared__ float d2s[TD + 1];
-    if (threadIdx.x <= TD)
-        d2s[threadIdx.x] =
-            (float)a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+    // Delta^2 as an unevaluated FP32 pair hi + lo: rounding Delta^2 to one
+    // float would shift every momentum's term at that Delta the same way
+    // (a systematic 6e-8), which the sum would not average out
+    __shared__ float2 d2s[TD + 1];
+    if (threadIdx.x <= TD) {
+        const double v = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+        const float hi = (float)v;
+        d2s[threadIdx.x] = make_float2(hi, (float)(v - (double)hi));
+    }
     __syncthreads();
 
     const double *cxt = a.trig;
@@ -491,7 +496,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         const int j = tj * kTileEdge + lj;
         int zoff = 0;
         asm volatile("" : "+v"(zoff));
-        const float *dp = d2s + zoff;
+        const float2 *dp = d2s + zoff;
         if (i < a.Lx && j < kr.jlim) {
             KQf r = kq_setup_f32(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i],
                                  cyt[j], syt[j]);
@@ -500,11 +505,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
                 neumaier(bs, bc, w * r.base);
             const float wf = (float)w;
             const bool pos = r.A0 >= 0.0f;
-            float dcur = dp[0];
+            float2 dcur = dp[0];
 #pragma unroll
             for (int t = 0; t < TD; ++t) {
-                const float dnext = dp[t + 1];
-                float g2 = dcur * r.eta2;
+                const float2 dnext = dp[t + 1];
+                float g2 = fmaf(dcur.x, r.eta2, dcur.y * r.eta2);
                 float R = __builtin_amdgcn_sqrtf(r.s2 + g2);
                 float del = g2 * __builtin_amdgcn_rcpf(R + r.as);
                 float x = r.A0 + del;

@@ -226,6 +226,28 @@ def test_fp32_compensated_random(seed):
     say(f"fp32c seed {seed}: worst rel {worst:.3e}")
 
 
+def test_precision_workload_fp32c_against_fp64():
+    """L = 2048, 512 Delta x 128 q x 2 bands: the FP32-compensated grid stays
+    within 1e-7 of the FP64 grid everywhere, the minima do not move, and the
+    FP64 grid matches the oracle on sampled entries around the minima."""
+    c = W.config("precision")
+    pts, delta, q = c["pts"], c["delta"], c["q"]
+    idx64, _, rows64, om64 = run_argmin(pts, delta, q, 3, OMEGA_FP64)
+    idx32, _, rows32, om32 = run_argmin(pts, delta, q, 3, OMEGA_FP32_COMP)
+    rel = np.max(np.abs(om32 - om64) / np.abs(om64))
+    say(f"precision workload: max rel fp32c vs fp64 {rel:.3e}; argmin fp64 "
+        f"{idx64.tolist()} fp32c {idx32.tolist()}")
+    assert rel <= 1e-7
+    np.testing.assert_array_equal(idx32, idx64)
+    oracle.set_threads(os.cpu_count() or 1)
+    for b in range(2):
+        d0, q0 = idx64[0, b]
+        ds = sorted({max(d0 - 1, 0), d0, min(d0 + 1, len(delta) - 1)})
+        ref = oracle.omega_grid(M, pts, delta[ds], q[q0:q0 + 1], 1 << b)[0, 0, 0]
+        assert_close(om64[0, b, q0, ds][None], ref[None], pts)
+        assert_close(om32[0, b, q0, ds][None], ref[None], pts, rel=1e-7, floor=1e-8)
+
+
 # ------------------------------------------------------------------ gradient
 
 @pytest.mark.parametrize("seed", range(3))
