@@ -1,9 +1,18 @@
 // C entry points of libomega (declared in include/omega.h): host-side
 // validation, workspace layout and the launch sequence of each call.
+//
+// Points are processed in groups of equal lattice size (first-appearance
+// order), each group in batches whose chunk partials fit a fixed budget.
+// A point's momentum chunking depends only on its own lattice size and the
+// call's Delta / Q / band counts, so its result is bitwise the same whatever
+// batch it travels in.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
+
+#include <algorithm>
+#include <vector>
 
 #include "omega.h"
 #include "omega_internal.h"
@@ -17,7 +26,11 @@ constexpr int kMaxL = 16384;
 constexpr long long kMaxK = 1LL << 26;
 constexpr int kMaxDelta = 1 << 20;
 constexpr int kMaxQ = 16384;
-constexpr int kMinWorkgroups = 4096;   // below this the chunks are split finer
+constexpr int kMaxPoints = 1 << 24;
+constexpr int kMinWorkgroups = 4096;       // per point, below this chunks split finer
+constexpr size_t kBatchBytes = 512u << 20; // chunk partials of one batch
+constexpr int kMaxGridZ = 65535;
+constexpr int kGradTilesPerChunk = 64;
 
 hipEvent_t g_sweep_start = nullptr;   // benchmark hook, see omega_set_sweep_events
 hipEvent_t g_sweep_stop = nullptr;
@@ -60,7 +73,7 @@ bool point_ok(const omega_point &p)
 
 bool points_ok(const omega_point *pts, int n_pts)
 {
-    if (!pts || n_pts <= 0)
+    if (!pts || n_pts <= 0 || n_pts > kMaxPoints)
         return false;
     for (int i = 0; i < n_pts; ++i)
         if (!point_ok(pts[i]))
@@ -68,15 +81,24 @@ bool points_ok(const omega_point *pts, int n_pts)
     return true;
 }
 
+bool sizes_ok(int n_delta, int n_q, int bands, int precision)
+{
+    return n_delta > 0 && n_delta <= kMaxDelta && n_q > 0 && n_q <= kMaxQ &&
+           bands >= 1 && bands <= 3 &&
+           (precision == OMEGA_FP64 || precision == OMEGA_FP32_COMP);
+}
+
 int delta_tile(int n_delta) { return n_delta >= 32 ? 32 : 16; }
 
-struct Plan {
-    int TX, TY, n_tiles, tiles_per_wg, n_chunks;
+struct Tiles {
+    int TX, TY, n_tiles, n_chunks;
 };
 
-Plan plan_tiles(int Lx, int Ly, long long other_blocks)
+// Sweep chunking of one point: 64 tiles per chunk, fewer while a single
+// point would give less than kMinWorkgroups workgroups.
+Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
 {
-    Plan r;
+    Tiles r;
     r.TX = (Lx + kTileEdge - 1) / kTileEdge;
     r.TY = (Ly + kTileEdge - 1) / kTileEdge;
     r.n_tiles = r.TX * r.TY;
@@ -84,40 +106,95 @@ Plan plan_tiles(int Lx, int Ly, long long other_blocks)
     while (tpw > 4 &&
            (long long)((r.n_tiles + tpw - 1) / tpw) * other_blocks < kMinWorkgroups)
         tpw /= 2;
-    r.tiles_per_wg = tpw;
     r.n_chunks = (r.n_tiles + tpw - 1) / tpw;
     return r;
 }
 
-// Per-point scratch of the sweep: trig tables, Delta^2, chunk partials.
-struct SweepLayout {
-    size_t trig, d2, part, base, total;
-};
-
-SweepLayout sweep_layout(const omega_point &p, int n_delta, int n_q, int nb)
+Tiles grad_tiles(int Lx, int Ly)
 {
-    const int td = delta_tile(n_delta);
-    const int n_dtiles = (n_delta + td - 1) / td;
-    const int n_delta_pad = n_dtiles * td;
-    const Plan pl = plan_tiles(p.Lx, p.Ly, (long long)n_dtiles * nb * n_q);
-    SweepLayout l;
-    l.trig = 0;
-    l.d2 = l.trig + align_up(sizeof(double) * 2 * ((size_t)p.Lx + p.Ly));
-    l.part = l.d2 + align_up(sizeof(double) * n_delta_pad);
-    l.base = l.part +
-             align_up(sizeof(double) * (size_t)nb * n_q * pl.n_chunks * n_delta_pad);
-    l.total = l.base + align_up(sizeof(double) * (size_t)nb * n_q * pl.n_chunks);
-    return l;
+    Tiles r;
+    r.TX = (Lx + kTileEdge - 1) / kTileEdge;
+    r.TY = (Ly + kTileEdge - 1) / kTileEdge;
+    r.n_tiles = r.TX * r.TY;
+    r.n_chunks = (r.n_tiles + kGradTilesPerChunk - 1) / kGradTilesPerChunk;
+    return r;
 }
 
-size_t sweep_bytes(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb)
+// Points of equal (Lx, Ly), in order of first appearance.
+struct Group {
+    int Lx, Ly;
+    std::vector<int> idx;
+};
+
+std::vector<Group> group_points(const omega_point *pts, int n)
 {
-    size_t mx = 0;
-    for (int i = 0; i < n_pts; ++i) {
-        size_t b = sweep_layout(pts[i], n_delta, n_q, nb).total;
-        mx = b > mx ? b : mx;
+    std::vector<Group> gs;
+    for (int i = 0; i < n; ++i) {
+        Group *g = nullptr;
+        for (Group &x : gs)
+            if (x.Lx == pts[i].Lx && x.Ly == pts[i].Ly) {
+                g = &x;
+                break;
+            }
+        if (!g) {
+            gs.push_back(Group{pts[i].Lx, pts[i].Ly, {}});
+            g = &gs.back();
+        }
+        g->idx.push_back(i);
     }
-    return mx;
+    return gs;
+}
+
+int batch_points(size_t per_point_bytes, int group_size, int max_z)
+{
+    size_t g = kBatchBytes / (per_point_bytes ? per_point_bytes : 1);
+    if (g < 1)
+        g = 1;
+    if (g > (size_t)group_size)
+        g = group_size;
+    if (g > (size_t)max_z)
+        g = max_z;
+    return (int)g;
+}
+
+// Workspace of a grid / argmin call.
+struct GridPlan {
+    int nb, td, n_dtiles, n_delta_pad, nbq;
+    std::vector<Group> groups;
+    std::vector<Tiles> tiles;   // per group
+    std::vector<int> batch;     // points per batch, per group
+    size_t off_d2, off_trig, off_table, off_part, off_base, sweep_bytes;
+};
+
+GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb)
+{
+    GridPlan p;
+    p.nb = nb;
+    p.td = delta_tile(n_delta);
+    p.n_dtiles = (n_delta + p.td - 1) / p.td;
+    p.n_delta_pad = p.n_dtiles * p.td;
+    p.nbq = nb * n_q;
+    p.groups = group_points(pts, n_pts);
+    size_t trig = 0, table = 0, part = 0, base = 0;
+    for (const Group &g : p.groups) {
+        const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
+        const size_t rows = (size_t)p.nbq * t.n_chunks;
+        const size_t per_point = sizeof(double) * rows * (p.n_delta_pad + 1);
+        const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
+        p.tiles.push_back(t);
+        p.batch.push_back(G);
+        trig = std::max(trig, sizeof(double) * 2 * ((size_t)g.Lx + g.Ly));
+        table = std::max(table, sizeof(PointRec) * (size_t)G);
+        part = std::max(part, sizeof(double) * rows * p.n_delta_pad * G);
+        base = std::max(base, sizeof(double) * rows * G);
+    }
+    p.off_d2 = 0;
+    p.off_trig = p.off_d2 + align_up(sizeof(double) * p.n_delta_pad);
+    p.off_table = p.off_trig + align_up(trig);
+    p.off_part = p.off_table + align_up(table);
+    p.off_base = p.off_part + align_up(part);
+    p.sweep_bytes = p.off_base + align_up(base);
+    return p;
 }
 
 size_t grid_bytes(int n_pts, int n_delta, int n_q, int nb)
@@ -125,28 +202,34 @@ size_t grid_bytes(int n_pts, int n_delta, int n_q, int nb)
     return align_up(sizeof(double) * (size_t)n_pts * nb * n_q * n_delta);
 }
 
-Plan grad_plan(const omega_point &p, int nb)
-{
-    return plan_tiles(p.Lx, p.Ly, nb);
-}
+// Workspace of a gradient call.
+struct GradPlan {
+    std::vector<Group> groups;
+    std::vector<Tiles> tiles;
+    std::vector<int> batch;
+    size_t off_trig, off_table, off_part, bytes;
+};
 
-size_t grad_bytes(const omega_point *pts, int n_pts, int nb)
+GradPlan plan_grad(const omega_point *pts, int n_pts, int nb)
 {
-    size_t mx = 0;
-    for (int i = 0; i < n_pts; ++i) {
-        const Plan pl = grad_plan(pts[i], nb);
-        size_t b = align_up(sizeof(double) * 2 * ((size_t)pts[i].Lx + pts[i].Ly)) +
-                   align_up(sizeof(double) * 5 * (size_t)nb * pl.n_chunks);
-        mx = b > mx ? b : mx;
+    GradPlan p;
+    p.groups = group_points(pts, n_pts);
+    size_t trig = 0, table = 0, part = 0;
+    for (const Group &g : p.groups) {
+        const Tiles t = grad_tiles(g.Lx, g.Ly);
+        const size_t per_point = sizeof(double) * 5 * (size_t)nb * t.n_chunks;
+        const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ);
+        p.tiles.push_back(t);
+        p.batch.push_back(G);
+        trig = std::max(trig, sizeof(double) * 2 * ((size_t)g.Lx + g.Ly));
+        table = std::max(table, sizeof(PointRec) * (size_t)G);
+        part = std::max(part, per_point * G);
     }
-    return mx;
-}
-
-bool sizes_ok(int n_delta, int n_q, int bands, int precision)
-{
-    return n_delta > 0 && n_delta <= kMaxDelta && n_q > 0 && n_q <= kMaxQ &&
-           bands >= 1 && bands <= 3 &&
-           (precision == OMEGA_FP64 || precision == OMEGA_FP32_COMP);
+    p.off_trig = 0;
+    p.off_table = align_up(trig);
+    p.off_part = p.off_table + align_up(table);
+    p.bytes = p.off_part + align_up(part);
+    return p;
 }
 
 Hop make_hop(const omega_model *m)
@@ -159,6 +242,33 @@ Hop make_hop(const omega_model *m)
     return h;
 }
 
+void band_signs(int nb, const int *list, double *eps)
+{
+    eps[0] = list[0] ? 1.0 : -1.0;
+    eps[1] = nb > 1 ? (list[1] ? 1.0 : -1.0) : eps[0];
+}
+
+// Write the records of points idx[0..G) into the device table.
+int upload_points(const omega_point *pts, const int *idx, int G, PointRec *table,
+                  hipStream_t s)
+{
+    for (int b = 0; b < G; b += kFillMax) {
+        PointPack pk;
+        pk.n = G - b < kFillMax ? G - b : kFillMax;
+        pk.pad = 0;
+        for (int i = 0; i < pk.n; ++i) {
+            const omega_point &pt = pts[idx[b + i]];
+            pk.rec[i].h = pt.h;
+            pk.rec[i].T = pt.T;
+            pk.rec[i].out = idx[b + i];
+            pk.rec[i].pad = 0;
+        }
+        if (launch_fill_points(pk, table + b, s) != hipSuccess)
+            return OMEGA_E_HIP;
+    }
+    return OMEGA_OK;
+}
+
 // Enqueue the sweep and row reduction of every point.  Omega goes to `grid`,
 // row minima to row_idx (optional).
 int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
@@ -168,74 +278,76 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
 {
     int list[2];
     const int nb = slot_bands(bands, list);
-    const int td = delta_tile(n_delta);
-    const int n_dtiles = (n_delta + td - 1) / td;
-    const int n_delta_pad = n_dtiles * td;
-    const int nbq = nb * n_q;
-    for (int p = 0; p < n_pts; ++p) {
-        const omega_point &pt = pts[p];
-        const SweepLayout l = sweep_layout(pt, n_delta, n_q, nb);
-        const Plan pl = plan_tiles(pt.Lx, pt.Ly, (long long)n_dtiles * nbq);
-        double *trig = (double *)(ws + l.trig);
-        double *d2 = (double *)(ws + l.d2);
-        double *part = (double *)(ws + l.part);
-        double *base = (double *)(ws + l.base);
-        if (launch_prep(pt.Lx, pt.Ly, trig, delta, n_delta, n_delta_pad, d2, s) !=
-            hipSuccess)
-            return OMEGA_E_HIP;
+    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb);
+    double *d2 = (double *)(ws + P.off_d2);
+    double *trig = (double *)(ws + P.off_trig);
+    PointRec *table = (PointRec *)(ws + P.off_table);
+    double *part = (double *)(ws + P.off_part);
+    double *base = (double *)(ws + P.off_base);
+    if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
+        return OMEGA_E_HIP;
 
-        SweepArgs a;
-        a.hop = make_hop(m);
-        a.eps[0] = list[0] ? 1.0 : -1.0;
-        a.eps[1] = nb > 1 ? (list[1] ? 1.0 : -1.0) : a.eps[0];
-        a.mu_up = m->mu + pt.h;
-        a.mu_dn = m->mu - pt.h;
-        a.T = pt.T;
-        a.invT = pt.T > 0.0 ? 1.0 / pt.T : 0.0;
-        a.cutT = kCutFp64 * pt.T;
-        a.Tf = (float)pt.T;
-        a.invTf = pt.T > 0.0 ? (float)(1.0 / pt.T) : 0.0f;
-        a.cutTf = kCutFp32 * (float)pt.T;
-        a.Lx = pt.Lx;
-        a.Ly = pt.Ly;
-        a.TX = pl.TX;
-        a.TY = pl.TY;
-        a.n_tiles = pl.n_tiles;
-        a.n_chunks = pl.n_chunks;
-        a.n_q = n_q;
-        a.n_delta_pad = n_delta_pad;
-        a.d2 = d2;
-        a.q = q;
-        a.trig = trig;
-        a.part = part;
-        a.base_part = base;
-        if (g_sweep_start && hipEventRecord(g_sweep_start, s) != hipSuccess)
-            return OMEGA_E_HIP;
-        hipError_t e = precision == OMEGA_FP64
-                           ? launch_sweep_f64(a, td, n_dtiles, nbq, s)
-                           : launch_sweep_f32c(a, td, n_dtiles, nbq, s);
-        if (e != hipSuccess)
-            return OMEGA_E_HIP;
-        if (g_sweep_stop && hipEventRecord(g_sweep_stop, s) != hipSuccess)
-            return OMEGA_E_HIP;
+    SweepArgs a;
+    a.hop = make_hop(m);
+    band_signs(nb, list, a.eps);
+    a.mu = m->mu;
+    a.pts = table;
+    a.n_q = n_q;
+    a.nbq = P.nbq;
+    a.n_delta_pad = P.n_delta_pad;
+    a.d2 = d2;
+    a.q = q;
+    a.trig = trig;
+    a.part = part;
+    a.base_part = base;
 
-        RowArgs r;
-        r.part = part;
-        r.base_part = base;
-        r.delta = delta;
-        r.q = q;
-        r.Vs[0] = m->V[list[0]];
-        r.Vs[1] = m->V[nb > 1 ? list[1] : list[0]];
-        r.n_k = (double)pt.Lx * pt.Ly;
-        r.tie_rel = tie_rel;
-        r.n_chunks = pl.n_chunks;
-        r.n_delta = n_delta;
-        r.n_delta_pad = n_delta_pad;
-        r.n_q = n_q;
-        r.omega = grid + (size_t)p * nbq * n_delta;
-        r.row_idx = row_idx ? row_idx + (size_t)p * nbq : nullptr;
-        if (launch_rows(r, nbq, s) != hipSuccess)
+    RowArgs r;
+    r.part = part;
+    r.base_part = base;
+    r.pts = table;
+    r.delta = delta;
+    r.q = q;
+    r.Vs[0] = m->V[list[0]];
+    r.Vs[1] = m->V[nb > 1 ? list[1] : list[0]];
+    r.tie_rel = tie_rel;
+    r.n_delta = n_delta;
+    r.n_delta_pad = P.n_delta_pad;
+    r.n_q = n_q;
+    r.nbq = P.nbq;
+    r.omega = grid;
+    r.row_idx = row_idx;
+
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        const Group &g = P.groups[gi];
+        const Tiles &t = P.tiles[gi];
+        if (launch_trig(g.Lx, g.Ly, trig, s) != hipSuccess)
             return OMEGA_E_HIP;
+        a.Lx = g.Lx;
+        a.Ly = g.Ly;
+        a.TX = t.TX;
+        a.TY = t.TY;
+        a.n_tiles = t.n_tiles;
+        a.n_chunks = t.n_chunks;
+        r.n_k = (double)g.Lx * g.Ly;
+        r.n_chunks = t.n_chunks;
+        const int n = (int)g.idx.size();
+        for (int b0 = 0; b0 < n; b0 += P.batch[gi]) {
+            const int G = n - b0 < P.batch[gi] ? n - b0 : P.batch[gi];
+            int rc = upload_points(pts, g.idx.data() + b0, G, table, s);
+            if (rc != OMEGA_OK)
+                return rc;
+            if (g_sweep_start && hipEventRecord(g_sweep_start, s) != hipSuccess)
+                return OMEGA_E_HIP;
+            hipError_t e = precision == OMEGA_FP64
+                               ? launch_sweep_f64(a, P.td, P.n_dtiles, G, s)
+                               : launch_sweep_f32c(a, P.td, P.n_dtiles, G, s);
+            if (e != hipSuccess)
+                return OMEGA_E_HIP;
+            if (g_sweep_stop && hipEventRecord(g_sweep_stop, s) != hipSuccess)
+                return OMEGA_E_HIP;
+            if (launch_rows(r, G, s) != hipSuccess)
+                return OMEGA_E_HIP;
+        }
     }
     return OMEGA_OK;
 }
@@ -251,10 +363,10 @@ size_t omega_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
         return 0;
     const int nb = n_bands(bands);
     if (grad)
-        return grad_bytes(pts, n_pts, nb);
+        return plan_grad(pts, n_pts, nb).bytes;
     if (!sizes_ok(n_delta, n_q, bands, precision))
         return 0;
-    return sweep_bytes(pts, n_pts, n_delta, n_q, nb) +
+    return plan_grid(pts, n_pts, n_delta, n_q, nb).sweep_bytes +
            grid_bytes(n_pts, n_delta, n_q, nb);
 }
 
@@ -269,7 +381,7 @@ int omega_grid(const omega_model *model, const omega_point *pts, int n_pts,
     if (!delta_dev || !q_dev || !omega_dev || !ws_dev)
         return OMEGA_E_INVAL;
     const int nb = n_bands(bands);
-    if (ws_bytes < sweep_bytes(pts, n_pts, n_delta, n_q, nb))
+    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, nb).sweep_bytes)
         return OMEGA_E_WORKSPACE;
     return enqueue_grid(model, pts, n_pts, delta_dev, n_delta, q_dev, n_q, bands,
                         precision, (char *)ws_dev, 0.0, omega_dev, nullptr,
@@ -291,7 +403,7 @@ int omega_argmin(const omega_model *model, const omega_point *pts, int n_pts,
     if (!(tie_rel >= 0.0) || !isfinite(tie_rel))
         return OMEGA_E_INVAL;
     const int nb = n_bands(bands);
-    const size_t sweep = sweep_bytes(pts, n_pts, n_delta, n_q, nb);
+    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb).sweep_bytes;
     const size_t need = sweep + (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
     if (ws_bytes < need)
         return OMEGA_E_WORKSPACE;
@@ -326,51 +438,60 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
         return OMEGA_E_INVAL;
     int list[2];
     const int nb = slot_bands(bands, list);
-    if (ws_bytes < grad_bytes(pts, n_pts, nb))
+    const GradPlan P = plan_grad(pts, n_pts, nb);
+    if (ws_bytes < P.bytes)
         return OMEGA_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)ws_dev;
-    for (int p = 0; p < n_pts; ++p) {
-        const omega_point &pt = pts[p];
-        const Plan pl = grad_plan(pt, nb);
-        double *trig = (double *)ws;
-        double *part =
-            (double *)(ws + align_up(sizeof(double) * 2 * ((size_t)pt.Lx + pt.Ly)));
-        if (launch_prep(pt.Lx, pt.Ly, trig, delta_dev, 1, 0, nullptr, s) != hipSuccess)
+    double *trig = (double *)(ws + P.off_trig);
+    PointRec *table = (PointRec *)(ws + P.off_table);
+    double *part = (double *)(ws + P.off_part);
+
+    GradArgs a;
+    a.hop = make_hop(model);
+    band_signs(nb, list, a.eps);
+    a.mu = model->mu;
+    a.pts = table;
+    a.nb = nb;
+    a.delta = delta_dev;
+    a.q = q_dev;
+    a.trig = trig;
+    a.part = part;
+    GradFinishArgs f;
+    f.part = part;
+    f.pts = table;
+    f.delta = delta_dev;
+    f.Vs[0] = model->V[list[0]];
+    f.Vs[1] = model->V[nb > 1 ? list[1] : list[0]];
+    f.nb = nb;
+    f.omega = omega_dev;
+    f.dDelta = dDelta_dev;
+    f.dq = dq_dev;
+    f.dmu = dmu_dev;
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        const Group &g = P.groups[gi];
+        const Tiles &t = P.tiles[gi];
+        if (launch_trig(g.Lx, g.Ly, trig, s) != hipSuccess)
             return OMEGA_E_HIP;
-        GradArgs a;
-        a.hop = make_hop(model);
-        a.eps[0] = list[0] ? 1.0 : -1.0;
-        a.eps[1] = nb > 1 ? (list[1] ? 1.0 : -1.0) : a.eps[0];
-        a.mu_up = model->mu + pt.h;
-        a.mu_dn = model->mu - pt.h;
-        a.T = pt.T;
-        a.invT = pt.T > 0.0 ? 1.0 / pt.T : 0.0;
-        a.Lx = pt.Lx;
-        a.Ly = pt.Ly;
-        a.TY = pl.TY;
-        a.n_tiles = pl.n_tiles;
-        a.tiles_per_wg = pl.tiles_per_wg;
-        a.n_chunks = pl.n_chunks;
-        a.delta = delta_dev + (size_t)p * nb;
-        a.q = q_dev + (size_t)p * nb * 2;
-        a.trig = trig;
-        a.part = part;
-        if (launch_grad(a, nb, s) != hipSuccess)
-            return OMEGA_E_HIP;
-        GradFinishArgs f;
-        f.part = part;
-        f.delta = a.delta;
-        f.Vs[0] = model->V[list[0]];
-        f.Vs[1] = model->V[nb > 1 ? list[1] : list[0]];
-        f.n_k = (double)pt.Lx * pt.Ly;
-        f.n_chunks = pl.n_chunks;
-        f.omega = omega_dev + (size_t)p * nb;
-        f.dDelta = dDelta_dev + (size_t)p * nb;
-        f.dq = dq_dev + (size_t)p * nb * 2;
-        f.dmu = dmu_dev + (size_t)p * nb;
-        if (launch_grad_finish(f, nb, s) != hipSuccess)
-            return OMEGA_E_HIP;
+        a.Lx = g.Lx;
+        a.Ly = g.Ly;
+        a.TX = t.TX;
+        a.TY = t.TY;
+        a.n_tiles = t.n_tiles;
+        a.n_chunks = t.n_chunks;
+        f.n_k = (double)g.Lx * g.Ly;
+        f.n_chunks = t.n_chunks;
+        const int n = (int)g.idx.size();
+        for (int b0 = 0; b0 < n; b0 += P.batch[gi]) {
+            const int G = n - b0 < P.batch[gi] ? n - b0 : P.batch[gi];
+            int rc = upload_points(pts, g.idx.data() + b0, G, table, s);
+            if (rc != OMEGA_OK)
+                return rc;
+            if (launch_grad(a, G, s) != hipSuccess)
+                return OMEGA_E_HIP;
+            if (launch_grad_finish(f, G, s) != hipSuccess)
+                return OMEGA_E_HIP;
+        }
     }
     return OMEGA_OK;
 }

@@ -27,39 +27,56 @@ constexpr float kCutFp32 = 17.0f;
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
 
-// Arguments of one Delta-sweep launch (one point, all bands and Q).
+// Per-point record of a batch, written into the workspace by fill_points.
+struct PointRec {
+    double h, T;       // Zeeman field, temperature
+    int32_t out;       // index of the point in the caller's arrays
+    int32_t pad;
+};
+
+// Records travel to the device inside kernel arguments (no host copy, so a
+// call stays capturable in a graph); kFillMax of them per fill launch.
+constexpr int kFillMax = 128;
+struct PointPack {
+    int32_t n, pad;
+    PointRec rec[kFillMax];
+};
+
+// Arguments of one Delta-sweep launch: a batch of G points of one lattice
+// size; grid (chunk, Delta tile, band*Q + nbq*g).
 struct SweepArgs {
     Hop hop;
     double eps[2];       // band sign per output slot (-1: E_-, +1: E_+)
-    double mu_up;        // mu + h  (spin up: E - mu - h)
-    double mu_dn;        // mu - h  (spin down: E - mu + h)
-    double T, invT, cutT;
-    float Tf, invTf, cutTf;
+    double mu;           // chemical potential
+    const PointRec *pts; // [G] this batch
     int Lx, Ly;
     int TX, TY;          // tiles along x and y (ceil(L / 8))
-    int n_tiles;         // ceil(Lx/8) * ceil(Ly/8)
-    int n_chunks;        // workgroups along the momentum axis
+    int n_tiles;         // TX * TY
+    int n_chunks;        // workgroups along the momentum axis per point
     int n_q;
+    int nbq;             // bands * n_q
     int n_delta_pad;     // n_delta rounded up to the Delta tile
     const double *d2;    // [n_delta_pad] Delta^2 (padding repeats the last)
     const double *q;     // [n_q][2]
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
-    double *part;        // [nb*n_q][n_chunks][n_delta_pad] sums of Delta parts
-    double *base_part;   // [nb*n_q][n_chunks] sums of Delta-independent parts
+    double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
+    double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
 };
 
-// Arguments of the per-row reduction / epilogue / row search (one point).
+// Arguments of the per-row reduction / epilogue / row search: grid
+// (band*Q, g) over a batch of G points.
 struct RowArgs {
     const double *part;
     const double *base_part;
+    const PointRec *pts;   // [G]
     const double *delta;   // [n_delta]
     const double *q;       // [n_q][2]
     double Vs[2];          // V per output slot
     double n_k;            // Lx * Ly
     double tie_rel;
-    int n_chunks, n_delta, n_delta_pad, n_q;
-    double *omega;         // [nb][n_q][n_delta] of this point
-    int32_t *row_idx;      // [nb][n_q] of this point, or nullptr
+    int n_chunks, n_delta, n_delta_pad, n_q, nbq;
+    double *omega;         // [n_pts][nbq][n_delta] (all points of the call)
+    int32_t *row_idx;      // [n_pts][nbq], or nullptr
 };
 
 struct ArgminArgs {
@@ -70,38 +87,41 @@ struct ArgminArgs {
     double *omin;          // [n_set]
 };
 
-// Gradient sweep: one point, one (Delta, Q) per band slot.
+// Gradient sweep over a batch of G points of one lattice size: grid
+// (chunk, band slot, g); one (Delta, Q) per point and slot.
 struct GradArgs {
     Hop hop;
     double eps[2];
-    double mu_up, mu_dn;
-    double T, invT;
-    int Lx, Ly, TY, n_tiles, tiles_per_wg, n_chunks;
-    const double *delta;   // [nb] for this point
-    const double *q;       // [nb][2] for this point
+    double mu;
+    const PointRec *pts;   // [G]
+    int Lx, Ly, TX, TY, n_tiles, n_chunks, nb;
+    const double *delta;   // [n_pts][nb] (all points of the call)
+    const double *q;       // [n_pts][nb][2]
     const double *trig;
-    double *part;          // [nb][n_chunks][5]
+    double *part;          // [G][nb][n_chunks][5]
 };
 
 struct GradFinishArgs {
     const double *part;
+    const PointRec *pts;
     const double *delta;
     double Vs[2];
     double n_k;
-    int n_chunks;
-    double *omega, *dDelta, *dq, *dmu;   // this point's outputs, [nb] ([nb][2])
+    int n_chunks, nb;
+    double *omega, *dDelta, *dq, *dmu;   // [n_pts][nb] ([n_pts][nb][2])
 };
 
-hipError_t launch_prep(int Lx, int Ly, double *trig, const double *delta,
-                       int n_delta, int n_delta_pad, double *d2,
-                       hipStream_t s);
-hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int nbq,
+hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s);
+hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
+hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
+                         double *d2, hipStream_t s);
+hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
                             hipStream_t s);
-hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int nbq,
+hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G,
                              hipStream_t s);
-hipError_t launch_rows(const RowArgs &a, int nbq, hipStream_t s);
+hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s);
 hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s);
-hipError_t launch_grad(const GradArgs &a, int nb, hipStream_t s);
-hipError_t launch_grad_finish(const GradFinishArgs &a, int nb, hipStream_t s);
+hipError_t launch_grad(const GradArgs &a, int G, hipStream_t s);
+hipError_t launch_grad_finish(const GradFinishArgs &a, int G, hipStream_t s);
 
 }  // namespace omega

@@ -188,9 +188,22 @@ __device__ __forceinline__ void wave_reduce_halving(double (&acc)[TD], int lane)
 
 // ------------------------------------------------------------------ prep
 
-// cos/sin of the lattice momenta 2 pi i / L and the squared Delta values.
-__global__ void prep_kernel(int Lx, int Ly, double *trig, const double *delta,
-                            int n_delta, int n_delta_pad, double *d2)
+// Point records of a batch, from kernel arguments into the workspace.
+__global__ void fill_points_kernel(const PointPack pk, PointRec *dst)
+{
+    const int t = threadIdx.x;
+    if (t < pk.n)
+        dst[t] = pk.rec[t];
+}
+
+hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_points_kernel, dim3(1), dim3(kFillMax), 0, s, pk, dst);
+    return hipGetLastError();
+}
+
+// cos/sin of the lattice momenta 2 pi i / L.
+__global__ void trig_kernel(int Lx, int Ly, double *trig)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     double s, c;
@@ -204,20 +217,32 @@ __global__ void prep_kernel(int Lx, int Ly, double *trig, const double *delta,
         trig[2 * Lx + t] = c;
         trig[2 * Lx + Ly + t] = s;
     }
+}
+
+hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s)
+{
+    const int n = Lx > Ly ? Lx : Ly;
+    hipLaunchKernelGGL(trig_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Lx, Ly,
+                       trig);
+    return hipGetLastError();
+}
+
+// Squared Delta values, padded to a whole Delta tile with the last value.
+__global__ void delta2_kernel(const double *delta, int n_delta, int n_delta_pad,
+                              double *d2)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_delta_pad) {
-        double D = delta[t < n_delta ? t : n_delta - 1];
+        const double D = delta[t < n_delta ? t : n_delta - 1];
         d2[t] = D * D;
     }
 }
 
-hipError_t launch_prep(int Lx, int Ly, double *trig, const double *delta,
-                       int n_delta, int n_delta_pad, double *d2, hipStream_t s)
+hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
+                         double *d2, hipStream_t s)
 {
-    int n = Lx > Ly ? Lx : Ly;
-    if (n_delta_pad > n)
-        n = n_delta_pad;
-    hipLaunchKernelGGL(prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, Lx,
-                       Ly, trig, delta, n_delta, n_delta_pad, d2);
+    hipLaunchKernelGGL(delta2_kernel, dim3((n_delta_pad + 255) / 256), dim3(256), 0,
+                       s, delta, n_delta, n_delta_pad, d2);
     return hipGetLastError();
 }
 
@@ -239,9 +264,10 @@ struct KQ {
 //   - max(R - |d|, 0) - T ln[(1 + u1)(1 + u2)]   (Delta-dependent)
 // with u1 = exp(-|R - |d||/T), u2 = exp(-(R + |d|)/T).
 __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
-                                       double cqx, double sqx, double cqy,
-                                       double sqy, double cx, double sx,
-                                       double cy, double sy)
+                                       double mu_up, double mu_dn, double cqx,
+                                       double sqx, double cqy, double sqy,
+                                       double cx, double sx, double cy,
+                                       double sy)
 {
     double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
     // cos/sin of (Q - k) by angle subtraction
@@ -250,8 +276,8 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
     double cpy = fma(cqy, cy, sqy * sy);
     double spy = fma(sqy, cy, -(cqy * sy));
     double Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
-    double up = Ek - a.mu_up;
-    double dn = Eq - a.mu_dn;
+    double up = Ek - mu_up;
+    double dn = Eq - mu_dn;
     double s = 0.5 * (up + dn);
     double d = 0.5 * (up - dn);
     double eta = cx * cy;
@@ -259,7 +285,7 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
     r.s2 = s * s;
     r.m = fabs(d);
     r.eta2 = eta * eta;
-    r.base = 2.0 * fmin(d, 0.0) + (Ek - a.mu_dn);
+    r.base = 2.0 * fmin(d, 0.0) + (Ek - mu_dn);
     return r;
 }
 
@@ -298,7 +324,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
 {
     const int chunk = blockIdx.x;
     const int dtile = blockIdx.y;
-    const int bq = blockIdx.z;
+    const int g = blockIdx.z / a.nbq;          // point within the batch
+    const int bq = blockIdx.z - g * a.nbq;
     const int slot = bq / a.n_q;
     const int iq = bq - slot * a.n_q;
     const double eps = slot ? a.eps[1] : a.eps[0];
@@ -306,6 +333,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     const int wave = threadIdx.x >> 6;
     const double qy = a.q[2 * iq + 1];
     const KRange kr = k_range(a, qy, chunk);
+    const PointRec pt = a.pts[g];
+    const double mu_up = a.mu + pt.h;          // spin up: E - mu - h
+    const double mu_dn = a.mu - pt.h;          // spin down: E - mu + h
+    const double T = pt.T;
+    const double invT = T > 0.0 ? 1.0 / T : 0.0;
 
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * iq], &sqx, &cqx);
@@ -322,6 +354,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     const double *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx;
     const double *syt = cyt + a.Ly;
+    const double cutT = kCutFp64 * T;
 
     double acc[TD];
 #pragma unroll
@@ -342,12 +375,12 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
         asm volatile("" : "+v"(zoff));
         const double *dp = d2s + zoff;
         if (i < a.Lx && j < kr.jlim) {
-            KQ r = kq_setup(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i], cyt[j],
-                            syt[j]);
+            KQ r = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
+                            sxt[i], cyt[j], syt[j]);
             const double w = mirror_weight(kr, j, a.Ly);
             if (do_base)
                 neumaier(bs, bc, w * r.base);
-            const double wT = w * a.T;
+            const double wT = w * T;
             // R^2 >= 1e-300 keeps the reciprocal square root finite; the
             // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
             const double s2p = r.s2 + 1e-300;
@@ -359,8 +392,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
                 const double x = R - r.m;
                 acc[t] = fma(w, fmax(x, 0.0), acc[t]);
                 const double ax = fabs(x);
-                if (ax < a.cutT)
-                    acc[t] = fma(wT, thermal_log(ax, R + r.m, a.invT, a.cutT), acc[t]);
+                if (ax < cutT)
+                    acc[t] = fma(wT, thermal_log(ax, R + r.m, invT, cutT), acc[t]);
                 dcur = dnext;
             }
         }
@@ -380,18 +413,18 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     if (threadIdx.x < TD) {
         const int src = threadIdx.x << SHIFT;
         double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-        a.part[((size_t)bq * a.n_chunks + chunk) * a.n_delta_pad +
+        a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
                dtile * TD + threadIdx.x] = v;
     }
     if (do_base && threadIdx.x == 0)
-        a.base_part[(size_t)bq * a.n_chunks + chunk] =
+        a.base_part[(size_t)blockIdx.z * a.n_chunks + chunk] =
             ((bred[0] + bred[1]) + bred[2]) + bred[3];
 }
 
-hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int nbq,
+hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
                             hipStream_t s)
 {
-    dim3 grid(a.n_chunks, n_dtiles, nbq);
+    dim3 grid(a.n_chunks, n_dtiles, a.nbq * G);
     switch (td) {
     case 16:
         hipLaunchKernelGGL(sweep_f64_kernel<16>, grid, dim3(kBlock), 0, s, a);
@@ -419,6 +452,7 @@ struct KQf {
 };
 
 __device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
+                                            double mu_up, double mu_dn,
                                             double cqx, double sqx, double cqy,
                                             double sqy, double cx, double sx,
                                             double cy, double sy)
@@ -429,8 +463,8 @@ __device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
     double cpy = fma(cqy, cy, sqy * sy);
     double spy = fma(sqy, cy, -(cqy * sy));
     double Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
-    double up = Ek - a.mu_up;
-    double dn = Eq - a.mu_dn;
+    double up = Ek - mu_up;
+    double dn = Eq - mu_dn;
     double s = 0.5 * (up + dn);
     double d = 0.5 * (up - dn);
     double eta = cx * cy;
@@ -442,7 +476,7 @@ __device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
     r.m = (float)m;
     r.eta2 = (float)(eta * eta);
     r.A0 = (float)A0;
-    r.base = (2.0 * fmin(d, 0.0) + (Ek - a.mu_dn)) - fmax(A0, 0.0);
+    r.base = (2.0 * fmin(d, 0.0) + (Ek - mu_dn)) - fmax(A0, 0.0);
     return r;
 }
 
@@ -451,7 +485,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
 {
     const int chunk = blockIdx.x;
     const int dtile = blockIdx.y;
-    const int bq = blockIdx.z;
+    const int g = blockIdx.z / a.nbq;          // point within the batch
+    const int bq = blockIdx.z - g * a.nbq;
     const int slot = bq / a.n_q;
     const int iq = bq - slot * a.n_q;
     const double eps = slot ? a.eps[1] : a.eps[0];
@@ -459,6 +494,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const int wave = threadIdx.x >> 6;
     const double qy = a.q[2 * iq + 1];
     const KRange kr = k_range(a, qy, chunk);
+    const PointRec pt = a.pts[g];
+    const double mu_up = a.mu + pt.h;          // spin up: E - mu - h
+    const double mu_dn = a.mu - pt.h;          // spin down: E - mu + h
+    const double T = pt.T;
+    const double invT = T > 0.0 ? 1.0 / T : 0.0;
 
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * iq], &sqx, &cqx);
@@ -486,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         acc[t] = 0.0f;
     double bs = 0.0, bc = 0.0;
     const bool do_base = (dtile == 0);
-    const float Tf = a.Tf, invTf = a.invTf, cutTf = a.cutTf;
+    const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
     const int li = lane >> 3, lj = lane & 7;
 
     for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
@@ -498,8 +538,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         asm volatile("" : "+v"(zoff));
         const float2 *dp = d2s + zoff;
         if (i < a.Lx && j < kr.jlim) {
-            KQf r = kq_setup_f32(a, eps, cqx, sqx, cqy, sqy, cxt[i], sxt[i],
-                                 cyt[j], syt[j]);
+            KQf r = kq_setup_f32(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
+                                 sxt[i], cyt[j], syt[j]);
             const double w = mirror_weight(kr, j, a.Ly);
             if (do_base)
                 neumaier(bs, bc, w * r.base);
@@ -545,18 +585,18 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     if (threadIdx.x < TD) {
         const int src = threadIdx.x << SHIFT;
         double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-        a.part[((size_t)bq * a.n_chunks + chunk) * a.n_delta_pad +
+        a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
                dtile * TD + threadIdx.x] = v;
     }
     if (do_base && threadIdx.x == 0)
-        a.base_part[(size_t)bq * a.n_chunks + chunk] =
+        a.base_part[(size_t)blockIdx.z * a.n_chunks + chunk] =
             ((bred[0] + bred[1]) + bred[2]) + bred[3];
 }
 
-hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int nbq,
+hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G,
                              hipStream_t s)
 {
-    dim3 grid(a.n_chunks, n_dtiles, nbq);
+    dim3 grid(a.n_chunks, n_dtiles, a.nbq * G);
     switch (td) {
     case 16:
         hipLaunchKernelGGL(sweep_f32c_kernel<16>, grid, dim3(kBlock), 0, s, a);
@@ -619,20 +659,23 @@ __device__ __forceinline__ double tie_threshold(double best, double tie_rel)
     return __dadd_rn(best, __dmul_rn(tie_rel, fabs(best)));
 }
 
-// One workgroup per (band slot, Q) row: fixed-order chunk sums, the
-// epilogue of Eq. (5) (+ N (-2 Delta^2 / V)), and the row search of
+// One workgroup per (band slot, Q) row of one point: fixed-order chunk sums,
+// the epilogue of Eq. (5) (+ N (-2 Delta^2 / V)), and the row search of
 // Algorithm 1 ("find and save Delta for this q").
 __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
 {
     const int bq = blockIdx.x;
+    const int g = blockIdx.y;
     const int slot = bq / r.n_q;
     const int iq = bq - slot * r.n_q;
+    const size_t row = (size_t)g * r.nbq + bq;       // partial row of the batch
+    const size_t orow = (size_t)r.pts[g].out * r.nbq + bq;  // output row
     __shared__ double sh_base;
     __shared__ double shd[4];
     __shared__ int shi[4];
     if (threadIdx.x == 0) {
         double s = 0.0, c = 0.0;
-        const double *bp = r.base_part + (size_t)bq * r.n_chunks;
+        const double *bp = r.base_part + row * r.n_chunks;
         for (int ch = 0; ch < r.n_chunks; ++ch)
             neumaier(s, c, bp[ch]);
         sh_base = s + c;
@@ -642,8 +685,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     // 0 * q is 0 for finite q and NaN for NaN q: a NaN momentum poisons the row
     const double qpoison = 0.0 * r.q[2 * iq] + 0.0 * r.q[2 * iq + 1];
     const double V = slot ? r.Vs[1] : r.Vs[0];
-    double *out = r.omega + (size_t)bq * r.n_delta;
-    const double *pp = r.part + (size_t)bq * r.n_chunks * r.n_delta_pad;
+    double *out = r.omega + orow * r.n_delta;
+    const double *pp = r.part + row * r.n_chunks * r.n_delta_pad;
 
     double best = __longlong_as_double(0x7ff8000000000000LL);
     for (int id = threadIdx.x; id < r.n_delta; id += kBlock) {
@@ -671,12 +714,12 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     }
     pick = block_int_min(pick, shi);
     if (threadIdx.x == 0)
-        r.row_idx[bq] = pick == 0x7fffffff ? -1 : pick;
+        r.row_idx[orow] = pick == 0x7fffffff ? -1 : pick;
 }
 
-hipError_t launch_rows(const RowArgs &a, int nbq, hipStream_t s)
+hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s)
 {
-    hipLaunchKernelGGL(rows_kernel, dim3(nbq), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(rows_kernel, dim3(a.nbq, G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -778,24 +821,30 @@ __device__ __forceinline__ double softplus_neg(double E, double T, double invT)
 
 // Per k: the term of Eq. (5) and its derivatives with respect to Delta,
 // qx, qy and mu; 5 compensated sums per thread, fixed-order block reduction.
+// Grid (chunk, band slot, point of the batch).
 __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
 {
     const int chunk = blockIdx.x;
     const int slot = blockIdx.y;
+    const int g = blockIdx.z;
+    const PointRec pt = a.pts[g];
+    const size_t io = (size_t)pt.out * a.nb + slot;   // input/output slot
     const double eps = slot ? a.eps[1] : a.eps[0];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const double D = a.delta[slot];
+    const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
+    const double T = pt.T;
+    const double invT = T > 0.0 ? 1.0 / T : 0.0;
+    const double D = a.delta[io];
     double sqx, cqx, sqy, cqy;
-    sincos(a.q[2 * slot], &sqx, &cqx);
-    sincos(a.q[2 * slot + 1], &sqy, &cqy);
+    sincos(a.q[2 * io], &sqx, &cqx);
+    sincos(a.q[2 * io + 1], &sqy, &cqy);
     const double *cxt = a.trig, *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx, *syt = cyt + a.Ly;
     double s_[5] = {0, 0, 0, 0, 0}, c_[5] = {0, 0, 0, 0, 0};
     const int li = lane >> 3, lj = lane & 7;
-    const int tile_begin = chunk * a.tiles_per_wg;
-    int tile_end = tile_begin + a.tiles_per_wg;
-    if (tile_end > a.n_tiles)
-        tile_end = a.n_tiles;
+    const int span = (a.n_tiles + a.n_chunks - 1) / a.n_chunks;
+    const int tile_begin = chunk * span;
+    const int tile_end = min(tile_begin + span, a.n_tiles);
     for (int tile = tile_begin + wave; tile < tile_end; tile += 4) {
         const int ti = tile / a.TY;
         const int tj = tile - ti * a.TY;
@@ -808,19 +857,19 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
             double cpy = fma(cqy, cy, sqy * sy), spy = fma(sqy, cy, -(cqy * sy));
             double Eq, bx, by;
             band_grad(a.hop, eps, cpx, spx, cpy, spy, Eq, bx, by);
-            double up = Ek - a.mu_up, dn = Eq - a.mu_dn;
+            double up = Ek - mu_up, dn = Eq - mu_dn;
             double s = 0.5 * (up + dn), d = 0.5 * (up - dn);
             double eta = cx * cy;
-            double g = D * eta;
-            double R = sqrt(fma(s, s, g * g));
+            double gap = D * eta;
+            double R = sqrt(fma(s, s, gap * gap));
             double Ep = d + R, Em = d - R;
-            double fp = fermi(Ep, a.T, a.invT), fm = fermi(Em, a.T, a.invT);
+            double fp = fermi(Ep, T, invT), fm = fermi(Em, T, invT);
             double sr = R > 0.0 ? s / R : 0.0;
-            double dr = R > 0.0 ? g * eta / R : 0.0;
+            double dr = R > 0.0 ? gap * eta / R : 0.0;
             double w = 0.5 * fp * (sr - 1.0) - 0.5 * fm * (sr + 1.0);
             neumaier(s_[0], c_[0],
-                     (softplus_neg(Ep, a.T, a.invT) + softplus_neg(Em, a.T, a.invT)) +
-                         (Ek - a.mu_dn));
+                     (softplus_neg(Ep, T, invT) + softplus_neg(Em, T, invT)) +
+                         (Ek - mu_dn));
             neumaier(s_[1], c_[1], dr * (fp - fm));
             neumaier(s_[2], c_[2], bx * w);
             neumaier(s_[3], c_[3], by * w);
@@ -837,51 +886,56 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
     __syncthreads();
     if (threadIdx.x < 5) {
         const int c = threadIdx.x;
-        a.part[((size_t)slot * a.n_chunks + chunk) * 5 + c] =
+        a.part[(((size_t)g * a.nb + slot) * a.n_chunks + chunk) * 5 + c] =
             ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
     }
 }
 
-hipError_t launch_grad(const GradArgs &a, int nb, hipStream_t s)
+hipError_t launch_grad(const GradArgs &a, int G, hipStream_t s)
 {
-    hipLaunchKernelGGL(grad_kernel, dim3(a.n_chunks, nb), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(grad_kernel, dim3(a.n_chunks, a.nb, G), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
+// Fixed-order chunk sums of the gradient sweep plus the Delta terms of
+// Eq. (5): grid (band slot, point of the batch), one lane per quantity.
 __global__ void grad_finish_kernel(const GradFinishArgs a)
 {
     const int slot = blockIdx.x;
+    const int g = blockIdx.y;
     const int c = threadIdx.x;
     if (c >= 5)
         return;
+    const size_t io = (size_t)a.pts[g].out * a.nb + slot;
+    const double *pp = a.part + ((size_t)g * a.nb + slot) * a.n_chunks * 5;
     double s = 0.0, e = 0.0;
     for (int ch = 0; ch < a.n_chunks; ++ch)
-        neumaier(s, e, a.part[((size_t)slot * a.n_chunks + ch) * 5 + c]);
+        neumaier(s, e, pp[(size_t)ch * 5 + c]);
     double v = s + e;
-    const double D = a.delta[slot];
+    const double D = a.delta[io];
     const double V = slot ? a.Vs[1] : a.Vs[0];
     switch (c) {
     case 0:
-        a.omega[slot] = v + a.n_k * (-2.0 * D * D / V);
+        a.omega[io] = v + a.n_k * (-2.0 * D * D / V);
         break;
     case 1:
-        a.dDelta[slot] = v - 4.0 * a.n_k * D / V;
+        a.dDelta[io] = v - 4.0 * a.n_k * D / V;
         break;
     case 2:
-        a.dq[2 * slot] = v;
+        a.dq[2 * io] = v;
         break;
     case 3:
-        a.dq[2 * slot + 1] = v;
+        a.dq[2 * io + 1] = v;
         break;
     default:
-        a.dmu[slot] = v - a.n_k;
+        a.dmu[io] = v - a.n_k;
         break;
     }
 }
 
-hipError_t launch_grad_finish(const GradFinishArgs &a, int nb, hipStream_t s)
+hipError_t launch_grad_finish(const GradFinishArgs &a, int G, hipStream_t s)
 {
-    hipLaunchKernelGGL(grad_finish_kernel, dim3(nb), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(grad_finish_kernel, dim3(a.nb, G), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
