@@ -91,8 +91,65 @@ def calibrate_copy(mib):
     return 0
 
 
+def phase_diagram(args):
+    """Phase-diagram workload: every (h, T) point of a 64 x 64 grid, lattice
+    sizes drawn per point, full Omega grid + argmin in one library call, FP64
+    then FP32-compensated.  Prints one JSON line with both wall times."""
+    import torch
+
+    from paper_1412_8754_amd import _abi, api
+    from paper_1412_8754_amd import workloads as W
+
+    cfg = W.phase_config()
+    pts = cfg["pts"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    delta = torch.as_tensor(cfg["delta"], dtype=torch.float64, device=dev)
+    q = torch.as_tensor(cfg["q"], dtype=torch.float64, device=dev).contiguous()
+    n_d, n_q, nb = delta.numel(), q.shape[0], 2
+    evals = sum(p[2] * p[3] for p in pts) * n_d * n_q * nb
+    res = {}
+    for name, prec in (("fp64", api.OMEGA_FP64), ("fp32c", api.OMEGA_FP32_COMP)):
+        ws = torch.empty(api.workspace_bytes(pts, n_d, n_q, 3, prec), dtype=torch.uint8,
+                         device=dev)
+        small = [p for p in pts if p[2] == 256][:8]
+        api.argmin(W.DEFAULT_MODEL, small, delta, q, 3, prec, keep_grid=False)   # warm-up
+        torch.cuda.synchronize()
+        print(f"bench: phase diagram {len(pts)} points, {evals:.3e} evals, {name}",
+              file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        idx, omin, rows, om = api.argmin(W.DEFAULT_MODEL, pts, delta, q, 3, prec,
+                                         workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"wall_s": dt, "evals_per_s": evals / dt, "idx": idx.cpu(),
+                     "om": om}
+        print(f"bench: {name} {dt:.3f} s, {evals / dt:.3e} evals/s", file=sys.stderr,
+              flush=True)
+        del ws
+    same = (res["fp64"]["idx"] == res["fp32c"]["idx"]).all(dim=-1)
+    rel = ((res["fp32c"]["om"] - res["fp64"]["om"]).abs() / res["fp64"]["om"].abs()).max().item()
+    out = {"metric": "phase-diagram wall time (Omega grid + argmin over all points)",
+           "value": res["fp64"]["wall_s"], "unit": "s", "higher_is_better": False,
+           "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"phase: {len(pts)} (h,T) points, h in [0,0.4], T in "
+                                  f"[1e-3,0.05], L per point from {{256,512,1024,2048}} "
+                                  f"(SplitMix64), {n_d} Delta x {n_q} Q x 2 bands",
+                      "evals": evals},
+           "fp64": {"wall_s": res["fp64"]["wall_s"], "evals_per_s": res["fp64"]["evals_per_s"]},
+           "fp32c": {"wall_s": res["fp32c"]["wall_s"],
+                     "evals_per_s": res["fp32c"]["evals_per_s"]},
+           "fp32c_vs_fp64": {"max_rel_omega": rel,
+                             "argmin_equal_fraction": same.float().mean().item(),
+                             "argmin_differs": int((~same).sum().item())}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     args = parse()
+    if args.workload == "phase":
+        return phase_diagram(args)
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
     if args.gpus != 1:

@@ -438,24 +438,39 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
     return hipGetLastError();
 }
 
-// FP32-compensated sweep.  The term is split as
-//   [2 min(d,0) + E_{k down} - max(|s| - |d|, 0)]                 FP64, once per (k, Q)
-//   - [max(R - |d|, 0) - max(|s| - |d|, 0) + T ln((1+u1)(1+u2))]   FP32, per Delta
+// FP32-compensated sweep.  With P(Delta) = max(R - |d|, 0) + T ln((1+u1)(1+u2))
+// the term of Eq. (5) is [2 min(d,0) + E_{k down}] - P(Delta), split as
+//   [2 min(d,0) + E_{k down} - P(0)]          FP64, once per (k, Q)
+//   - [P(Delta) - P(0)]                       FP32, per Delta
 // With A0 = |s| - |d| and delta = R - |s| = Delta^2 eta^2 / (R + |s|) (no
-// cancellation), the FP32 difference is delta when A0 >= 0 and
-// max(A0 + delta, 0) otherwise; it is small where the term is large, so its
-// FP32 rounding is small against Omega.  Each thread sums a few tens of
-// momenta per Delta in FP32 before the FP64 reduction tree.
+// cancellation), the cold part of the difference is delta when A0 >= 0 and
+// max(A0 + delta, 0) otherwise.  The thermal part is T (L(Delta) - L(0)) with
+// both logarithms in FP32.  The difference vanishes at Delta = 0, where the
+// result is exactly the FP64 value (Delta = 0 slots are zeroed), so the
+// Q-degenerate normal-state row keeps its FP64 degeneracy; elsewhere it is
+// small where the term is large.  Each thread sums a few tens of momenta per
+// Delta in FP32 before the FP64 reduction tree.
 struct KQf {
     float s2, as, m, eta2, A0;
+    float P0;      // T * L(0) in FP32, through the Delta loop's own arithmetic
     double base;
 };
+
+// FP32 thermal logarithm of the Delta loop, ln((1 + u1)(1 + u2)).
+__device__ __forceinline__ float thermal_log_f32(float ax, float y, float invT,
+                                                 float cutT)
+{
+    float u1 = __expf(-ax * invT);
+    float u2 = (y < cutT) ? __expf(-y * invT) : 0.0f;
+    return __logf(1.0f + (u1 + u2 + u1 * u2));
+}
 
 __device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
                                             double mu_up, double mu_dn,
                                             double cqx, double sqx, double cqy,
                                             double sqy, double cx, double sx,
-                                            double cy, double sy)
+                                            double cy, double sy, double T,
+                                            double invT)
 {
     double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
     double cpx = fma(cqx, cx, sqx * sx);
@@ -470,13 +485,25 @@ __device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
     double eta = cx * cy;
     double as = fabs(s), m = fabs(d);
     double A0 = as - m;
+    // P(0) in FP64 for the baseline
+    const double cutT = kCutFp64 * T;
+    double P0 = fmax(A0, 0.0);
+    if (fabs(A0) < cutT)
+        P0 = fma(T, thermal_log(fabs(A0), as + m, invT, cutT), P0);
     KQf r;
     r.s2 = (float)(s * s);
-    r.as = (float)as;
+    // |s| >= 1e-30 keeps R + |s| > 0 at s = Delta = 0 (delta stays 0 there)
+    r.as = (float)fmax(as, 1e-30);
     r.m = (float)m;
     r.eta2 = (float)(eta * eta);
     r.A0 = (float)A0;
-    r.base = (2.0 * fmin(d, 0.0) + (Ek - mu_dn)) - fmax(A0, 0.0);
+    const float Tf = (float)T, cutTf = kCutFp32 * Tf;
+    const float ax0 = fabsf(r.A0);
+    r.P0 = ax0 < cutTf
+               ? Tf * thermal_log_f32(ax0, __builtin_amdgcn_sqrtf(r.s2) + r.m,
+                                      (float)invT, cutTf)
+               : 0.0f;
+    r.base = (2.0 * fmin(d, 0.0) + (Ek - mu_dn)) - P0;
     return r;
 }
 
@@ -539,7 +566,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         const float2 *dp = d2s + zoff;
         if (i < a.Lx && j < kr.jlim) {
             KQf r = kq_setup_f32(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
-                                 sxt[i], cyt[j], syt[j]);
+                                 sxt[i], cyt[j], syt[j], T, invT);
+            const bool hot0 = r.P0 != 0.0f;
             const double w = mirror_weight(kr, j, a.Ly);
             if (do_base)
                 neumaier(bs, bc, w * r.base);
@@ -555,11 +583,10 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
                 float x = r.A0 + del;
                 float piece = pos ? del : fmaxf(x, 0.0f);
                 float ax = fabsf(x);
-                if (ax < cutTf) {
-                    float u1 = __expf(-ax * invTf);
-                    float y = R + r.m;
-                    float u2 = (y < cutTf) ? __expf(-y * invTf) : 0.0f;
-                    piece = fmaf(Tf, __logf(1.0f + (u1 + u2 + u1 * u2)), piece);
+                if (ax < cutTf || hot0) {
+                    float L = ax < cutTf ? thermal_log_f32(ax, R + r.m, invTf, cutTf)
+                                         : 0.0f;
+                    piece += fmaf(Tf, L, -r.P0);
                 }
                 acc[t] = fmaf(wf, piece, acc[t]);
                 dcur = dnext;
@@ -567,10 +594,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         }
     }
 
+    // Delta = 0 slots: the FP32 difference is zero by construction
     double accd[TD];
 #pragma unroll
     for (int t = 0; t < TD; ++t)
-        accd[t] = (double)acc[t];
+        accd[t] = (d2s[t].x == 0.0f && d2s[t].y == 0.0f) ? 0.0 : (double)acc[t];
     __shared__ double red[4][64];
     __shared__ double bred[4];
     wave_reduce_halving<TD>(accd, lane);

@@ -75,6 +75,13 @@ def config(name: str) -> dict:
     raise KeyError(name)
 
 
+def phase_config(n_h: int = 64, n_t: int = 64, fixed_L: int | None = None) -> dict:
+    """Phase diagram: 64 x 64 (h, T) points, lattice sizes drawn per point,
+    128 Delta in [0, 0.6], 32 Q = (j pi/256, 0), both bands."""
+    return {"name": "phase", "pts": phase_points(n_h, n_t, fixed_L=fixed_L),
+            "delta": delta_grid(128), "q": q_axis(32, math.pi / 256), "bands": BAND_BOTH}
+
+
 def phase_points(n_h: int = 64, n_t: int = 64, seed: int = 0x14128754,
                  sizes=(256, 512, 1024, 2048), fixed_L: int | None = None):
     """Phase-diagram points: h in [0, 0.4], T in [1e-3, 0.05] (both linear),
