@@ -140,13 +140,20 @@ const char *omega_strerror(int code);
 int omega_version(void);
 
 /* Timing hook for benchmarks (the paper times the computation part only,
- * Sec. 3.3).  While set, every Delta-sweep kernel the process enqueues is
- * bracketed by hipEventRecord(start_event) and hipEventRecord(stop_event) on
- * the call's stream; start_event and stop_event are hipEvent_t handles owned
- * by the caller.  Passing NULL for both clears the hook.  Process-wide, not
+ * Sec. 3.3).  While set, the per-Delta sweep kernel of every batch the
+ * process enqueues is bracketed by hipEventRecord(start_event) and
+ * hipEventRecord(stop_event) on the call's stream; start_event and stop_event are hipEvent_t handles owned by the
+ * caller.  Passing NULL for both clears the hook.  Process-wide, not
  * thread-safe: set it only while a single thread drives the library.
  * Returns OMEGA_E_INVAL if exactly one of the two is NULL. */
 int omega_set_sweep_events(void *start_event, void *stop_event);
+
+/* Work counter for benchmarks.  While set (count_dev a device pointer to one
+ * zeroed unsigned 64-bit integer), the per-Delta sweep adds the number of
+ * (k, Delta) terms it evaluated directly; terms whose Delta dependence is
+ * summed through moments of the Delta^2 series (where |s| - |d| >= 36 T
+ * and Delta_max^2 eta^2 <= 0.3 s^2) are not counted.  NULL clears it.  Process-wide, not thread-safe.  Always OMEGA_OK. */
+int omega_set_sweep_counter(unsigned long long *count_dev);
 
 #ifdef __cplusplus
 }

@@ -12,7 +12,8 @@ OMEGA_FP64, OMEGA_FP32_COMP = 0, 1
 OMEGA_OK, OMEGA_E_INVAL, OMEGA_E_WORKSPACE, OMEGA_E_HIP, OMEGA_E_UNSUPPORTED = 0, -1, -2, -3, -4
 
 EXPORTS = ("omega_workspace_bytes", "omega_grid", "omega_argmin", "omega_grad",
-           "omega_strerror", "omega_version", "omega_set_sweep_events")
+           "omega_strerror", "omega_version", "omega_set_sweep_events",
+           "omega_set_sweep_counter")
 
 
 class Model(ctypes.Structure):
@@ -68,6 +69,8 @@ def load() -> ctypes.CDLL:
     L.omega_version.argtypes = []
     L.omega_set_sweep_events.restype = i32
     L.omega_set_sweep_events.argtypes = [vp, vp]
+    L.omega_set_sweep_counter.restype = i32
+    L.omega_set_sweep_counter.argtypes = [vp]
     _lib = L
     return L
 

@@ -32,8 +32,9 @@ constexpr size_t kBatchBytes = 512u << 20; // chunk partials of one batch
 constexpr int kMaxGridZ = 65535;
 constexpr int kGradTilesPerChunk = 64;
 
-hipEvent_t g_sweep_start = nullptr;   // benchmark hook, see omega_set_sweep_events
-hipEvent_t g_sweep_stop = nullptr;
+hipEvent_t g_sweep_start = nullptr;   // benchmark hooks, see omega_set_sweep_events
+hipEvent_t g_sweep_stop = nullptr;    // and omega_set_sweep_counter
+unsigned long long *g_sweep_count = nullptr;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -163,7 +164,7 @@ struct GridPlan {
     std::vector<Group> groups;
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
-    size_t off_d2, off_trig, off_table, off_part, off_base, sweep_bytes;
+    size_t off_d2, off_trig, off_table, off_part, off_base, off_mom, off_mask, sweep_bytes;
 };
 
 GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb)
@@ -175,11 +176,13 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.n_delta_pad = p.n_dtiles * p.td;
     p.nbq = nb * n_q;
     p.groups = group_points(pts, n_pts);
-    size_t trig = 0, table = 0, part = 0, base = 0;
+    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
         const size_t rows = (size_t)p.nbq * t.n_chunks;
-        const size_t per_point = sizeof(double) * rows * (p.n_delta_pad + 1);
+        const size_t per_point =
+            sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots) +
+            sizeof(unsigned long long) * p.nbq * t.n_tiles;
         const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
         p.tiles.push_back(t);
         p.batch.push_back(G);
@@ -187,13 +190,17 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         table = std::max(table, sizeof(PointRec) * (size_t)G);
         part = std::max(part, sizeof(double) * rows * p.n_delta_pad * G);
         base = std::max(base, sizeof(double) * rows * G);
+        mom = std::max(mom, sizeof(double) * rows * kMomentSlots * G);
+        mask = std::max(mask, sizeof(unsigned long long) * p.nbq * t.n_tiles * G);
     }
     p.off_d2 = 0;
-    p.off_trig = p.off_d2 + align_up(sizeof(double) * p.n_delta_pad);
+    p.off_trig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 1));
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.off_base = p.off_part + align_up(part);
-    p.sweep_bytes = p.off_base + align_up(base);
+    p.off_mom = p.off_base + align_up(base);
+    p.off_mask = p.off_mom + align_up(mom);
+    p.sweep_bytes = p.off_mask + align_up(mask);
     return p;
 }
 
@@ -284,6 +291,8 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     PointRec *table = (PointRec *)(ws + P.off_table);
     double *part = (double *)(ws + P.off_part);
     double *base = (double *)(ws + P.off_base);
+    double *mom = (double *)(ws + P.off_mom);
+    unsigned long long *mask = (unsigned long long *)(ws + P.off_mask);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
         return OMEGA_E_HIP;
 
@@ -300,10 +309,14 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     a.trig = trig;
     a.part = part;
     a.base_part = base;
+    a.mpart = mom;
+    a.mask = mask;
+    a.count = g_sweep_count;
 
     RowArgs r;
     r.part = part;
     r.base_part = base;
+    r.mpart = mom;
     r.pts = table;
     r.delta = delta;
     r.q = q;
@@ -336,6 +349,8 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
             int rc = upload_points(pts, g.idx.data() + b0, G, table, s);
             if (rc != OMEGA_OK)
                 return rc;
+            if (launch_series(a, G, precision == OMEGA_FP64, s) != hipSuccess)
+                return OMEGA_E_HIP;
             if (g_sweep_start && hipEventRecord(g_sweep_start, s) != hipSuccess)
                 return OMEGA_E_HIP;
             hipError_t e = precision == OMEGA_FP64
@@ -515,6 +530,12 @@ const char *omega_strerror(int code)
 }
 
 int omega_version(void) { return 1; }
+
+int omega_set_sweep_counter(unsigned long long *count_dev)
+{
+    g_sweep_count = count_dev;
+    return OMEGA_OK;
+}
 
 int omega_set_sweep_events(void *start_event, void *stop_event)
 {

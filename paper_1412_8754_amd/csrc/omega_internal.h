@@ -24,6 +24,18 @@ constexpr double kCutFp64 = 36.0;
 // the terms it would be added to.
 constexpr float kCutFp32 = 17.0f;
 
+// Series path of the sweep.  Where A0 = |s| - |d| >= 36 T (the term is
+// R - |d| >= 36 T for every Delta: cold, positive, no thermal part) and
+// Delta_max^2 eta^2 <= kSeriesRho s^2, the Delta-dependent term
+//   R - |d| = (|s| - |d|) + |s| sum_{n>=1} c_n (Delta^2 eta^2 / s^2)^n,
+// c_n = binomial(1/2, n), is summed over k through the moments
+// C0 = sum (|s| - |d|) and M_n = sum |s| (eta^2/s^2)^n, n = 1..kSeriesTerms.
+// The series alternates with decreasing terms, so the truncation is below
+// |c_31| 0.3^31 = 1e-19 of |s| per term.
+constexpr double kSeriesRho = 0.3;
+constexpr int kSeriesTerms = 30;
+constexpr int kMomentSlots = 32;   // C0, M_1..M_30, one unused slot
+
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
 
@@ -56,11 +68,15 @@ struct SweepArgs {
     int n_q;
     int nbq;             // bands * n_q
     int n_delta_pad;     // n_delta rounded up to the Delta tile
-    const double *d2;    // [n_delta_pad] Delta^2 (padding repeats the last)
+    const double *d2;    // [n_delta_pad + 1] Delta^2 (padding repeats the last),
+                         // then max Delta^2 over the grid
     const double *q;     // [n_q][2]
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
+    double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments
+    unsigned long long *mask;    // [G*nbq][n_tiles] lanes evaluated per Delta
+    unsigned long long *count;   // optional: per-Delta terms evaluated directly
 };
 
 // Arguments of the per-row reduction / epilogue / row search: grid
@@ -68,6 +84,7 @@ struct SweepArgs {
 struct RowArgs {
     const double *part;
     const double *base_part;
+    const double *mpart;   // [G*nbq][n_chunks][kMomentSlots] series moments
     const PointRec *pts;   // [G]
     const double *delta;   // [n_delta]
     const double *q;       // [n_q][2]
@@ -115,6 +132,7 @@ hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s)
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s);
+hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s);
 hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
                             hipStream_t s);
 hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G,

@@ -51,6 +51,14 @@ __device__ __forceinline__ double sqrt_1s(double x)
     return fma(0.5 * s, t, s);
 }
 
+// 1/x for x > 0 (normal): hardware reciprocal and two Newton steps.
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
 // exp(z) for -745 < z <= 0: z = n ln2 + r, |r| <= ln2/2, Taylor series of
 // degree 11 (truncation < 7e-15 relative), scaled by 2^n.
 __device__ __forceinline__ double exp_nonpos(double z)
@@ -227,30 +235,47 @@ hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s)
     return hipGetLastError();
 }
 
-// Squared Delta values, padded to a whole Delta tile with the last value.
-__global__ void delta2_kernel(const double *delta, int n_delta, int n_delta_pad,
-                              double *d2)
+// Squared Delta values, padded to a whole Delta tile with the last value;
+// workgroup 0 also writes max Delta^2 (NaN ignored) into d2[n_delta_pad].
+__global__ __launch_bounds__(kBlock) void delta2_kernel(const double *delta, int n_delta,
+                                                        int n_delta_pad, double *d2)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n_delta_pad) {
         const double D = delta[t < n_delta ? t : n_delta - 1];
         d2[t] = D * D;
     }
+    if (blockIdx.x == 0) {
+        __shared__ double sh[kBlock];
+        double mx = 0.0;
+        for (int i = threadIdx.x; i < n_delta; i += kBlock)
+            mx = fmax(mx, delta[i] * delta[i]);
+        sh[threadIdx.x] = mx;
+        __syncthreads();
+        for (int w = kBlock / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w)
+                sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0)
+            d2[n_delta_pad] = sh[0];
+    }
 }
 
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s)
 {
-    hipLaunchKernelGGL(delta2_kernel, dim3((n_delta_pad + 255) / 256), dim3(256), 0,
-                       s, delta, n_delta, n_delta_pad, d2);
+    hipLaunchKernelGGL(delta2_kernel, dim3((n_delta_pad + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, s, delta, n_delta, n_delta_pad, d2);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ sweep
 
-// Per (k, Q) invariants of one band, shared by the sweep kernels.
+// Per (k, Q) invariants of one band.
 struct KQ {
     double s2;     // ((a + b)/2)^2
+    double as;     // |s|
     double m;      // |(a - b)/2|
     double eta2;   // (cos kx cos ky)^2
     double base;   // Delta-independent part of the term
@@ -283,14 +308,34 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
     double eta = cx * cy;
     KQ r;
     r.s2 = s * s;
+    r.as = fabs(s);
     r.m = fabs(d);
     r.eta2 = eta * eta;
     r.base = 2.0 * fmin(d, 0.0) + (Ek - mu_dn);
     return r;
 }
 
-// Momentum range of one sweep workgroup.  With qy == 0 only ky indices
-// 0..Ly/2 are visited (mirror symmetry); the tiles of either layout are spread
+// Whether the (k, Q) term's Delta dependence goes through the Delta^2 series
+// (see kSeriesRho) rather than the per-Delta loop.  Decided once, in
+// series_kernel, and handed to the sweeps as a per-tile lane mask.
+__device__ __forceinline__ bool series_term(const KQ &r, double dmax2, double cutT)
+{
+    return (r.as - r.m) >= cutT && dmax2 * r.eta2 <= kSeriesRho * r.s2;
+}
+
+// Adds a workgroup's count of directly evaluated (k, Delta) terms (optional
+// instrumentation for the benchmark; integer sums are order independent).
+__device__ __forceinline__ void count_direct(unsigned long long *count, int n)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        n += __shfl_xor(n, off, 64);
+    if ((threadIdx.x & 63) == 0 && n)
+        atomicAdd(count, (unsigned long long)n);
+}
+
+// Momentum range of one workgroup.  With qy == 0 only ky indices 0..Ly/2
+// are visited (mirror symmetry); the tiles of either layout are spread
 // evenly over the same n_chunks workgroups.
 struct KRange {
     bool fold;
@@ -319,6 +364,113 @@ __device__ __forceinline__ double mirror_weight(const KRange &k, int j, int Ly)
     return (k.fold && j != 0 && 2 * j != Ly) ? 2.0 : 1.0;
 }
 
+// Per-(k, Q) pass over one (band, Q, point) and momentum chunk, shared by
+// both precisions:
+//   - the Delta-independent part of the term, Neumaier-summed (for the FP32
+//     sweep minus P(0), the full Delta-dependent part at Delta = 0);
+//   - the Delta^2 series moments C0 = sum w (|s| - |d|) (FP64 only; in FP32
+//     it is part of P(0)) and M_n = sum w |s| (eta^2/s^2)^n;
+//   - for every 8 x 8 tile, the ballot of lanes the per-Delta sweep must
+//     evaluate directly.
+// Grid (chunk, band*Q + nbq*g).
+__global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
+{
+    const int chunk = blockIdx.x;
+    const int g = blockIdx.y / a.nbq;
+    const int bq = blockIdx.y - g * a.nbq;
+    const int slot = bq / a.n_q;
+    const int iq = bq - slot * a.n_q;
+    const double eps = slot ? a.eps[1] : a.eps[0];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const double qy = a.q[2 * iq + 1];
+    const KRange kr = k_range(a, qy, chunk);
+    const PointRec pt = a.pts[g];
+    const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
+    const double T = pt.T;
+    const double invT = T > 0.0 ? 1.0 / T : 0.0;
+    const double cutT = kCutFp64 * T;
+    const double dmax2 = a.d2[a.n_delta_pad];
+    double sqx, cqx, sqy, cqy;
+    sincos(a.q[2 * iq], &sqx, &cqx);
+    sincos(qy, &sqy, &cqy);
+    const double *cxt = a.trig;
+    const double *sxt = a.trig + a.Lx;
+    const double *cyt = a.trig + 2 * a.Lx;
+    const double *syt = cyt + a.Ly;
+    unsigned long long *mask = a.mask + (size_t)blockIdx.y * a.n_tiles;
+    double mom[kMomentSlots];
+#pragma unroll
+    for (int n = 0; n < kMomentSlots; ++n)
+        mom[n] = 0.0;
+    double bs = 0.0, bc = 0.0;
+    const int li = lane >> 3, lj = lane & 7;
+    for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+        const int ti = tile / kr.TYw;
+        const int tj = tile - ti * kr.TYw;
+        const int i = ti * kTileEdge + li;
+        const int j = tj * kTileEdge + lj;
+        bool direct = false;
+        if (i < a.Lx && j < kr.jlim) {
+            const KQ r = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
+                                  sxt[i], cyt[j], syt[j]);
+            const double w = mirror_weight(kr, j, a.Ly);
+            const double A0 = r.as - r.m;
+            double base = r.base;
+            if (!fp64) {
+                double P0 = fmax(A0, 0.0);
+                if (fabs(A0) < cutT)
+                    P0 = fma(T, thermal_log(fabs(A0), r.as + r.m, invT, cutT), P0);
+                base -= P0;
+            }
+            neumaier(bs, bc, w * base);
+            if (series_term(r, dmax2, cutT)) {
+                if (fp64)
+                    mom[0] = fma(w, A0, mom[0]);
+                // s^2 = 0 here only with eta^2 = 0 or Delta_max = 0: the powers vanish
+                const double ratio = r.s2 > 0.0 ? r.eta2 * rcp_nr(r.s2) : 0.0;
+                double t = w * r.as;
+#pragma unroll
+                for (int n = 1; n <= kSeriesTerms; ++n) {
+                    t *= ratio;
+                    mom[n] += t;
+                }
+            } else {
+                direct = true;
+            }
+        }
+        const unsigned long long ballot = __ballot(direct);
+        if (lane == 0)
+            mask[tile] = ballot;
+    }
+    __shared__ double red[4][64];
+    __shared__ double bred[4];
+    const double bv = wave_sum(bs + bc);
+    if (lane == 0)
+        bred[wave] = bv;
+    wave_reduce_halving<kMomentSlots>(mom, lane);
+    red[wave][lane] = mom[0];
+    __syncthreads();
+    constexpr int SHIFT = 6 - Log2<kMomentSlots>::value;
+    if (threadIdx.x < kMomentSlots) {
+        const int src = threadIdx.x << SHIFT;
+        a.mpart[((size_t)blockIdx.y * a.n_chunks + chunk) * kMomentSlots + threadIdx.x] =
+            ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+    }
+    if (threadIdx.x == 0)
+        a.base_part[(size_t)blockIdx.y * a.n_chunks + chunk] =
+            ((bred[0] + bred[1]) + bred[2]) + bred[3];
+}
+
+hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s)
+{
+    hipLaunchKernelGGL(series_kernel, dim3(a.n_chunks, a.nbq * G), dim3(kBlock), 0, s, a,
+                       fp64 ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Per-Delta FP64 sweep over the lanes series_kernel marked for direct
+// evaluation; tiles without such lanes are skipped whole.
 template <int TD>
 __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
 {
@@ -338,6 +490,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     const double mu_dn = a.mu - pt.h;          // spin down: E - mu + h
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
+    const double cutT = kCutFp64 * T;
+    const unsigned long long *mask = a.mask + (size_t)blockIdx.z * a.n_tiles;
 
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * iq], &sqx, &cqx);
@@ -354,17 +508,18 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     const double *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx;
     const double *syt = cyt + a.Ly;
-    const double cutT = kCutFp64 * T;
 
     double acc[TD];
 #pragma unroll
     for (int t = 0; t < TD; ++t)
         acc[t] = 0.0;
-    double bs = 0.0, bc = 0.0;
-    const bool do_base = (dtile == 0);
+    int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
 
     for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+        const unsigned long long mk = mask[tile];
+        if (mk == 0ull)
+            continue;
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
@@ -374,13 +529,12 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
         int zoff = 0;
         asm volatile("" : "+v"(zoff));
         const double *dp = d2s + zoff;
-        if (i < a.Lx && j < kr.jlim) {
+        if ((mk >> lane) & 1ull) {
             KQ r = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
                             sxt[i], cyt[j], syt[j]);
             const double w = mirror_weight(kr, j, a.Ly);
-            if (do_base)
-                neumaier(bs, bc, w * r.base);
             const double wT = w * T;
+            ++n_direct;
             // R^2 >= 1e-300 keeps the reciprocal square root finite; the
             // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
             const double s2p = r.s2 + 1e-300;
@@ -399,15 +553,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
         }
     }
 
+    if (a.count)
+        count_direct(a.count, n_direct * TD);
     __shared__ double red[4][64];
-    __shared__ double bred[4];
     wave_reduce_halving<TD>(acc, lane);
     red[wave][lane] = acc[0];
-    if (do_base) {
-        double bv = wave_sum(bs + bc);
-        if (lane == 0)
-            bred[wave] = bv;
-    }
     __syncthreads();
     constexpr int SHIFT = 6 - Log2<TD>::value;
     if (threadIdx.x < TD) {
@@ -416,9 +566,6 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
         a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
                dtile * TD + threadIdx.x] = v;
     }
-    if (do_base && threadIdx.x == 0)
-        a.base_part[(size_t)blockIdx.z * a.n_chunks + chunk] =
-            ((bred[0] + bred[1]) + bred[2]) + bred[3];
 }
 
 hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
@@ -440,7 +587,7 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
 
 // FP32-compensated sweep.  With P(Delta) = max(R - |d|, 0) + T ln((1+u1)(1+u2))
 // the term of Eq. (5) is [2 min(d,0) + E_{k down}] - P(Delta), split as
-//   [2 min(d,0) + E_{k down} - P(0)]          FP64, once per (k, Q)
+//   [2 min(d,0) + E_{k down} - P(0)]          FP64, in series_kernel
 //   - [P(Delta) - P(0)]                       FP32, per Delta
 // With A0 = |s| - |d| and delta = R - |s| = Delta^2 eta^2 / (R + |s|) (no
 // cancellation), the cold part of the difference is delta when A0 >= 0 and
@@ -448,12 +595,12 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
 // both logarithms in FP32.  The difference vanishes at Delta = 0, where the
 // result is exactly the FP64 value (Delta = 0 slots are zeroed), so the
 // Q-degenerate normal-state row keeps its FP64 degeneracy; elsewhere it is
-// small where the term is large.  Each thread sums a few tens of momenta per
-// Delta in FP32 before the FP64 reduction tree.
+// small where the term is large.  Terms on the series path contribute
+// delta through the FP64 moments instead.  Each thread sums a few tens of
+// momenta per Delta in FP32 before the FP64 reduction tree.
 struct KQf {
     float s2, as, m, eta2, A0;
     float P0;      // T * L(0) in FP32, through the Delta loop's own arithmetic
-    double base;
 };
 
 // FP32 thermal logarithm of the Delta loop, ln((1 + u1)(1 + u2)).
@@ -465,45 +612,21 @@ __device__ __forceinline__ float thermal_log_f32(float ax, float y, float invT,
     return __logf(1.0f + (u1 + u2 + u1 * u2));
 }
 
-__device__ __forceinline__ KQf kq_setup_f32(const SweepArgs &a, double eps,
-                                            double mu_up, double mu_dn,
-                                            double cqx, double sqx, double cqy,
-                                            double sqy, double cx, double sx,
-                                            double cy, double sy, double T,
-                                            double invT)
+__device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
 {
-    double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
-    double cpx = fma(cqx, cx, sqx * sx);
-    double spx = fma(sqx, cx, -(cqx * sx));
-    double cpy = fma(cqy, cy, sqy * sy);
-    double spy = fma(sqy, cy, -(cqy * sy));
-    double Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
-    double up = Ek - mu_up;
-    double dn = Eq - mu_dn;
-    double s = 0.5 * (up + dn);
-    double d = 0.5 * (up - dn);
-    double eta = cx * cy;
-    double as = fabs(s), m = fabs(d);
-    double A0 = as - m;
-    // P(0) in FP64 for the baseline
-    const double cutT = kCutFp64 * T;
-    double P0 = fmax(A0, 0.0);
-    if (fabs(A0) < cutT)
-        P0 = fma(T, thermal_log(fabs(A0), as + m, invT, cutT), P0);
     KQf r;
-    r.s2 = (float)(s * s);
+    r.s2 = (float)q.s2;
     // |s| >= 1e-30 keeps R + |s| > 0 at s = Delta = 0 (delta stays 0 there)
-    r.as = (float)fmax(as, 1e-30);
-    r.m = (float)m;
-    r.eta2 = (float)(eta * eta);
-    r.A0 = (float)A0;
+    r.as = (float)fmax(q.as, 1e-30);
+    r.m = (float)q.m;
+    r.eta2 = (float)q.eta2;
+    r.A0 = (float)(q.as - q.m);
     const float Tf = (float)T, cutTf = kCutFp32 * Tf;
     const float ax0 = fabsf(r.A0);
     r.P0 = ax0 < cutTf
                ? Tf * thermal_log_f32(ax0, __builtin_amdgcn_sqrtf(r.s2) + r.m,
                                       (float)invT, cutTf)
                : 0.0f;
-    r.base = (2.0 * fmin(d, 0.0) + (Ek - mu_dn)) - P0;
     return r;
 }
 
@@ -522,10 +645,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const double qy = a.q[2 * iq + 1];
     const KRange kr = k_range(a, qy, chunk);
     const PointRec pt = a.pts[g];
-    const double mu_up = a.mu + pt.h;          // spin up: E - mu - h
-    const double mu_dn = a.mu - pt.h;          // spin down: E - mu + h
+    const double mu_up = a.mu + pt.h;
+    const double mu_dn = a.mu - pt.h;
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
+    const unsigned long long *mask = a.mask + (size_t)blockIdx.z * a.n_tiles;
 
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * iq], &sqx, &cqx);
@@ -551,12 +675,14 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
 #pragma unroll
     for (int t = 0; t < TD; ++t)
         acc[t] = 0.0f;
-    double bs = 0.0, bc = 0.0;
-    const bool do_base = (dtile == 0);
+    int n_direct = 0;
     const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
     const int li = lane >> 3, lj = lane & 7;
 
     for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+        const unsigned long long mk = mask[tile];
+        if (mk == 0ull)
+            continue;
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
@@ -564,14 +690,13 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         int zoff = 0;
         asm volatile("" : "+v"(zoff));
         const float2 *dp = d2s + zoff;
-        if (i < a.Lx && j < kr.jlim) {
-            KQf r = kq_setup_f32(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
-                                 sxt[i], cyt[j], syt[j], T, invT);
+        if ((mk >> lane) & 1ull) {
+            const KQ q64 = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
+                                    sxt[i], cyt[j], syt[j]);
+            const KQf r = kq_setup_f32(q64, T, invT);
+            const float wf = (float)mirror_weight(kr, j, a.Ly);
+            ++n_direct;
             const bool hot0 = r.P0 != 0.0f;
-            const double w = mirror_weight(kr, j, a.Ly);
-            if (do_base)
-                neumaier(bs, bc, w * r.base);
-            const float wf = (float)w;
             const bool pos = r.A0 >= 0.0f;
             float2 dcur = dp[0];
 #pragma unroll
@@ -599,15 +724,11 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
 #pragma unroll
     for (int t = 0; t < TD; ++t)
         accd[t] = (d2s[t].x == 0.0f && d2s[t].y == 0.0f) ? 0.0 : (double)acc[t];
+    if (a.count)
+        count_direct(a.count, n_direct * TD);
     __shared__ double red[4][64];
-    __shared__ double bred[4];
     wave_reduce_halving<TD>(accd, lane);
     red[wave][lane] = accd[0];
-    if (do_base) {
-        double bv = wave_sum(bs + bc);
-        if (lane == 0)
-            bred[wave] = bv;
-    }
     __syncthreads();
     constexpr int SHIFT = 6 - Log2<TD>::value;
     if (threadIdx.x < TD) {
@@ -616,9 +737,6 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
                dtile * TD + threadIdx.x] = v;
     }
-    if (do_base && threadIdx.x == 0)
-        a.base_part[(size_t)blockIdx.z * a.n_chunks + chunk] =
-            ((bred[0] + bred[1]) + bred[2]) + bred[3];
 }
 
 hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G,
@@ -701,12 +819,25 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     __shared__ double sh_base;
     __shared__ double shd[4];
     __shared__ int shi[4];
+    __shared__ double sh_mom[kMomentSlots];   // C0, c_n M_n
     if (threadIdx.x == 0) {
         double s = 0.0, c = 0.0;
         const double *bp = r.base_part + row * r.n_chunks;
         for (int ch = 0; ch < r.n_chunks; ++ch)
             neumaier(s, c, bp[ch]);
         sh_base = s + c;
+    }
+    if (threadIdx.x < kMomentSlots) {
+        // fixed-order chunk sum of one moment (positive terms)
+        double s = 0.0, c = 0.0;
+        const double *mp = r.mpart + row * r.n_chunks * kMomentSlots + threadIdx.x;
+        for (int ch = 0; ch < r.n_chunks; ++ch)
+            neumaier(s, c, mp[(size_t)ch * kMomentSlots]);
+        // binomial(1/2, n) by its recurrence, c_1 = 1/2
+        double cn = 1.0;
+        for (int n = 0; n < (int)threadIdx.x; ++n)
+            cn = cn * (0.5 - n) / (n + 1);
+        sh_mom[threadIdx.x] = threadIdx.x == 0 ? (s + c) : cn * (s + c);
     }
     __syncthreads();
     const double base = sh_base;
@@ -722,7 +853,13 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
         for (int ch = 0; ch < r.n_chunks; ++ch)
             neumaier(s, c, pp[(size_t)ch * r.n_delta_pad + id]);
         const double D = r.delta[id];
-        const double om = (base - (s + c)) + r.n_k * (-2.0 * D * D / V) + qpoison;
+        // series part: C0 + sum_n c_n M_n (Delta^2)^n by Horner
+        const double x = D * D;
+        double ser = sh_mom[kSeriesTerms];
+        for (int n = kSeriesTerms - 1; n >= 1; --n)
+            ser = fma(ser, x, sh_mom[n]);
+        ser = fma(ser, x, sh_mom[0]);
+        const double om = (base - ((s + c) + ser)) + r.n_k * (-2.0 * D * D / V) + qpoison;
         out[id] = om;
         best = nan_min(best, om);
     }
@@ -828,23 +965,28 @@ __device__ __forceinline__ void band_grad(const Hop &t, double eps, double cx,
     }
 }
 
-__device__ __forceinline__ double fermi(double E, double T, double invT)
-{
-    if (T == 0.0)
-        return E < 0.0 ? 1.0 : (E > 0.0 ? 0.0 : 0.5);
-    if (E > 0.0) {
-        double e = exp(-E * invT);
-        return e / (1.0 + e);
-    }
-    return 1.0 / (1.0 + exp(E * invT));
-}
+// Fermi function f(E) = 1/(1 + exp(E/T)) and -T ln(1 + exp(-E/T)) of one
+// quasiparticle branch.  Beyond |E| >= 36 T both take their T -> 0 values
+// (changes below 2.4e-16 relative); T = 0 gives the step (1/2 at E = 0).
+struct Thermal {
+    double f, sp;
+};
 
-__device__ __forceinline__ double softplus_neg(double E, double T, double invT)
+__device__ __forceinline__ Thermal thermal_branch(double E, double T, double invT,
+                                                  double cutT)
 {
-    double lo = fmin(E, 0.0);
-    if (T == 0.0)
-        return lo;
-    return lo - T * log1p(exp(-fabs(E) * invT));
+    const double aE = fabs(E);
+    Thermal r;
+    const double lo = fmin(E, 0.0);
+    if (aE < cutT) {
+        const double e = exp_nonpos(-aE * invT);
+        r.f = (E > 0.0 ? e : 1.0) * rcp_nr(1.0 + e);
+        r.sp = lo - T * log1p_small(e);
+    } else {
+        r.f = E < 0.0 ? 1.0 : (E > 0.0 ? 0.0 : 0.5);
+        r.sp = lo;
+    }
+    return r;
 }
 
 // Per k: the term of Eq. (5) and its derivatives with respect to Delta,
@@ -862,6 +1004,7 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
     const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
+    const double cutT = kCutFp64 * T;
     const double D = a.delta[io];
     double sqx, cqx, sqy, cqy;
     sincos(a.q[2 * io], &sqx, &cqx);
@@ -889,15 +1032,16 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
             double s = 0.5 * (up + dn), d = 0.5 * (up - dn);
             double eta = cx * cy;
             double gap = D * eta;
-            double R = sqrt(fma(s, s, gap * gap));
+            double R = sqrt_rn(fma(s, s, gap * gap));
             double Ep = d + R, Em = d - R;
-            double fp = fermi(Ep, T, invT), fm = fermi(Em, T, invT);
-            double sr = R > 0.0 ? s / R : 0.0;
-            double dr = R > 0.0 ? gap * eta / R : 0.0;
+            const Thermal tp = thermal_branch(Ep, T, invT, cutT);
+            const Thermal tm = thermal_branch(Em, T, invT, cutT);
+            const double fp = tp.f, fm = tm.f;
+            const double rR = R > 0.0 ? rcp_nr(R) : 0.0;
+            double sr = s * rR;
+            double dr = gap * eta * rR;
             double w = 0.5 * fp * (sr - 1.0) - 0.5 * fm * (sr + 1.0);
-            neumaier(s_[0], c_[0],
-                     (softplus_neg(Ep, T, invT) + softplus_neg(Em, T, invT)) +
-                         (Ek - mu_dn));
+            neumaier(s_[0], c_[0], (tp.sp + tm.sp) + (Ek - mu_dn));
             neumaier(s_[1], c_[1], dr * (fp - fm));
             neumaier(s_[2], c_[2], bx * w);
             neumaier(s_[3], c_[3], by * w);

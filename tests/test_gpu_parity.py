@@ -127,6 +127,22 @@ def test_mirror_folded_rows_match_oracle(Lx, Ly):
         say(f"fold {Lx}x{Ly} prec {prec}: worst rel {worst:.3e}")
 
 
+@pytest.mark.parametrize("dmax,T", [(0.01, 0.002), (0.6, 0.0), (2.0, 0.004), (0.3, 0.08)])
+def test_series_and_direct_split_against_oracle(dmax, T):
+    # The Delta-dependent term goes through the Delta^2 series where
+    # Delta_max^2 eta^2 <= 0.3 s^2 and |s| - |d| >= 36 T, else through the
+    # per-Delta loop: a tiny Delta range puts almost every momentum on the
+    # series, a wide one almost none, T = 0 moves the thermal boundary to 0.
+    pts = [(0.08, T, 48, 40), (-0.05, T, 33, 64)]
+    delta = np.linspace(0.0, dmax, 37)
+    q = np.array([[0.0, 0.0], [0.2, 0.0], [0.1, 0.15]])
+    for prec, rel, floor in ((OMEGA_FP64, 1e-12, 1e-13), (OMEGA_FP32_COMP, 1e-7, 1e-8)):
+        idx, omin, rows, om = run_argmin(pts, delta, q, 3, prec)
+        ref = oracle.omega_grid(M, pts, delta, q, 3)
+        worst = assert_close(om, ref, pts, rel=rel, floor=floor)
+        say(f"series split dmax={dmax} T={T} prec={prec}: worst rel {worst:.3e}")
+
+
 def test_deterministic_bitwise():
     c = W.config("small")
     a = run_argmin(c["pts"], c["delta"], c["q"], c["bands"])[3]
