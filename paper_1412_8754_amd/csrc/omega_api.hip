@@ -95,7 +95,7 @@ struct Tiles {
     int TX, TY, n_tiles, n_chunks;
 };
 
-// Sweep chunking of one point: 64 tiles per chunk, fewer while a single
+// Sweep chunking of one point: 256 tiles per chunk, fewer while a single
 // point would give less than kMinWorkgroups workgroups.
 Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
 {
@@ -103,7 +103,7 @@ Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
     r.TX = (Lx + kTileEdge - 1) / kTileEdge;
     r.TY = (Ly + kTileEdge - 1) / kTileEdge;
     r.n_tiles = r.TX * r.TY;
-    int tpw = 64;
+    int tpw = 256;
     while (tpw > 4 &&
            (long long)((r.n_tiles + tpw - 1) / tpw) * other_blocks < kMinWorkgroups)
         tpw /= 2;
@@ -164,7 +164,8 @@ struct GridPlan {
     std::vector<Group> groups;
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
-    size_t off_d2, off_trig, off_table, off_part, off_base, off_mom, off_mask, sweep_bytes;
+    size_t off_d2, off_qtrig, off_trig, off_table, off_part, off_base, off_mom, off_mask,
+        sweep_bytes;
 };
 
 GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb)
@@ -194,7 +195,8 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         mask = std::max(mask, sizeof(unsigned long long) * p.nbq * t.n_tiles * G);
     }
     p.off_d2 = 0;
-    p.off_trig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 1));
+    p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 1));
+    p.off_trig = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.off_base = p.off_part + align_up(part);
@@ -214,7 +216,7 @@ struct GradPlan {
     std::vector<Group> groups;
     std::vector<Tiles> tiles;
     std::vector<int> batch;
-    size_t off_trig, off_table, off_part, bytes;
+    size_t off_qtrig, off_trig, off_table, off_part, bytes;
 };
 
 GradPlan plan_grad(const omega_point *pts, int n_pts, int nb)
@@ -232,8 +234,9 @@ GradPlan plan_grad(const omega_point *pts, int n_pts, int nb)
         table = std::max(table, sizeof(PointRec) * (size_t)G);
         part = std::max(part, per_point * G);
     }
-    p.off_trig = 0;
-    p.off_table = align_up(trig);
+    p.off_qtrig = 0;
+    p.off_trig = align_up(sizeof(double) * 4 * (size_t)n_pts * nb);
+    p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.bytes = p.off_part + align_up(part);
     return p;
@@ -287,6 +290,7 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     const int nb = slot_bands(bands, list);
     const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb);
     double *d2 = (double *)(ws + P.off_d2);
+    double *qtrig = (double *)(ws + P.off_qtrig);
     double *trig = (double *)(ws + P.off_trig);
     PointRec *table = (PointRec *)(ws + P.off_table);
     double *part = (double *)(ws + P.off_part);
@@ -294,6 +298,8 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     double *mom = (double *)(ws + P.off_mom);
     unsigned long long *mask = (unsigned long long *)(ws + P.off_mask);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
+        return OMEGA_E_HIP;
+    if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
         return OMEGA_E_HIP;
 
     SweepArgs a;
@@ -306,6 +312,7 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     a.n_delta_pad = P.n_delta_pad;
     a.d2 = d2;
     a.q = q;
+    a.qtrig = qtrig;
     a.trig = trig;
     a.part = part;
     a.base_part = base;
@@ -458,9 +465,12 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
         return OMEGA_E_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)ws_dev;
+    double *qtrig = (double *)(ws + P.off_qtrig);
     double *trig = (double *)(ws + P.off_trig);
     PointRec *table = (PointRec *)(ws + P.off_table);
     double *part = (double *)(ws + P.off_part);
+    if (launch_qtrig(q_dev, n_pts * nb, qtrig, s) != hipSuccess)
+        return OMEGA_E_HIP;
 
     GradArgs a;
     a.hop = make_hop(model);
@@ -470,6 +480,7 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
     a.nb = nb;
     a.delta = delta_dev;
     a.q = q_dev;
+    a.qtrig = qtrig;
     a.trig = trig;
     a.part = part;
     GradFinishArgs f;

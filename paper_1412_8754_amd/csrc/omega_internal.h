@@ -71,6 +71,7 @@ struct SweepArgs {
     const double *d2;    // [n_delta_pad + 1] Delta^2 (padding repeats the last),
                          // then max Delta^2 over the grid
     const double *q;     // [n_q][2]
+    const double *qtrig; // [n_q][4] cos qx, sin qx, cos qy, sin qy
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
@@ -114,6 +115,7 @@ struct GradArgs {
     int Lx, Ly, TX, TY, n_tiles, n_chunks, nb;
     const double *delta;   // [n_pts][nb] (all points of the call)
     const double *q;       // [n_pts][nb][2]
+    const double *qtrig;   // [n_pts][nb][4] cos/sin of q
     const double *trig;
     double *part;          // [G][nb][n_chunks][5]
 };
@@ -130,6 +132,7 @@ struct GradFinishArgs {
 
 hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s);
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
+hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s);
 hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s);

@@ -129,6 +129,73 @@ __device__ __attribute__((noinline)) double thermal_log(double ax, double y,
     return log1p_small(u1 + u2 + u1 * u2);
 }
 
+// Tables of the inline thermal term, filled per workgroup in LDS.
+struct ThermalTables {
+    double e[64];    // 2^(-k/64)
+    double ic[64];   // 1 / (1 + j/64)
+    double lc[64];   // ln(1 + j/64)
+};
+
+__device__ __forceinline__ void fill_thermal_tables(ThermalTables &t)
+{
+    if (threadIdx.x < 64) {
+        const int k = threadIdx.x;
+        t.e[k] = exp2(-k / 64.0);
+        const double c = 1.0 + k / 64.0;
+        t.ic[k] = 1.0 / c;
+        t.lc[k] = log(c);
+    }
+}
+
+// e^-a for 0 <= a < 2^12 ln2/64: with N = rint(64 a / ln2) = 64 m + k and
+// a = N ln2/64 + r (two-part ln2/64, exact N * head), e^-a = 2^-m 2^-k/64 e^-r,
+// |r| <= ln2/128, series to r^5 (truncation 4e-17).  Measured max relative
+// error against the device libm: 4.4e-16.
+__device__ __forceinline__ double exp_neg_tab(double a, const ThermalTables &t)
+{
+    const double kInvL = 92.33248261689366;          // 64 / ln2
+    const double kLh = 0.010830424696251839;         // ln2/64, 41 significant bits
+    const double kLl = -2.693663207127318e-15;       // ln2/64 - kLh
+    const double N = rint(a * kInvL);
+    const int n = (int)N;
+    double r = fma(-N, kLh, a);
+    r = fma(-N, kLl, r);
+    double p = -1.0 / 120.0;
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, -1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, -1.0);
+    p = fma(p, r, 1.0);
+    return __builtin_amdgcn_ldexp(t.e[n & 63] * p, -(n >> 6));
+}
+
+// ln(1 + u) for 0 <= u <= 1: w = 1 + u, c = 1 + j/64 <= w with j = [64 u],
+// rho = (w - c)/c in [0, 1/64), ln w = ln c + series in rho to rho^8
+// (truncation 5e-16 of rho).  The rounding of 1 + u bounds the absolute
+// error by 2.2e-16 (measured).
+__device__ __forceinline__ double log1p_tab(double u, const ThermalTables &t)
+{
+    const double w = 1.0 + u;
+    int j = (int)(u * 64.0);
+    j = j > 63 ? 63 : j;
+    const double rho = (w - (1.0 + j * (1.0 / 64.0))) * t.ic[j];
+    double p = -1.0 / 8.0;
+    p = fma(p, rho, 1.0 / 7.0);
+    p = fma(p, rho, -1.0 / 6.0);
+    p = fma(p, rho, 1.0 / 5.0);
+    p = fma(p, rho, -1.0 / 4.0);
+    p = fma(p, rho, 1.0 / 3.0);
+    p = fma(p, rho, -0.5);
+    p = fma(p, rho, 1.0);
+    return fma(p, rho, t.lc[j]);
+}
+
+// ln(1 + e^-z) for the rare second branch (R + |d| < 36 T), out of line.
+__device__ __attribute__((noinline)) double log1p_exp_neg(double z)
+{
+    return log1p_small(exp_nonpos(-z));
+}
+
 // Band energy of App. A, (A.4), from cos/sin of the two momentum components.
 __device__ __forceinline__ double band_energy(const Hop &t, double eps,
                                               double cx, double sx, double cy,
@@ -270,6 +337,28 @@ hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
     return hipGetLastError();
 }
 
+// cos and sin of both components of n pair momenta, [n][4] =
+// (cos qx, sin qx, cos qy, sin qy), once per call.
+__global__ void qtrig_kernel(const double *q, int n, double *out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) {
+        double s, c;
+        sincos(q[2 * t], &s, &c);
+        out[4 * t] = c;
+        out[4 * t + 1] = s;
+        sincos(q[2 * t + 1], &s, &c);
+        out[4 * t + 2] = c;
+        out[4 * t + 3] = s;
+    }
+}
+
+hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(qtrig_kernel, dim3((n + 255) / 256), dim3(256), 0, s, q, n, out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ sweep
 
 // Per (k, Q) invariants of one band.
@@ -391,9 +480,8 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
     const double cutT = kCutFp64 * T;
     const double dmax2 = a.d2[a.n_delta_pad];
-    double sqx, cqx, sqy, cqy;
-    sincos(a.q[2 * iq], &sqx, &cqx);
-    sincos(qy, &sqy, &cqy);
+    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
     const double *cxt = a.trig;
     const double *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx;
@@ -472,7 +560,8 @@ hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s)
 // Per-Delta FP64 sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.
 template <int TD>
-__global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void sweep_f64_kernel(const SweepArgs a)
 {
     const int chunk = blockIdx.x;
     const int dtile = blockIdx.y;
@@ -493,15 +582,16 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
     const double cutT = kCutFp64 * T;
     const unsigned long long *mask = a.mask + (size_t)blockIdx.z * a.n_tiles;
 
-    double sqx, cqx, sqy, cqy;
-    sincos(a.q[2 * iq], &sqx, &cqx);
-    sincos(qy, &sqy, &cqy);
+    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
 
     // Delta^2 of this tile, read from LDS inside the loop (one extra slot for
-    // the look-ahead read of the last iteration)
+    // the look-ahead read of the last iteration), and the thermal tables
     __shared__ double d2s[TD + 1];
+    __shared__ ThermalTables tabs;
     if (threadIdx.x <= TD)
         d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+    fill_thermal_tables(tabs);
     __syncthreads();
 
     const double *cxt = a.trig;
@@ -546,8 +636,14 @@ __global__ __launch_bounds__(kBlock) void sweep_f64_kernel(const SweepArgs a)
                 const double x = R - r.m;
                 acc[t] = fma(w, fmax(x, 0.0), acc[t]);
                 const double ax = fabs(x);
-                if (ax < cutT)
-                    acc[t] = fma(wT, thermal_log(ax, R + r.m, invT, cutT), acc[t]);
+                if (ax < cutT) {
+                    // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
+                    double L = log1p_tab(exp_neg_tab(ax * invT, tabs), tabs);
+                    const double y = R + r.m;
+                    if (y < cutT)
+                        L += log1p_exp_neg(y * invT);
+                    acc[t] = fma(wT, L, acc[t]);
+                }
                 dcur = dnext;
             }
         }
@@ -651,9 +747,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
     const unsigned long long *mask = a.mask + (size_t)blockIdx.z * a.n_tiles;
 
-    double sqx, cqx, sqy, cqy;
-    sincos(a.q[2 * iq], &sqx, &cqx);
-    sincos(qy, &sqy, &cqy);
+    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
 
     // Delta^2 as an unevaluated FP32 pair hi + lo: rounding Delta^2 to one
     // float would shift every momentum's term at that Delta the same way
@@ -1006,9 +1101,8 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
     const double cutT = kCutFp64 * T;
     const double D = a.delta[io];
-    double sqx, cqx, sqy, cqy;
-    sincos(a.q[2 * io], &sqx, &cqx);
-    sincos(a.q[2 * io + 1], &sqy, &cqy);
+    const double cqx = a.qtrig[4 * io], sqx = a.qtrig[4 * io + 1];
+    const double cqy = a.qtrig[4 * io + 2], sqy = a.qtrig[4 * io + 3];
     const double *cxt = a.trig, *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx, *syt = cyt + a.Ly;
     double s_[5] = {0, 0, 0, 0, 0}, c_[5] = {0, 0, 0, 0, 0};
