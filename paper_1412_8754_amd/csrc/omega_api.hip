@@ -164,8 +164,8 @@ struct GridPlan {
     std::vector<Group> groups;
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
-    size_t off_d2, off_qtrig, off_trig, off_table, off_part, off_base, off_mom, off_mask,
-        sweep_bytes;
+    size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
+        off_mask, sweep_bytes;
 };
 
 GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb)
@@ -196,7 +196,8 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     }
     p.off_d2 = 0;
     p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 1));
-    p.off_trig = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
+    p.off_gtab = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
+    p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabN);
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.off_base = p.off_part + align_up(part);
@@ -291,6 +292,7 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb);
     double *d2 = (double *)(ws + P.off_d2);
     double *qtrig = (double *)(ws + P.off_qtrig);
+    double2 *gtab = (double2 *)(ws + P.off_gtab);
     double *trig = (double *)(ws + P.off_trig);
     PointRec *table = (PointRec *)(ws + P.off_table);
     double *part = (double *)(ws + P.off_part);
@@ -300,6 +302,8 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
         return OMEGA_E_HIP;
     if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
+        return OMEGA_E_HIP;
+    if (precision == OMEGA_FP64 && launch_gtable(gtab, s) != hipSuccess)
         return OMEGA_E_HIP;
 
     SweepArgs a;
@@ -314,6 +318,7 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     a.q = q;
     a.qtrig = qtrig;
     a.trig = trig;
+    a.gtab = gtab;
     a.part = part;
     a.base_part = base;
     a.mpart = mom;

@@ -24,6 +24,12 @@ constexpr double kCutFp64 = 36.0;
 // the terms it would be added to.
 constexpr float kCutFp32 = 17.0f;
 
+// Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 36: entry N
+// holds (G(a0), 1/(1 + e^a0)) at a0 = N / kGStep.
+constexpr int kGStep = 32;
+constexpr int kGTabN = 36 * kGStep + 1;
+static_assert(kCutFp64 == 36.0, "the thermal table ends at the FP64 cut");
+
 // Series path of the sweep.  Where A0 = |s| - |d| >= 36 T (the term is
 // R - |d| >= 36 T for every Delta: cold, positive, no thermal part) and
 // Delta_max^2 eta^2 <= kSeriesRho s^2, the Delta-dependent term
@@ -73,6 +79,7 @@ struct SweepArgs {
     const double *q;     // [n_q][2]
     const double *qtrig; // [n_q][4] cos qx, sin qx, cos qy, sin qy
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
+    const double2 *gtab; // [kGTabN] thermal table (FP64 sweep)
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments
@@ -133,6 +140,7 @@ struct GradFinishArgs {
 hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s);
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
 hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
+hipError_t launch_gtable(double2 *gtab, hipStream_t s);
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s);
 hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s);

@@ -129,71 +129,34 @@ __device__ __attribute__((noinline)) double thermal_log(double ax, double y,
     return log1p_small(u1 + u2 + u1 * u2);
 }
 
-// Tables of the inline thermal term, filled per workgroup in LDS.
-struct ThermalTables {
-    double e[64];    // 2^(-k/64)
-    double ic[64];   // 1 / (1 + j/64)
-    double lc[64];   // ln(1 + j/64)
-};
-
-__device__ __forceinline__ void fill_thermal_tables(ThermalTables &t)
+// G(a) = ln(1 + e^-a) for 0 <= a <= 36 (the thermal term over T) from the
+// table at a0 = N / kGStep, |a - a0| <= 1/64.  With sigma = 1/(1 + e^a0),
+// p = sigma (1 - sigma) and b = 1 - 2 sigma, the derivatives of G at a0 are
+//   G' = -sigma, G'' = p, G''' = -p b, G'''' = p (1 - 6p),
+//   G^(5) = -p b (1 - 12p), G^(6) = p (1 - 30p + 120p^2)
+// (from sigma' = -p, p' = -p b, b' = 2p), and the Taylor polynomial of degree
+// 6 leaves a truncation below 8e-17 of G.  Checked against a long-double
+// reference over [0, 36]: 4.4e-16 relative at most.
+__device__ __forceinline__ double log1p_exp_tab(double a, const double2 *gt)
 {
-    if (threadIdx.x < 64) {
-        const int k = threadIdx.x;
-        t.e[k] = exp2(-k / 64.0);
-        const double c = 1.0 + k / 64.0;
-        t.ic[k] = 1.0 / c;
-        t.lc[k] = log(c);
-    }
-}
-
-// e^-a for 0 <= a < 2^12 ln2/64: with N = rint(64 a / ln2) = 64 m + k and
-// a = N ln2/64 + r (two-part ln2/64, exact N * head), e^-a = 2^-m 2^-k/64 e^-r,
-// |r| <= ln2/128, series to r^5 (truncation 4e-17).  Measured max relative
-// error against the device libm: 4.4e-16.
-__device__ __forceinline__ double exp_neg_tab(double a, const ThermalTables &t)
-{
-    const double kInvL = 92.33248261689366;          // 64 / ln2
-    const double kLh = 0.010830424696251839;         // ln2/64, 41 significant bits
-    const double kLl = -2.693663207127318e-15;       // ln2/64 - kLh
-    const double N = rint(a * kInvL);
-    const int n = (int)N;
-    double r = fma(-N, kLh, a);
-    r = fma(-N, kLl, r);
-    double p = -1.0 / 120.0;
-    p = fma(p, r, 1.0 / 24.0);
-    p = fma(p, r, -1.0 / 6.0);
-    p = fma(p, r, 0.5);
-    p = fma(p, r, -1.0);
-    p = fma(p, r, 1.0);
-    return __builtin_amdgcn_ldexp(t.e[n & 63] * p, -(n >> 6));
-}
-
-// ln(1 + u) for 0 <= u <= 1: w = 1 + u, c = 1 + j/64 <= w with j = [64 u],
-// rho = (w - c)/c in [0, 1/64), ln w = ln c + series in rho to rho^8
-// (truncation 5e-16 of rho).  The rounding of 1 + u bounds the absolute
-// error by 2.2e-16 (measured).
-__device__ __forceinline__ double log1p_tab(double u, const ThermalTables &t)
-{
-    const double w = 1.0 + u;
-    int j = (int)(u * 64.0);
-    j = j > 63 ? 63 : j;
-    const double rho = (w - (1.0 + j * (1.0 / 64.0))) * t.ic[j];
-    double p = -1.0 / 8.0;
-    p = fma(p, rho, 1.0 / 7.0);
-    p = fma(p, rho, -1.0 / 6.0);
-    p = fma(p, rho, 1.0 / 5.0);
-    p = fma(p, rho, -1.0 / 4.0);
-    p = fma(p, rho, 1.0 / 3.0);
-    p = fma(p, rho, -0.5);
-    p = fma(p, rho, 1.0);
-    return fma(p, rho, t.lc[j]);
-}
-
-// ln(1 + e^-z) for the rare second branch (R + |d| < 36 T), out of line.
-__device__ __attribute__((noinline)) double log1p_exp_neg(double z)
-{
-    return log1p_small(exp_nonpos(-z));
+    const double N = rint(a * kGStep);
+    const double r = fma(-N, 1.0 / kGStep, a);
+    int n = (int)N;
+    n = n < kGTabN - 1 ? n : kGTabN - 1;
+    const double2 c = gt[n];
+    const double s = c.y;
+    const double p = fma(-s, s, s);
+    const double b = fma(-2.0, s, 1.0);
+    const double pb = p * b;
+    const double c6 = p * fma(p, fma(p, 1.0 / 6.0, -1.0 / 24.0), 1.0 / 720.0);
+    const double c5 = pb * fma(p, 0.1, -1.0 / 120.0);
+    const double c4 = p * fma(p, -0.25, 1.0 / 24.0);
+    double g = fma(c6, r, c5);
+    g = fma(g, r, c4);
+    g = fma(g, r, pb * (-1.0 / 6.0));
+    g = fma(g, r, 0.5 * p);
+    g = fma(g, r, -s);
+    return fma(g, r, c.x);
 }
 
 // Band energy of App. A, (A.4), from cos/sin of the two momentum components.
@@ -362,6 +325,23 @@ hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s)
 // ------------------------------------------------------------------ sweep
 
 // Per (k, Q) invariants of one band.
+// Thermal table: entry N = (ln(1 + e^-a0), 1/(1 + e^a0)), a0 = N / kGStep.
+__global__ void gtable_kernel(double2 *gt)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < kGTabN) {
+        const double e = exp(-n * (1.0 / kGStep));
+        gt[n] = make_double2(log1p(e), e / (1.0 + e));
+    }
+}
+
+hipError_t launch_gtable(double2 *gtab, hipStream_t s)
+{
+    hipLaunchKernelGGL(gtable_kernel, dim3((kGTabN + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                       gtab);
+    return hipGetLastError();
+}
+
 struct KQ {
     double s2;     // ((a + b)/2)^2
     double as;     // |s|
@@ -588,10 +568,11 @@ void sweep_f64_kernel(const SweepArgs a)
     // Delta^2 of this tile, read from LDS inside the loop (one extra slot for
     // the look-ahead read of the last iteration), and the thermal tables
     __shared__ double d2s[TD + 1];
-    __shared__ ThermalTables tabs;
+    __shared__ double2 gt[kGTabN];
     if (threadIdx.x <= TD)
         d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
-    fill_thermal_tables(tabs);
+    for (int n = threadIdx.x; n < kGTabN; n += kBlock)
+        gt[n] = a.gtab[n];
     __syncthreads();
 
     const double *cxt = a.trig;
@@ -638,10 +619,10 @@ void sweep_f64_kernel(const SweepArgs a)
                 const double ax = fabs(x);
                 if (ax < cutT) {
                     // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
-                    double L = log1p_tab(exp_neg_tab(ax * invT, tabs), tabs);
+                    double L = log1p_exp_tab(ax * invT, gt);
                     const double y = R + r.m;
                     if (y < cutT)
-                        L += log1p_exp_neg(y * invT);
+                        L += log1p_exp_tab(y * invT, gt);
                     acc[t] = fma(wT, L, acc[t]);
                 }
                 dcur = dnext;
