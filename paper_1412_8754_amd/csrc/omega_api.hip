@@ -195,7 +195,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         mask = std::max(mask, sizeof(unsigned long long) * p.nbq * t.n_tiles * G);
     }
     p.off_d2 = 0;
-    p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 1));
+    p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 2));
     p.off_gtab = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
     p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabN);
     p.off_table = p.off_trig + align_up(trig);
@@ -329,6 +329,7 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     r.part = part;
     r.base_part = base;
     r.mpart = mom;
+    r.d2c = d2 + P.n_delta_pad;
     r.pts = table;
     r.delta = delta;
     r.q = q;

@@ -30,17 +30,18 @@ constexpr int kGStep = 32;
 constexpr int kGTabN = 36 * kGStep + 1;
 static_assert(kCutFp64 == 36.0, "the thermal table ends at the FP64 cut");
 
-// Series path of the sweep.  Where A0 = |s| - |d| >= 36 T (the term is
-// R - |d| >= 36 T for every Delta: cold, positive, no thermal part) and
-// Delta_max^2 eta^2 <= kSeriesRho s^2, the Delta-dependent term
-//   R - |d| = (|s| - |d|) + |s| sum_{n>=1} c_n (Delta^2 eta^2 / s^2)^n,
-// c_n = binomial(1/2, n), is summed over k through the moments
-// C0 = sum (|s| - |d|) and M_n = sum |s| (eta^2/s^2)^n, n = 1..kSeriesTerms.
-// The series alternates with decreasing terms, so the truncation is below
-// |c_31| 0.3^31 = 1e-19 of |s| per term.
-constexpr double kSeriesRho = 0.3;
-constexpr int kSeriesTerms = 30;
-constexpr int kMomentSlots = 32;   // C0, M_1..M_30, one unused slot
+// Series path of the sweep.  With x = Delta^2, the centre x0 and half-width
+// hw of the call's Delta^2 range, R0 = sqrt(s^2 + x0 eta^2) and
+// z = (x - x0) eta^2 / R0^2, the Delta-dependent term is
+//   R - |d| = (R0 - |d|) + R0 sum_{n>=1} c_n z^n,  c_n = binomial(1/2, n).
+// Where A0 = |s| - |d| >= 36 T (R - |d| >= 36 T for every Delta: cold,
+// positive, no thermal part) and hw eta^2 <= kSeriesRho R0^2 (so |z| <= 1/3),
+// it is summed over k through the moments C0 = sum (R0 - |d|) and
+// M_n = sum R0 (eta^2/R0^2)^n, n = 1..kSeriesTerms.  Since |c_n| decreases,
+// the truncation is below |c_32| 3^-32 / (1 - 1/3) = 1.3e-18 of R0 per term.
+constexpr double kSeriesRho = 1.0 / 3.0;
+constexpr int kSeriesTerms = 31;
+constexpr int kMomentSlots = 32;   // C0, M_1..M_31
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
@@ -74,8 +75,8 @@ struct SweepArgs {
     int n_q;
     int nbq;             // bands * n_q
     int n_delta_pad;     // n_delta rounded up to the Delta tile
-    const double *d2;    // [n_delta_pad + 1] Delta^2 (padding repeats the last),
-                         // then max Delta^2 over the grid
+    const double *d2;    // [n_delta_pad + 2] Delta^2 (padding repeats the last),
+                         // then centre and half-width of the Delta^2 range
     const double *q;     // [n_q][2]
     const double *qtrig; // [n_q][4] cos qx, sin qx, cos qy, sin qy
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
@@ -93,6 +94,7 @@ struct RowArgs {
     const double *part;
     const double *base_part;
     const double *mpart;   // [G*nbq][n_chunks][kMomentSlots] series moments
+    const double *d2c;     // centre of the Delta^2 range (series variable x - x0)
     const PointRec *pts;   // [G]
     const double *delta;   // [n_delta]
     const double *q;       // [n_q][2]

@@ -276,19 +276,31 @@ __global__ __launch_bounds__(kBlock) void delta2_kernel(const double *delta, int
         d2[t] = D * D;
     }
     if (blockIdx.x == 0) {
-        __shared__ double sh[kBlock];
-        double mx = 0.0;
-        for (int i = threadIdx.x; i < n_delta; i += kBlock)
-            mx = fmax(mx, delta[i] * delta[i]);
-        sh[threadIdx.x] = mx;
+        // centre and half-width of [min Delta^2, max Delta^2] (NaN ignored;
+        // a NaN Delta still poisons its own output through Delta^2)
+        __shared__ double sh[2][kBlock];
+        double mx = 0.0, mn = __builtin_inf();
+        for (int i = threadIdx.x; i < n_delta; i += kBlock) {
+            const double x = delta[i] * delta[i];
+            mx = fmax(mx, x);
+            mn = fmin(mn, x);
+        }
+        sh[0][threadIdx.x] = mx;
+        sh[1][threadIdx.x] = mn;
         __syncthreads();
         for (int w = kBlock / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w)
-                sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+            if (threadIdx.x < w) {
+                sh[0][threadIdx.x] = fmax(sh[0][threadIdx.x], sh[0][threadIdx.x + w]);
+                sh[1][threadIdx.x] = fmin(sh[1][threadIdx.x], sh[1][threadIdx.x + w]);
+            }
             __syncthreads();
         }
-        if (threadIdx.x == 0)
-            d2[n_delta_pad] = sh[0];
+        if (threadIdx.x == 0) {
+            const double hi = sh[0][0];
+            const double lo = fmin(sh[1][0], hi);
+            d2[n_delta_pad] = 0.5 * (lo + hi);
+            d2[n_delta_pad + 1] = 0.5 * (hi - lo);
+        }
     }
 }
 
@@ -385,11 +397,12 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
 }
 
 // Whether the (k, Q) term's Delta dependence goes through the Delta^2 series
-// (see kSeriesRho) rather than the per-Delta loop.  Decided once, in
-// series_kernel, and handed to the sweeps as a per-tile lane mask.
-__device__ __forceinline__ bool series_term(const KQ &r, double dmax2, double cutT)
+// (see kSeriesRho) rather than the per-Delta loop; R02 = s^2 + x0 eta^2.
+// Decided once, in series_kernel, and handed to the sweeps as a per-tile lane
+// mask.
+__device__ __forceinline__ bool series_term(const KQ &r, double R02, double hw, double cutT)
 {
-    return (r.as - r.m) >= cutT && dmax2 * r.eta2 <= kSeriesRho * r.s2;
+    return (r.as - r.m) >= cutT && hw * r.eta2 <= kSeriesRho * R02;
 }
 
 // Adds a workgroup's count of directly evaluated (k, Delta) terms (optional
@@ -437,8 +450,9 @@ __device__ __forceinline__ double mirror_weight(const KRange &k, int j, int Ly)
 // both precisions:
 //   - the Delta-independent part of the term, Neumaier-summed (for the FP32
 //     sweep minus P(0), the full Delta-dependent part at Delta = 0);
-//   - the Delta^2 series moments C0 = sum w (|s| - |d|) (FP64 only; in FP32
-//     it is part of P(0)) and M_n = sum w |s| (eta^2/s^2)^n;
+//   - the Delta^2 series moments C0 = sum w (R0 - |d|) (for the FP32 sweep
+//     sum w (R0 - |s|), as |s| - |d| is part of P(0)) and
+//     M_n = sum w R0 (eta^2/R0^2)^n;
 //   - for every 8 x 8 tile, the ballot of lanes the per-Delta sweep must
 //     evaluate directly.
 // Grid (chunk, band*Q + nbq*g).
@@ -459,7 +473,8 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
     const double cutT = kCutFp64 * T;
-    const double dmax2 = a.d2[a.n_delta_pad];
+    const double x0 = a.d2[a.n_delta_pad];
+    const double hw = a.d2[a.n_delta_pad + 1];
     const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
     const double *cxt = a.trig;
@@ -492,12 +507,16 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
                 base -= P0;
             }
             neumaier(bs, bc, w * base);
-            if (series_term(r, dmax2, cutT)) {
-                if (fp64)
-                    mom[0] = fma(w, A0, mom[0]);
-                // s^2 = 0 here only with eta^2 = 0 or Delta_max = 0: the powers vanish
-                const double ratio = r.s2 > 0.0 ? r.eta2 * rcp_nr(r.s2) : 0.0;
-                double t = w * r.as;
+            const double R02 = fma(x0, r.eta2, r.s2);
+            if (series_term(r, R02, hw, cutT)) {
+                const double R0 = sqrt_rn(R02);
+                // R0 - |s| = x0 eta^2 / (R0 + |s|) without cancellation
+                const double c0 = fp64 ? R0 - r.m
+                                       : (R02 > 0.0 ? x0 * r.eta2 * rcp_nr(R0 + r.as) : 0.0);
+                mom[0] = fma(w, c0, mom[0]);
+                // R0 = 0 only with s = 0 and eta^2 x0 = 0: then the powers vanish
+                const double ratio = R02 > 0.0 ? r.eta2 * rcp_nr(R02) : 0.0;
+                double t = w * R0;
 #pragma unroll
                 for (int n = 1; n <= kSeriesTerms; ++n) {
                     t *= ratio;
@@ -909,7 +928,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
         const double *mp = r.mpart + row * r.n_chunks * kMomentSlots + threadIdx.x;
         for (int ch = 0; ch < r.n_chunks; ++ch)
             neumaier(s, c, mp[(size_t)ch * kMomentSlots]);
-        // binomial(1/2, n) by its recurrence, c_1 = 1/2
+        // binomial(1/2, n) by its recurrence, c_1 = 1/2 (c_0 = 1 is in C0)
         double cn = 1.0;
         for (int n = 0; n < (int)threadIdx.x; ++n)
             cn = cn * (0.5 - n) / (n + 1);
@@ -917,6 +936,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     }
     __syncthreads();
     const double base = sh_base;
+    const double x0 = *r.d2c;
     // 0 * q is 0 for finite q and NaN for NaN q: a NaN momentum poisons the row
     const double qpoison = 0.0 * r.q[2 * iq] + 0.0 * r.q[2 * iq + 1];
     const double V = slot ? r.Vs[1] : r.Vs[0];
@@ -929,8 +949,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
         for (int ch = 0; ch < r.n_chunks; ++ch)
             neumaier(s, c, pp[(size_t)ch * r.n_delta_pad + id]);
         const double D = r.delta[id];
-        // series part: C0 + sum_n c_n M_n (Delta^2)^n by Horner
-        const double x = D * D;
+        // series part: C0 + sum_n c_n M_n (Delta^2 - x0)^n by Horner
+        const double x = D * D - x0;
         double ser = sh_mom[kSeriesTerms];
         for (int n = kSeriesTerms - 1; n >= 1; --n)
             ser = fma(ser, x, sh_mom[n]);

@@ -129,8 +129,9 @@ def test_mirror_folded_rows_match_oracle(Lx, Ly):
 
 @pytest.mark.parametrize("dmax,T", [(0.01, 0.002), (0.6, 0.0), (2.0, 0.004), (0.3, 0.08)])
 def test_series_and_direct_split_against_oracle(dmax, T):
-    # The Delta-dependent term goes through the Delta^2 series where
-    # Delta_max^2 eta^2 <= 0.3 s^2 and |s| - |d| >= 36 T, else through the
+    # The Delta-dependent term goes through the series in Delta^2 - x0 (x0 the
+    # centre of the Delta^2 range, half-width hw) where
+    # hw eta^2 <= (s^2 + x0 eta^2)/3 and |s| - |d| >= 36 T, else through the
     # per-Delta loop: a tiny Delta range puts almost every momentum on the
     # series, a wide one almost none, T = 0 moves the thermal boundary to 0.
     pts = [(0.08, T, 48, 40), (-0.05, T, 33, 64)]
@@ -141,6 +142,27 @@ def test_series_and_direct_split_against_oracle(dmax, T):
         ref = oracle.omega_grid(M, pts, delta, q, 3)
         worst = assert_close(om, ref, pts, rel=rel, floor=floor)
         say(f"series split dmax={dmax} T={T} prec={prec}: worst rel {worst:.3e}")
+
+
+@pytest.mark.parametrize("kind", ["offset", "shuffled", "two_values"])
+def test_series_centre_for_offset_and_unsorted_delta(kind):
+    # The series centre comes from the min and max of Delta^2, not from the
+    # first and last entries: a range away from 0, a shuffled grid and a
+    # two-value grid.
+    rng = np.random.default_rng(17)
+    if kind == "offset":
+        delta = np.linspace(0.35, 0.6, 29)
+    elif kind == "shuffled":
+        delta = rng.permutation(np.linspace(0.0, 0.5, 41))
+    else:
+        delta = np.array([0.45, 0.05])
+    pts = [(0.05, 0.003, 40, 36), (0.12, 0.0, 24, 30)]
+    q = np.array([[0.0, 0.0], [2 * np.pi / 40, 0.0], [0.05, 0.1]])
+    for prec, rel, floor in ((OMEGA_FP64, 1e-12, 1e-13), (OMEGA_FP32_COMP, 1e-7, 1e-8)):
+        idx, omin, rows, om = run_argmin(pts, delta, q, 3, prec)
+        ref = oracle.omega_grid(M, pts, delta, q, 3)
+        worst = assert_close(om, ref, pts, rel=rel, floor=floor)
+        say(f"series centre {kind} prec={prec}: worst rel {worst:.3e}")
 
 
 def test_deterministic_bitwise():
