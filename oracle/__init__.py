@@ -84,6 +84,10 @@ def lib():
         L.oracle_gap_root.restype = ctypes.c_double
         L.oracle_gap_root.argtypes = [mp, pp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_omega_row_tab.restype = ctypes.c_int
+        L.oracle_omega_row_tab.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           dp, ctypes.c_int, dp]
         L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L

@@ -185,6 +185,33 @@ static int band_list(int bands, int *list)
 
 /* ------------------------------------------------- Eq. (4)-(5), Alg. 1 */
 
+/* Eq. (4)-(5) summed over the zone for every Delta_i, from the per-k arrays
+ * E_{eps k up}, E_{eps,-k+q,down}, E_{eps k down} and eta(k).  The Delta loop
+ * is the OpenMP-parallel one; the k sum is Neumaier-compensated in the
+ * arrays' (i-major) order. */
+static void eq5_sum(long N, const double *e_up, const double *e_dn,
+                    const double *e_kd, const double *eta, double V, double T,
+                    const double *delta, int n_delta, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int id = 0; id < n_delta; ++id) {
+        const double D = delta[id];
+        nsum acc = {0.0, 0.0};
+        for (long k = 0; k < N; ++k) {
+            double gap = D * eta[k];                      /* Delta_{eps k} */
+            double half_sum = 0.5 * (e_up[k] + e_dn[k]);
+            double half_diff = 0.5 * (e_up[k] - e_dn[k]);
+            double root = sqrt(half_sum * half_sum + gap * gap);
+            double Ep = half_diff + root;                 /* Eq. (4), + */
+            double Em = half_diff - root;                 /* Eq. (4), - */
+            nadd(&acc, softplus_term(Ep, T));
+            nadd(&acc, softplus_term(Em, T));
+            nadd(&acc, e_kd[k]);
+        }
+        out[id] = nval(&acc) + (double)N * (-2.0 * D * D / V);
+    }
+}
+
 /* Omega_eps(Delta_i, q) for every Delta_i, one band, one q, one point.
  * Follows Algorithm 1: the arrays E_{k up} and E_{-k+q down} are generated
  * once for the q, then for each Delta Eq. (4) and Eq. (5) are evaluated over
@@ -216,24 +243,7 @@ static void omega_row(const or_model *m, const or_point *p, int band,
         }
     }
 
-    const double V = m->V[band];
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int id = 0; id < n_delta; ++id) {
-        const double D = delta[id];
-        nsum acc = {0.0, 0.0};
-        for (long k = 0; k < N; ++k) {
-            double gap = D * eta[k];                      /* Delta_{eps k} */
-            double half_sum = 0.5 * (e_up[k] + e_dn[k]);
-            double half_diff = 0.5 * (e_up[k] - e_dn[k]);
-            double root = sqrt(half_sum * half_sum + gap * gap);
-            double Ep = half_diff + root;                 /* Eq. (4), + */
-            double Em = half_diff - root;                 /* Eq. (4), - */
-            nadd(&acc, softplus_term(Ep, T));
-            nadd(&acc, softplus_term(Em, T));
-            nadd(&acc, e_kd[k]);
-        }
-        out[id] = nval(&acc) + (double)N * (-2.0 * D * D / V);
-    }
+    eq5_sum(N, e_up, e_dn, e_kd, eta, m->V[band], T, delta, n_delta, out);
     free(e_up);
     free(e_dn);
     free(e_kd);
@@ -262,6 +272,44 @@ int oracle_omega_grid(const or_model *m, const or_point *pts, int n_pts,
                 omega_row(m, &pts[p], list[b], q[2 * iq], q[2 * iq + 1], delta,
                           n_delta, row);
             }
+    return OR_OK;
+}
+
+/* Eq. (4)-(5) for one band, one q and one point from tabulated band
+ * energies (the paper's recipe for models whose bands are found numerically,
+ * Sec. 3.2, e.g. the three-band model of App. B): ek[i*Ly + j] = E_eps(k) and
+ * eqk[i*Ly + j] = E_eps(q - k) at kx = 2 pi i / Lx, ky = 2 pi j / Ly.
+ * out[id] = Omega_eps(delta[id], q).  T >= 0, V != 0. */
+int oracle_omega_row_tab(const double *ek, const double *eqk, int Lx, int Ly,
+                         double mu, double h, double T, double V,
+                         const double *delta, int n_delta, double *out)
+{
+    if (!ek || !eqk || !delta || !out || Lx < 2 || Ly < 2 || n_delta <= 0)
+        return OR_EINVAL;
+    if (!isfinite(mu) || !isfinite(h) || !isfinite(T) || T < 0.0 || V == 0.0 ||
+        !isfinite(V))
+        return OR_EINVAL;
+    const long N = (long)Lx * Ly;
+    double *e_up = (double *)malloc(sizeof(double) * N);
+    double *e_dn = (double *)malloc(sizeof(double) * N);
+    double *e_kd = (double *)malloc(sizeof(double) * N);
+    double *eta = (double *)malloc(sizeof(double) * N);
+    for (int i = 0; i < Lx; ++i) {
+        double kx = 2.0 * OR_PI * i / Lx;
+        for (int j = 0; j < Ly; ++j) {
+            double ky = 2.0 * OR_PI * j / Ly;
+            long k = (long)i * Ly + j;
+            e_up[k] = ek[k] - (mu + h);
+            e_dn[k] = eqk[k] - (mu - h);
+            e_kd[k] = ek[k] - (mu - h);
+            eta[k] = cos(kx) * cos(ky);
+        }
+    }
+    eq5_sum(N, e_up, e_dn, e_kd, eta, V, T, delta, n_delta, out);
+    free(e_up);
+    free(e_dn);
+    free(e_kd);
+    free(eta);
     return OR_OK;
 }
 

@@ -22,6 +22,16 @@ DEFAULT_MODEL = {"t1": -1.0, "t2": 1.3, "t3": -0.85, "t4": -0.85, "mu": 1.54,
 
 BAND_MINUS, BAND_PLUS, BAND_BOTH = 1, 2, 3
 
+# App. B (three-band model of Daghofer et al.): hoppings t1..t12 and the d_xy
+# on-site energy in eV as printed; mu = 0.4748 eV gives four electrons per
+# site.  The paper gives no V; these put the low-T minimum of every band
+# inside Delta in [0, 0.1] eV (about 0.045, 0.025 and 0.03 eV at h = 0, q = 0).
+# Bands are numbered 0, 1, 2 in ascending energy; band mask bits 1, 2, 4.
+DAGHOFER_MODEL = {"t": (-0.08, 0.1825, 0.08375, -0.03, 0.15, 0.15, -0.12, 0.06, 0.0,
+                        -0.024, -0.01, 0.0275),
+                  "eps0": 0.75, "mu": 0.4748, "V": (-4.5, -2.5, -2.0)}
+BAND3_ALL = 7
+
 # ---------------------------------------------------------------- SplitMix64
 # Steele, Lea & Flood, "Fast splittable pseudorandom number generators",
 # OOPSLA 2014: state advances by the golden-ratio increment, output is the
@@ -62,6 +72,8 @@ def config(name: str) -> dict:
     small      L=64, 128 Delta in [0,0.6], 16 q = 2 pi j / 64 along x, h=0, T=0.001
     paper      L=1024, 256 Delta, 64 q = j pi / 512 (j<64), h=0.1, T=0.002
     precision  L=2048, 512 Delta, 128 q = j pi / 1024, h=0.1, T=0.002
+    three_band App. B model, L=512, 128 Delta in [0,0.1] eV, 32 q = 2 pi j / 512,
+               h=0.01 eV, T=0.0005 eV, all three bands
     """
     if name == "small":
         return {"name": name, "pts": [(0.0, 0.001, 64, 64)], "delta": delta_grid(128),
@@ -72,6 +84,10 @@ def config(name: str) -> dict:
     if name == "precision":
         return {"name": name, "pts": [(0.1, 0.002, 2048, 2048)], "delta": delta_grid(512),
                 "q": q_axis(128, math.pi / 1024), "bands": BAND_BOTH}
+    if name == "three_band":
+        return {"name": name, "pts": [(0.01, 0.0005, 512, 512)],
+                "delta": delta_grid(128, 0.1), "q": q_axis(32, 2.0 * math.pi / 512),
+                "bands": BAND3_ALL, "model": DAGHOFER_MODEL}
     raise KeyError(name)
 
 
