@@ -133,10 +133,63 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
                double *dDelta_dev, double *dq_dev, double *dmu_dev,
                void *stream);
 
+/* ------------------------------------------------------------------------
+ * Three-band model of App. B (Daghofer et al.; orbitals d_xz, d_yz, d_xy).
+ * The band energies are the eigenvalues of the 3x3 orbital matrix of App. B,
+ * which has no closed form the paper uses; as the paper proposes (Sec. 3.2),
+ * they are computed numerically once per lattice and stored (a device table
+ * [3][Lx][Ly]), and E(Q - k) is read from the same table where Q lies on the
+ * lattice (Q = (2 pi m/Lx, 2 pi n/Ly) to 1e-13), else diagonalised at Q - k.
+ * Eq. (4)-(5) and Algorithm 1 then apply per band exactly as above.  Bands
+ * are numbered 0, 1, 2 in ascending energy at each k (energies in eV in the
+ * paper's parametrisation).
+ * ------------------------------------------------------------------------ */
+
+/* t[0..11] = t1..t12 and eps0 as in App. B (printed: t1 = -0.08,
+ * t2 = 0.1825, t3 = 0.08375, t4 = -0.03, t5 = t6 = 0.15, t7 = -0.12,
+ * t8 = 0.06, t9 = 0, t10 = -0.024, t11 = -0.01, t12 = 0.0275,
+ * eps0 = 0.75; mu = 0.4748 gives four electrons per site); V[b]: pairing
+ * strength of band b in Eq. (5).  All finite; V[b] != 0 for selected bands. */
+typedef struct {
+    double t[12];
+    double eps0;
+    double mu;
+    double V[3];
+} omega3_model;
+
+/* Band selection of the three-band model; outputs hold the selected bands in
+ * ascending order. */
+enum { OMEGA3_BAND_0 = 1, OMEGA3_BAND_1 = 2, OMEGA3_BAND_2 = 4, OMEGA3_BAND_ALL = 7 };
+
+/* Band table of App. B on the Lx x Ly lattice: E_dev [3][Lx][Ly] (band, i, j)
+ * at kx = 2 pi i/Lx, ky = 2 pi j/Ly, ascending per momentum.  Needs
+ * ws_bytes >= 16 (Lx + Ly) bytes of workspace.  The V of `model` is not
+ * used here. */
+int omega3_bands(const omega3_model *model, int Lx, int Ly, void *ws_dev, size_t ws_bytes,
+                 double *E_dev, void *stream);
+
+/* Workspace bytes of omega3_grid / omega3_argmin; 0 if the arguments are
+ * invalid.  bands is an OMEGA3_BAND_* mask (1..7). */
+size_t omega3_workspace_bytes(const omega_point *pts, int n_pts, int n_delta, int n_q,
+                              int bands, int precision);
+
+/* As omega_grid, for the three-band model; nb = bands selected (1..3). */
+int omega3_grid(const omega3_model *model, const omega_point *pts, int n_pts,
+                const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                int bands, int precision, void *ws_dev, size_t ws_bytes,
+                double *omega_dev, void *stream);
+
+/* As omega_argmin, for the three-band model (same tie rule and outputs). */
+int omega3_argmin(const omega3_model *model, const omega_point *pts, int n_pts,
+                  const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                  int bands, int precision, double tie_rel, void *ws_dev,
+                  size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
+                  int32_t *row_idx_dev, double *omega_dev, void *stream);
+
 /* Static description of an OMEGA_* code (never NULL). */
 const char *omega_strerror(int code);
 
-/* Library interface version, currently 1. */
+/* Library interface version, currently 2 (2 added the three-band model). */
 int omega_version(void);
 
 /* Timing hook for benchmarks (the paper times the computation part only,
@@ -151,8 +204,8 @@ int omega_set_sweep_events(void *start_event, void *stop_event);
 /* Work counter for benchmarks.  While set (count_dev a device pointer to one
  * zeroed unsigned 64-bit integer), the per-Delta sweep adds the number of
  * (k, Delta) terms it evaluated directly; terms whose Delta dependence is
- * summed through moments of the Delta^2 series (where |s| - |d| >= 36 T
- * and Delta_max^2 eta^2 <= 0.3 s^2) are not counted.  NULL clears it.  Process-wide, not thread-safe.  Always OMEGA_OK. */
+ * summed through moments of a series in Delta^2 (where |s| - |d| >= 36 T
+ * and the series converges fast) are not counted.  NULL clears it.  Process-wide, not thread-safe.  Always OMEGA_OK. */
 int omega_set_sweep_counter(unsigned long long *count_dev);
 
 #ifdef __cplusplus

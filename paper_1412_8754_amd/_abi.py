@@ -11,15 +11,23 @@ OMEGA_BAND_MINUS, OMEGA_BAND_PLUS, OMEGA_BAND_BOTH = 1, 2, 3
 OMEGA_FP64, OMEGA_FP32_COMP = 0, 1
 OMEGA_OK, OMEGA_E_INVAL, OMEGA_E_WORKSPACE, OMEGA_E_HIP, OMEGA_E_UNSUPPORTED = 0, -1, -2, -3, -4
 
+OMEGA3_BAND_0, OMEGA3_BAND_1, OMEGA3_BAND_2, OMEGA3_BAND_ALL = 1, 2, 4, 7
+
 EXPORTS = ("omega_workspace_bytes", "omega_grid", "omega_argmin", "omega_grad",
            "omega_strerror", "omega_version", "omega_set_sweep_events",
-           "omega_set_sweep_counter")
+           "omega_set_sweep_counter", "omega3_bands", "omega3_workspace_bytes",
+           "omega3_grid", "omega3_argmin")
 
 
 class Model(ctypes.Structure):
     _fields_ = [("t1", ctypes.c_double), ("t2", ctypes.c_double),
                 ("t3", ctypes.c_double), ("t4", ctypes.c_double),
                 ("mu", ctypes.c_double), ("V", ctypes.c_double * 2)]
+
+
+class Model3(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double * 12), ("eps0", ctypes.c_double),
+                ("mu", ctypes.c_double), ("V", ctypes.c_double * 3)]
 
 
 class Point(ctypes.Structure):
@@ -71,6 +79,16 @@ def load() -> ctypes.CDLL:
     L.omega_set_sweep_events.argtypes = [vp, vp]
     L.omega_set_sweep_counter.restype = i32
     L.omega_set_sweep_counter.argtypes = [vp]
+    m3 = ctypes.POINTER(Model3)
+    L.omega3_bands.restype = i32
+    L.omega3_bands.argtypes = [m3, i32, i32, vp, sz, vp, vp]
+    L.omega3_workspace_bytes.restype = sz
+    L.omega3_workspace_bytes.argtypes = [pp, i32, i32, i32, i32, i32]
+    L.omega3_grid.restype = i32
+    L.omega3_grid.argtypes = [m3, pp, i32, vp, i32, vp, i32, i32, i32, vp, sz, vp, vp]
+    L.omega3_argmin.restype = i32
+    L.omega3_argmin.argtypes = [m3, pp, i32, vp, i32, vp, i32, i32, i32, ctypes.c_double,
+                                vp, sz, vp, vp, vp, vp, vp]
     _lib = L
     return L
 
@@ -86,6 +104,13 @@ def make_model(m) -> Model:
                  float(m["mu"]), (ctypes.c_double * 2)(*[float(v) for v in m["V"]]))
 
 
+def make_model3(m) -> Model3:
+    if isinstance(m, Model3):
+        return m
+    return Model3((ctypes.c_double * 12)(*[float(v) for v in m["t"]]), float(m["eps0"]),
+                  float(m["mu"]), (ctypes.c_double * 3)(*[float(v) for v in m["V"]]))
+
+
 def make_points(pts):
     arr = (Point * len(pts))()
     for i, (h, T, Lx, Ly) in enumerate(pts):
@@ -95,3 +120,7 @@ def make_points(pts):
 
 def n_bands(bands: int) -> int:
     return int(bool(bands & 1)) + int(bool(bands & 2))
+
+
+def n_bands3(bands: int) -> int:
+    return int(bool(bands & 1)) + int(bool(bands & 2)) + int(bool(bands & 4))

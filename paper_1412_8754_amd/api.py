@@ -12,8 +12,9 @@ import ctypes
 import torch
 
 from . import _abi
-from ._abi import (OMEGA_BAND_BOTH, OMEGA_FP32_COMP, OMEGA_FP64, OmegaError,  # noqa: F401
-                   make_model, make_points, n_bands)
+from ._abi import (OMEGA3_BAND_ALL, OMEGA_BAND_BOTH, OMEGA_FP32_COMP,  # noqa: F401
+                   OMEGA_FP64, OmegaError, make_model, make_model3, make_points, n_bands,
+                   n_bands3)
 
 
 def _stream_ptr(stream) -> int:
@@ -124,3 +125,75 @@ def grad(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, device="cuda", work
                       gd.data_ptr(), gq.data_ptr(), gm.data_ptr(), _stream_ptr(stream))
     _check(rc, "omega_grad")
     return om, gd, gq, gm
+
+
+# ------------------------------------------------------------- three-band model
+
+def bands3(model, Lx: int, Ly: int, device="cuda", stream=None) -> torch.Tensor:
+    """Band table of App. B on the Lx x Ly lattice, [3][Lx][Ly], ascending."""
+    L = _abi.load()
+    out = torch.empty((3, int(Lx), int(Ly)), dtype=torch.float64, device=device)
+    ws = torch.empty(16 * (int(Lx) + int(Ly)), dtype=torch.uint8, device=device)
+    m = make_model3(model)
+    rc = L.omega3_bands(ctypes.byref(m), int(Lx), int(Ly), ws.data_ptr(), ws.numel(),
+                        out.data_ptr(), _stream_ptr(stream))
+    _check(rc, "omega3_bands")
+    return out
+
+
+def workspace_bytes3(pts, n_delta: int, n_q: int, bands: int = OMEGA3_BAND_ALL,
+                     precision: int = OMEGA_FP64) -> int:
+    L = _abi.load()
+    p = make_points(pts)
+    n = L.omega3_workspace_bytes(p, len(pts), int(n_delta), int(n_q), int(bands),
+                                 int(precision))
+    if n == 0:
+        raise OmegaError(_abi.OMEGA_E_INVAL, "omega3_workspace_bytes")
+    return int(n)
+
+
+def grid3(model, pts, delta, q, bands: int = OMEGA3_BAND_ALL, precision: int = OMEGA_FP64,
+          device="cuda", out=None, workspace=None, stream=None) -> torch.Tensor:
+    """Three-band Omega grid [n_pts][n_bands][n_q][n_delta]."""
+    L = _abi.load()
+    d = _dev_f64(delta, device, (-1,))
+    qq = _dev_f64(q, device, (-1, 2))
+    nb = n_bands3(bands)
+    shape = (len(pts), nb, qq.shape[0], d.numel())
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=device)
+    assert out.is_contiguous() and tuple(out.shape) == shape and out.dtype == torch.float64
+    ws = _workspace(workspace_bytes3(pts, d.numel(), qq.shape[0], bands, precision), device,
+                    workspace)
+    m = make_model3(model)
+    p = make_points(pts)
+    rc = L.omega3_grid(ctypes.byref(m), p, len(pts), d.data_ptr(), d.numel(), qq.data_ptr(),
+                       qq.shape[0], int(bands), int(precision), ws.data_ptr(),
+                       ws.numel() * ws.element_size(), out.data_ptr(), _stream_ptr(stream))
+    _check(rc, "omega3_grid")
+    return out
+
+
+def argmin3(model, pts, delta, q, bands: int = OMEGA3_BAND_ALL, precision: int = OMEGA_FP64,
+            tie_rel: float = 1e-11, keep_grid: bool = True, rows: bool = True,
+            device="cuda", workspace=None, stream=None):
+    """Three-band grid plus the searches of Algorithm 1 (outputs as argmin)."""
+    L = _abi.load()
+    d = _dev_f64(delta, device, (-1,))
+    qq = _dev_f64(q, device, (-1, 2))
+    nb = n_bands3(bands)
+    n_pts, n_q, n_d = len(pts), qq.shape[0], d.numel()
+    idx = torch.empty((n_pts, nb, 2), dtype=torch.int32, device=device)
+    omin = torch.empty((n_pts, nb), dtype=torch.float64, device=device)
+    row_idx = torch.empty((n_pts, nb, n_q), dtype=torch.int32, device=device) if rows else None
+    om = torch.empty((n_pts, nb, n_q, n_d), dtype=torch.float64, device=device) if keep_grid else None
+    ws = _workspace(workspace_bytes3(pts, n_d, n_q, bands, precision), device, workspace)
+    m = make_model3(model)
+    p = make_points(pts)
+    rc = L.omega3_argmin(ctypes.byref(m), p, n_pts, d.data_ptr(), n_d, qq.data_ptr(), n_q,
+                         int(bands), int(precision), float(tie_rel), ws.data_ptr(),
+                         ws.numel() * ws.element_size(), idx.data_ptr(), omin.data_ptr(),
+                         row_idx.data_ptr() if row_idx is not None else None,
+                         om.data_ptr() if om is not None else None, _stream_ptr(stream))
+    _check(rc, "omega3_argmin")
+    return idx, omin, row_idx, om

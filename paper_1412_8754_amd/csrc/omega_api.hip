@@ -50,6 +50,30 @@ int slot_bands(int bands, int *list)
     return nb;
 }
 
+int slot_bands3(int bands, int *list)
+{
+    int nb = 0;
+    for (int b = 0; b < 3; ++b)
+        if (bands & (1 << b))
+            list[nb++] = b;
+    return nb;
+}
+
+bool model3_ok(const omega3_model *m, int bands)
+{
+    if (!m)
+        return false;
+    for (double x : m->t)
+        if (!isfinite(x))
+            return false;
+    if (!isfinite(m->eps0) || !isfinite(m->mu))
+        return false;
+    for (int b = 0; b < 3; ++b)
+        if ((bands & (1 << b)) && (!isfinite(m->V[b]) || m->V[b] == 0.0))
+            return false;
+    return true;
+}
+
 bool model_ok(const omega_model *m)
 {
     if (!m)
@@ -165,10 +189,13 @@ struct GridPlan {
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_mask, sweep_bytes;
+        off_mask, off_etab, off_qlat, sweep_bytes;
 };
 
-GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb)
+// b3: three-band model, which adds the band table [3][Lx][Ly] of the largest
+// lattice and the lattice indices of the pair momenta.
+GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb,
+                   bool b3 = false)
 {
     GridPlan p;
     p.nb = nb;
@@ -177,9 +204,11 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.n_delta_pad = p.n_dtiles * p.td;
     p.nbq = nb * n_q;
     p.groups = group_points(pts, n_pts);
-    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0;
+    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0, etab = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
+        if (b3)
+            etab = std::max(etab, sizeof(double) * 3 * (size_t)g.Lx * g.Ly);
         const size_t rows = (size_t)p.nbq * t.n_chunks;
         const size_t per_point =
             sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots) +
@@ -203,7 +232,9 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_base = p.off_part + align_up(part);
     p.off_mom = p.off_base + align_up(base);
     p.off_mask = p.off_mom + align_up(mom);
-    p.sweep_bytes = p.off_mask + align_up(mask);
+    p.off_etab = p.off_mask + align_up(mask);
+    p.off_qlat = p.off_etab + align_up(etab);
+    p.sweep_bytes = p.off_qlat + (b3 ? align_up(sizeof(int) * 2 * (size_t)n_q) : 0);
     return p;
 }
 
@@ -280,16 +311,53 @@ int upload_points(const omega_point *pts, const int *idx, int G, PointRec *table
     return OMEGA_OK;
 }
 
+// Either model, as the sweep sees it: band selection per output slot,
+// couplings and hoppings.
+struct ModelDesc {
+    bool b3;
+    int nb;
+    int list[3];
+    double mu;
+    double V[3];     // per output slot
+    Hop hop;         // two-band
+    Hop3 hop3;       // three-band
+};
+
+ModelDesc describe(const omega_model *m, int bands)
+{
+    ModelDesc d{};
+    d.b3 = false;
+    d.nb = slot_bands(bands, d.list);
+    d.mu = m->mu;
+    for (int k = 0; k < 3; ++k)
+        d.V[k] = m->V[d.list[k < d.nb ? k : 0]];
+    d.hop = make_hop(m);
+    return d;
+}
+
+ModelDesc describe3(const omega3_model *m, int bands)
+{
+    ModelDesc d{};
+    d.b3 = true;
+    d.nb = slot_bands3(bands, d.list);
+    d.mu = m->mu;
+    for (int k = 0; k < 3; ++k)
+        d.V[k] = m->V[d.list[k < d.nb ? k : 0]];
+    for (int k = 0; k < 12; ++k)
+        d.hop3.t[k] = m->t[k];
+    d.hop3.eps0 = m->eps0;
+    return d;
+}
+
 // Enqueue the sweep and row reduction of every point.  Omega goes to `grid`,
 // row minima to row_idx (optional).
-int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
+int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
                  const double *delta, int n_delta, const double *q, int n_q,
-                 int bands, int precision, char *ws, double tie_rel,
+                 int precision, char *ws, double tie_rel,
                  double *grid, int32_t *row_idx, hipStream_t s)
 {
-    int list[2];
-    const int nb = slot_bands(bands, list);
-    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb);
+    const int nb = md.nb;
+    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3);
     double *d2 = (double *)(ws + P.off_d2);
     double *qtrig = (double *)(ws + P.off_qtrig);
     double2 *gtab = (double2 *)(ws + P.off_gtab);
@@ -299,6 +367,8 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     double *base = (double *)(ws + P.off_base);
     double *mom = (double *)(ws + P.off_mom);
     unsigned long long *mask = (unsigned long long *)(ws + P.off_mask);
+    double *etab = (double *)(ws + P.off_etab);
+    int *qlat = (int *)(ws + P.off_qlat);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
         return OMEGA_E_HIP;
     if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
@@ -307,9 +377,14 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
         return OMEGA_E_HIP;
 
     SweepArgs a;
-    a.hop = make_hop(m);
-    band_signs(nb, list, a.eps);
-    a.mu = m->mu;
+    a.hop = md.hop;
+    band_signs(nb, md.list, a.eps);
+    a.hop3 = md.hop3;
+    for (int k = 0; k < 3; ++k)
+        a.band3[k] = md.list[k < nb ? k : 0];
+    a.etab = etab;
+    a.qlat = qlat;
+    a.mu = md.mu;
     a.pts = table;
     a.n_q = n_q;
     a.nbq = P.nbq;
@@ -333,8 +408,8 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
     r.pts = table;
     r.delta = delta;
     r.q = q;
-    r.Vs[0] = m->V[list[0]];
-    r.Vs[1] = m->V[nb > 1 ? list[1] : list[0]];
+    for (int k = 0; k < 3; ++k)
+        r.Vs[k] = md.V[k];
     r.tie_rel = tie_rel;
     r.n_delta = n_delta;
     r.n_delta_pad = P.n_delta_pad;
@@ -347,6 +422,9 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
         const Group &g = P.groups[gi];
         const Tiles &t = P.tiles[gi];
         if (launch_trig(g.Lx, g.Ly, trig, s) != hipSuccess)
+            return OMEGA_E_HIP;
+        if (md.b3 && (launch_etab(md.hop3, trig, g.Lx, g.Ly, etab, s) != hipSuccess ||
+                      launch_qlat(q, n_q, g.Lx, g.Ly, qlat, s) != hipSuccess))
             return OMEGA_E_HIP;
         a.Lx = g.Lx;
         a.Ly = g.Ly;
@@ -362,13 +440,13 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
             int rc = upload_points(pts, g.idx.data() + b0, G, table, s);
             if (rc != OMEGA_OK)
                 return rc;
-            if (launch_series(a, G, precision == OMEGA_FP64, s) != hipSuccess)
+            if (launch_series(a, G, precision == OMEGA_FP64, md.b3, s) != hipSuccess)
                 return OMEGA_E_HIP;
             if (g_sweep_start && hipEventRecord(g_sweep_start, s) != hipSuccess)
                 return OMEGA_E_HIP;
             hipError_t e = precision == OMEGA_FP64
-                               ? launch_sweep_f64(a, P.td, P.n_dtiles, G, s)
-                               : launch_sweep_f32c(a, P.td, P.n_dtiles, G, s);
+                               ? launch_sweep_f64(a, P.td, P.n_dtiles, G, md.b3, s)
+                               : launch_sweep_f32c(a, P.td, P.n_dtiles, G, md.b3, s);
             if (e != hipSuccess)
                 return OMEGA_E_HIP;
             if (g_sweep_stop && hipEventRecord(g_sweep_stop, s) != hipSuccess)
@@ -377,6 +455,52 @@ int enqueue_grid(const omega_model *m, const omega_point *pts, int n_pts,
                 return OMEGA_E_HIP;
         }
     }
+    return OMEGA_OK;
+}
+
+// Shared bodies of the grid / argmin entry points of both models (inputs
+// already validated except pointers, workspace and tie_rel).
+int run_grid(const ModelDesc &md, const omega_point *pts, int n_pts, const double *delta_dev,
+             int n_delta, const double *q_dev, int n_q, int precision, void *ws_dev,
+             size_t ws_bytes, double *omega_dev, void *stream)
+{
+    if (!delta_dev || !q_dev || !omega_dev || !ws_dev)
+        return OMEGA_E_INVAL;
+    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, md.nb, md.b3).sweep_bytes)
+        return OMEGA_E_WORKSPACE;
+    return enqueue_grid(md, pts, n_pts, delta_dev, n_delta, q_dev, n_q, precision,
+                        (char *)ws_dev, 0.0, omega_dev, nullptr, (hipStream_t)stream);
+}
+
+int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const double *delta_dev,
+               int n_delta, const double *q_dev, int n_q, int precision, double tie_rel,
+               void *ws_dev, size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
+               int32_t *row_idx_dev, double *omega_dev, void *stream)
+{
+    if (!delta_dev || !q_dev || !idx_dev || !omin_dev || !ws_dev)
+        return OMEGA_E_INVAL;
+    if (!(tie_rel >= 0.0) || !isfinite(tie_rel))
+        return OMEGA_E_INVAL;
+    const int nb = md.nb;
+    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3).sweep_bytes;
+    const size_t need = sweep + (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
+    if (ws_bytes < need)
+        return OMEGA_E_WORKSPACE;
+    double *grid = omega_dev ? omega_dev : (double *)((char *)ws_dev + sweep);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = enqueue_grid(md, pts, n_pts, delta_dev, n_delta, q_dev, n_q, precision,
+                          (char *)ws_dev, tie_rel, grid, row_idx_dev, s);
+    if (rc != OMEGA_OK)
+        return rc;
+    ArgminArgs a;
+    a.omega = grid;
+    a.n_q = n_q;
+    a.n_delta = n_delta;
+    a.tie_rel = tie_rel;
+    a.idx = idx_dev;
+    a.omin = omin_dev;
+    if (launch_argmin(a, n_pts * nb, s) != hipSuccess)
+        return OMEGA_E_HIP;
     return OMEGA_OK;
 }
 
@@ -406,14 +530,8 @@ int omega_grid(const omega_model *model, const omega_point *pts, int n_pts,
     if (!model_ok(model) || !points_ok(pts, n_pts) ||
         !sizes_ok(n_delta, n_q, bands, precision))
         return OMEGA_E_INVAL;
-    if (!delta_dev || !q_dev || !omega_dev || !ws_dev)
-        return OMEGA_E_INVAL;
-    const int nb = n_bands(bands);
-    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, nb).sweep_bytes)
-        return OMEGA_E_WORKSPACE;
-    return enqueue_grid(model, pts, n_pts, delta_dev, n_delta, q_dev, n_q, bands,
-                        precision, (char *)ws_dev, 0.0, omega_dev, nullptr,
-                        (hipStream_t)stream);
+    return run_grid(describe(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
+                    precision, ws_dev, ws_bytes, omega_dev, stream);
 }
 
 int omega_argmin(const omega_model *model, const omega_point *pts, int n_pts,
@@ -426,31 +544,67 @@ int omega_argmin(const omega_model *model, const omega_point *pts, int n_pts,
     if (!model_ok(model) || !points_ok(pts, n_pts) ||
         !sizes_ok(n_delta, n_q, bands, precision))
         return OMEGA_E_INVAL;
-    if (!delta_dev || !q_dev || !idx_dev || !omin_dev || !ws_dev)
+    return run_argmin(describe(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
+                      precision, tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev, row_idx_dev,
+                      omega_dev, stream);
+}
+
+int omega3_bands(const omega3_model *model, int Lx, int Ly, void *ws_dev, size_t ws_bytes,
+                 double *E_dev, void *stream)
+{
+    if (!model3_ok(model, 0) || !E_dev || !ws_dev)
         return OMEGA_E_INVAL;
-    if (!(tie_rel >= 0.0) || !isfinite(tie_rel))
+    const omega_point p{0.0, 0.0, Lx, Ly};
+    if (!point_ok(p))
         return OMEGA_E_INVAL;
-    const int nb = n_bands(bands);
-    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb).sweep_bytes;
-    const size_t need = sweep + (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
-    if (ws_bytes < need)
+    if (ws_bytes < sizeof(double) * 2 * ((size_t)Lx + Ly))
         return OMEGA_E_WORKSPACE;
-    double *grid = omega_dev ? omega_dev : (double *)((char *)ws_dev + sweep);
     hipStream_t s = (hipStream_t)stream;
-    int rc = enqueue_grid(model, pts, n_pts, delta_dev, n_delta, q_dev, n_q, bands,
-                          precision, (char *)ws_dev, tie_rel, grid, row_idx_dev, s);
-    if (rc != OMEGA_OK)
-        return rc;
-    ArgminArgs a;
-    a.omega = grid;
-    a.n_q = n_q;
-    a.n_delta = n_delta;
-    a.tie_rel = tie_rel;
-    a.idx = idx_dev;
-    a.omin = omin_dev;
-    if (launch_argmin(a, n_pts * nb, s) != hipSuccess)
+    double *trig = (double *)ws_dev;
+    if (launch_trig(Lx, Ly, trig, s) != hipSuccess)
+        return OMEGA_E_HIP;
+    if (launch_etab(describe3(model, 0).hop3, trig, Lx, Ly, E_dev, s) != hipSuccess)
         return OMEGA_E_HIP;
     return OMEGA_OK;
+}
+
+size_t omega3_workspace_bytes(const omega_point *pts, int n_pts, int n_delta, int n_q,
+                              int bands, int precision)
+{
+    if (!points_ok(pts, n_pts) || bands < 1 || bands > 7)
+        return 0;
+    if (!sizes_ok(n_delta, n_q, 1, precision))
+        return 0;
+    int list[3];
+    const int nb = slot_bands3(bands, list);
+    return plan_grid(pts, n_pts, n_delta, n_q, nb, true).sweep_bytes +
+           grid_bytes(n_pts, n_delta, n_q, nb);
+}
+
+int omega3_grid(const omega3_model *model, const omega_point *pts, int n_pts,
+                const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                int bands, int precision, void *ws_dev, size_t ws_bytes,
+                double *omega_dev, void *stream)
+{
+    if (bands < 1 || bands > 7 || !model3_ok(model, bands) || !points_ok(pts, n_pts) ||
+        !sizes_ok(n_delta, n_q, 1, precision))
+        return OMEGA_E_INVAL;
+    return run_grid(describe3(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
+                    precision, ws_dev, ws_bytes, omega_dev, stream);
+}
+
+int omega3_argmin(const omega3_model *model, const omega_point *pts, int n_pts,
+                  const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                  int bands, int precision, double tie_rel, void *ws_dev,
+                  size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
+                  int32_t *row_idx_dev, double *omega_dev, void *stream)
+{
+    if (bands < 1 || bands > 7 || !model3_ok(model, bands) || !points_ok(pts, n_pts) ||
+        !sizes_ok(n_delta, n_q, 1, precision))
+        return OMEGA_E_INVAL;
+    return run_argmin(describe3(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
+                      precision, tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev, row_idx_dev,
+                      omega_dev, stream);
 }
 
 int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
@@ -546,7 +700,7 @@ const char *omega_strerror(int code)
     }
 }
 
-int omega_version(void) { return 1; }
+int omega_version(void) { return 2; }
 
 int omega_set_sweep_counter(unsigned long long *count_dev)
 {

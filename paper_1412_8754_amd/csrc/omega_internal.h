@@ -17,6 +17,14 @@ struct Hop {
     double tA, tB, tD, tC;
 };
 
+// Three-band model of App. B: hoppings t1..t12 (t[0] = t1) and the d_xy
+// on-site energy; bands are the eigenvalues of the 3x3 orbital matrix in
+// ascending order, tabulated per lattice (Sec. 3.2: precomputed and stored).
+struct Hop3 {
+    double t[12];
+    double eps0;
+};
+
 // Skip threshold of the thermal term: where |E|/T exceeds this,
 // T ln(1 + exp(-|E|/T)) < T * 2.4e-16 and the term is dropped.
 constexpr double kCutFp64 = 36.0;
@@ -65,7 +73,11 @@ struct PointPack {
 // size; grid (chunk, Delta tile, band*Q + nbq*g).
 struct SweepArgs {
     Hop hop;
-    double eps[2];       // band sign per output slot (-1: E_-, +1: E_+)
+    double eps[2];       // two-band: band sign per output slot (-1: E_-, +1: E_+)
+    Hop3 hop3;           // three-band: model, for momenta off the lattice
+    int band3[3];        // three-band: band index per output slot
+    const double *etab;  // three-band: E_b(k) [3][Lx][Ly]
+    const int *qlat;     // three-band: [n_q][2] lattice index of Q, or -1 if off it
     double mu;           // chemical potential
     const PointRec *pts; // [G] this batch
     int Lx, Ly;
@@ -98,7 +110,7 @@ struct RowArgs {
     const PointRec *pts;   // [G]
     const double *delta;   // [n_delta]
     const double *q;       // [n_q][2]
-    double Vs[2];          // V per output slot
+    double Vs[3];          // V per output slot
     double n_k;            // Lx * Ly
     double tie_rel;
     int n_chunks, n_delta, n_delta_pad, n_q, nbq;
@@ -145,10 +157,13 @@ hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
 hipError_t launch_gtable(double2 *gtab, hipStream_t s);
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s);
-hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s);
-hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
+hipError_t launch_etab(const Hop3 &h, const double *trig, int Lx, int Ly, double *etab,
+                       hipStream_t s);
+hipError_t launch_qlat(const double *q, int n_q, int Lx, int Ly, int *qlat, hipStream_t s);
+hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStream_t s);
+hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                             hipStream_t s);
-hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G,
+hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                              hipStream_t s);
 hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s);
 hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s);

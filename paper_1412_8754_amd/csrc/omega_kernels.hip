@@ -369,19 +369,9 @@ struct KQ {
 //   2 min(d, 0) + E_{k down}                     (Delta-independent)
 //   - max(R - |d|, 0) - T ln[(1 + u1)(1 + u2)]   (Delta-dependent)
 // with u1 = exp(-|R - |d||/T), u2 = exp(-(R + |d|)/T).
-__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
-                                       double mu_up, double mu_dn, double cqx,
-                                       double sqx, double cqy, double sqy,
-                                       double cx, double sx, double cy,
-                                       double sy)
+__device__ __forceinline__ KQ kq_from(double Ek, double Eq, double mu_up, double mu_dn,
+                                      double cx, double cy)
 {
-    double Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
-    // cos/sin of (Q - k) by angle subtraction
-    double cpx = fma(cqx, cx, sqx * sx);
-    double spx = fma(sqx, cx, -(cqx * sx));
-    double cpy = fma(cqy, cy, sqy * sy);
-    double spy = fma(sqy, cy, -(cqy * sy));
-    double Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
     double up = Ek - mu_up;
     double dn = Eq - mu_dn;
     double s = 0.5 * (up + dn);
@@ -394,6 +384,178 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, double eps,
     r.eta2 = eta * eta;
     r.base = 2.0 * fmin(d, 0.0) + (Ek - mu_dn);
     return r;
+}
+
+// Real symmetric 3x3 matrix [[a00, a01, a02], [a01, a11, a12], [a02, a12, a22]].
+struct Sym3 {
+    double a00, a11, a22, a01, a02, a12;
+};
+
+// One Jacobi rotation in the (p, q) plane annihilating apq; r is the third
+// index.  t = tan of the rotation angle, the smaller root of
+// t^2 + 2 theta t - 1 = 0 with theta = (aqq - app) / (2 apq); tau = s/(1 + c).
+__device__ __forceinline__ void jacobi_rotate(double &app, double &aqq, double &apq,
+                                              double &arp, double &arq)
+{
+    if (fabs(apq) <= 1e-18 * (fabs(app) + fabs(aqq)) + 1e-300) {
+        apq = 0.0;
+        return;
+    }
+    const double theta = (aqq - app) / (2.0 * apq);
+    const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
+    const double c = 1.0 / sqrt(fma(t, t, 1.0));
+    const double sn = t * c;
+    const double tau = sn / (1.0 + c);
+    app = fma(-t, apq, app);
+    aqq = fma(t, apq, aqq);
+    apq = 0.0;
+    const double rp = arp, rq = arq;
+    arp = rp - sn * fma(tau, rp, rq);
+    arq = rq + sn * fma(-tau, rq, rp);
+}
+
+// Eigenvalues of App. B's orbital matrix at one momentum, ascending.  With
+// T13 = i alpha and T23 = i beta (alpha, beta real) the unitary
+// diag(1, 1, i) maps the Hermitian matrix onto the real symmetric one with
+// off-diagonals (T12, alpha, beta) up to a common sign of the last two,
+// which leaves the spectrum unchanged; it is diagonalised by cyclic Jacobi
+// sweeps (backward stable: eigenvalue errors of order 1e-16 of the norm).
+__device__ __forceinline__ void eig3(const Hop3 &h, double cx, double sx, double cy,
+                                     double sy, double c2x, double c2y, double *E)
+{
+    const double *t = h.t;   // t[0] = t1
+    Sym3 A;
+    const double cxy = cx * cy, c2xy = c2x * c2y, dc2 = c2x - c2y;
+    A.a00 = 2.0 * t[1] * cx + 2.0 * t[0] * cy + 4.0 * t[2] * cxy + 2.0 * t[10] * dc2 +
+            4.0 * t[11] * c2xy;
+    A.a11 = 2.0 * t[0] * cx + 2.0 * t[1] * cy + 4.0 * t[2] * cxy - 2.0 * t[10] * dc2 +
+            4.0 * t[11] * c2xy;
+    A.a22 = h.eps0 + 2.0 * t[4] * (cx + cy) + 4.0 * t[5] * cxy + 2.0 * t[8] * (c2x + c2y) +
+            4.0 * t[9] * (c2x * cy + cx * c2y);
+    A.a01 = 4.0 * t[3] * sx * sy;
+    A.a02 = 2.0 * t[6] * sx + 4.0 * t[7] * sx * cy;
+    A.a12 = 2.0 * t[6] * sy + 4.0 * t[7] * sy * cx;
+#pragma unroll 1
+    for (int sweep = 0; sweep < 12; ++sweep) {
+        if (A.a01 == 0.0 && A.a02 == 0.0 && A.a12 == 0.0)
+            break;
+        jacobi_rotate(A.a00, A.a11, A.a01, A.a02, A.a12);
+        jacobi_rotate(A.a00, A.a22, A.a02, A.a01, A.a12);
+        jacobi_rotate(A.a11, A.a22, A.a12, A.a01, A.a02);
+    }
+    double e0 = A.a00, e1 = A.a11, e2 = A.a22, tmp;
+    if (e0 > e1) { tmp = e0; e0 = e1; e1 = tmp; }
+    if (e1 > e2) { tmp = e1; e1 = e2; e2 = tmp; }
+    if (e0 > e1) { tmp = e0; e0 = e1; e1 = tmp; }
+    E[0] = e0;
+    E[1] = e1;
+    E[2] = e2;
+}
+
+// One band of eig3 at Q - k, for pair momenta off the lattice.
+__device__ __forceinline__ double eig3_band(const Hop3 &h, double c, double sn, double cy,
+                                            double sy, int b)
+{
+    double ev[3];
+    eig3(h, c, sn, cy, sy, (c - sn) * (c + sn), (cy - sy) * (cy + sy), ev);
+    return b == 0 ? ev[0] : (b == 1 ? ev[1] : ev[2]);
+}
+
+// E(k) and E(Q - k) of one momentum for output slot `slot` and pair momentum
+// iq.  Two-band: (A.4) in closed form, with cos/sin of Q - k by angle
+// subtraction.  Three-band: E(k) from the lattice table; E(Q - k) from the
+// same table at the lattice index of Q - k when Q lies on the lattice, else
+// by diagonalising at Q - k.
+template <bool B3>
+__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int iq, int i, int j,
+                                       double eps, double mu_up, double mu_dn, double cqx,
+                                       double sqx, double cqy, double sqy, double cx,
+                                       double sx, double cy, double sy)
+{
+    const double cpx = fma(cqx, cx, sqx * sx);
+    const double spx = fma(sqx, cx, -(cqx * sx));
+    const double cpy = fma(cqy, cy, sqy * sy);
+    const double spy = fma(sqy, cy, -(cqy * sy));
+    double Ek, Eq;
+    if constexpr (!B3) {
+        Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
+        Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
+    } else {
+        const int b = a.band3[slot];
+        const double *E = a.etab + (size_t)b * a.Lx * a.Ly;
+        Ek = E[(size_t)i * a.Ly + j];
+        const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
+        if (mx >= 0 && my >= 0) {
+            int ii = mx - i;
+            ii += ii < 0 ? a.Lx : 0;
+            int jj = my - j;
+            jj += jj < 0 ? a.Ly : 0;
+            Eq = E[(size_t)ii * a.Ly + jj];
+        } else {
+            Eq = eig3_band(a.hop3, cpx, spx, cpy, spy, b);
+        }
+    }
+    return kq_from(Ek, Eq, mu_up, mu_dn, cx, cy);
+}
+
+// Band table of the three-band model over the lattice, [3][Lx][Ly], from the
+// cos/sin table (cos 2k at the lattice index 2i mod L).
+__global__ void etab_kernel(const Hop3 h, const double *trig, int Lx, int Ly, double *E)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)Lx * Ly;
+    if (t >= n)
+        return;
+    const int i = (int)(t / Ly);
+    const int j = (int)(t - (long long)i * Ly);
+    const double *cxt = trig, *sxt = trig + Lx, *cyt = trig + 2 * Lx, *syt = cyt + Ly;
+    const int i2 = (int)((2LL * i) % Lx), j2 = (int)((2LL * j) % Ly);
+    double ev[3];
+    eig3(h, cxt[i], sxt[i], cyt[j], syt[j], cxt[i2], cyt[j2], ev);
+    E[t] = ev[0];
+    E[n + t] = ev[1];
+    E[2 * n + t] = ev[2];
+}
+
+hipError_t launch_etab(const Hop3 &h, const double *trig, int Lx, int Ly, double *etab,
+                       hipStream_t s)
+{
+    const long long n = (long long)Lx * Ly;
+    hipLaunchKernelGGL(etab_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, h, trig, Lx, Ly, etab);
+    return hipGetLastError();
+}
+
+// Lattice index of each pair momentum: (m, n) with Q = (2 pi m/Lx, 2 pi n/Ly)
+// to within 1e-13 (m, n reduced into [0, L)), else (-1, -1).
+__global__ void qlat_kernel(const double *q, int n_q, int Lx, int Ly, int *qlat)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_q)
+        return;
+    int idx[2] = {-1, -1};
+    const int L[2] = {Lx, Ly};
+    bool ok = true;
+    for (int c = 0; c < 2; ++c) {
+        const double v = q[2 * t + c];
+        const double step = 2.0 * M_PI / L[c];
+        const double m = rint(v / step);
+        if (!(fabs(v - m * step) <= 1e-13 * fmax(1.0, fabs(v))) || fabs(m) > 1e9) {
+            ok = false;
+            break;
+        }
+        long long mi = (long long)m % L[c];
+        idx[c] = (int)(mi < 0 ? mi + L[c] : mi);
+    }
+    qlat[2 * t] = ok ? idx[0] : -1;
+    qlat[2 * t + 1] = ok ? idx[1] : -1;
+}
+
+hipError_t launch_qlat(const double *q, int n_q, int Lx, int Ly, int *qlat, hipStream_t s)
+{
+    hipLaunchKernelGGL(qlat_kernel, dim3((n_q + kBlock - 1) / kBlock), dim3(kBlock), 0, s, q,
+                       n_q, Lx, Ly, qlat);
+    return hipGetLastError();
 }
 
 // Whether the (k, Q) term's Delta dependence goes through the Delta^2 series
@@ -456,6 +618,7 @@ __device__ __forceinline__ double mirror_weight(const KRange &k, int j, int Ly)
 //   - for every 8 x 8 tile, the ballot of lanes the per-Delta sweep must
 //     evaluate directly.
 // Grid (chunk, band*Q + nbq*g).
+template <bool B3>
 __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
 {
     const int chunk = blockIdx.x;
@@ -495,8 +658,8 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
         const int j = tj * kTileEdge + lj;
         bool direct = false;
         if (i < a.Lx && j < kr.jlim) {
-            const KQ r = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
-                                  sxt[i], cyt[j], syt[j]);
+            const KQ r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy,
+                                      sqy, cxt[i], sxt[i], cyt[j], syt[j]);
             const double w = mirror_weight(kr, j, a.Ly);
             const double A0 = r.as - r.m;
             double base = r.base;
@@ -549,16 +712,19 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
             ((bred[0] + bred[1]) + bred[2]) + bred[3];
 }
 
-hipError_t launch_series(const SweepArgs &a, int G, bool fp64, hipStream_t s)
+hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStream_t s)
 {
-    hipLaunchKernelGGL(series_kernel, dim3(a.n_chunks, a.nbq * G), dim3(kBlock), 0, s, a,
-                       fp64 ? 1 : 0);
+    const dim3 grid(a.n_chunks, a.nbq * G);
+    if (b3)
+        hipLaunchKernelGGL(series_kernel<true>, grid, dim3(kBlock), 0, s, a, fp64 ? 1 : 0);
+    else
+        hipLaunchKernelGGL(series_kernel<false>, grid, dim3(kBlock), 0, s, a, fp64 ? 1 : 0);
     return hipGetLastError();
 }
 
 // Per-Delta FP64 sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.
-template <int TD>
+template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
 void sweep_f64_kernel(const SweepArgs a)
 {
@@ -620,8 +786,8 @@ void sweep_f64_kernel(const SweepArgs a)
         asm volatile("" : "+v"(zoff));
         const double *dp = d2s + zoff;
         if ((mk >> lane) & 1ull) {
-            KQ r = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
-                            sxt[i], cyt[j], syt[j]);
+            KQ r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
+                                cxt[i], sxt[i], cyt[j], syt[j]);
             const double w = mirror_weight(kr, j, a.Ly);
             const double wT = w * T;
             ++n_direct;
@@ -664,20 +830,20 @@ void sweep_f64_kernel(const SweepArgs a)
     }
 }
 
-hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G,
+hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                             hipStream_t s)
 {
     dim3 grid(a.n_chunks, n_dtiles, a.nbq * G);
-    switch (td) {
-    case 16:
-        hipLaunchKernelGGL(sweep_f64_kernel<16>, grid, dim3(kBlock), 0, s, a);
-        break;
-    case 32:
-        hipLaunchKernelGGL(sweep_f64_kernel<32>, grid, dim3(kBlock), 0, s, a);
-        break;
-    default:
+    if (td == 16 && !b3)
+        hipLaunchKernelGGL((sweep_f64_kernel<16, false>), grid, dim3(kBlock), 0, s, a);
+    else if (td == 32 && !b3)
+        hipLaunchKernelGGL((sweep_f64_kernel<32, false>), grid, dim3(kBlock), 0, s, a);
+    else if (td == 16)
+        hipLaunchKernelGGL((sweep_f64_kernel<16, true>), grid, dim3(kBlock), 0, s, a);
+    else if (td == 32)
+        hipLaunchKernelGGL((sweep_f64_kernel<32, true>), grid, dim3(kBlock), 0, s, a);
+    else
         return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
@@ -726,7 +892,7 @@ __device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
     return r;
 }
 
-template <int TD>
+template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
 {
     const int chunk = blockIdx.x;
@@ -786,8 +952,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
         asm volatile("" : "+v"(zoff));
         const float2 *dp = d2s + zoff;
         if ((mk >> lane) & 1ull) {
-            const KQ q64 = kq_setup(a, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy, cxt[i],
-                                    sxt[i], cyt[j], syt[j]);
+            const KQ q64 = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx,
+                                        cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
             const KQf r = kq_setup_f32(q64, T, invT);
             const float wf = (float)mirror_weight(kr, j, a.Ly);
             ++n_direct;
@@ -834,20 +1000,20 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     }
 }
 
-hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G,
+hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                              hipStream_t s)
 {
     dim3 grid(a.n_chunks, n_dtiles, a.nbq * G);
-    switch (td) {
-    case 16:
-        hipLaunchKernelGGL(sweep_f32c_kernel<16>, grid, dim3(kBlock), 0, s, a);
-        break;
-    case 32:
-        hipLaunchKernelGGL(sweep_f32c_kernel<32>, grid, dim3(kBlock), 0, s, a);
-        break;
-    default:
+    if (td == 16 && !b3)
+        hipLaunchKernelGGL((sweep_f32c_kernel<16, false>), grid, dim3(kBlock), 0, s, a);
+    else if (td == 32 && !b3)
+        hipLaunchKernelGGL((sweep_f32c_kernel<32, false>), grid, dim3(kBlock), 0, s, a);
+    else if (td == 16)
+        hipLaunchKernelGGL((sweep_f32c_kernel<16, true>), grid, dim3(kBlock), 0, s, a);
+    else if (td == 32)
+        hipLaunchKernelGGL((sweep_f32c_kernel<32, true>), grid, dim3(kBlock), 0, s, a);
+    else
         return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 
@@ -939,7 +1105,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     const double x0 = *r.d2c;
     // 0 * q is 0 for finite q and NaN for NaN q: a NaN momentum poisons the row
     const double qpoison = 0.0 * r.q[2 * iq] + 0.0 * r.q[2 * iq + 1];
-    const double V = slot ? r.Vs[1] : r.Vs[0];
+    const double V = r.Vs[slot];
     double *out = r.omega + orow * r.n_delta;
     const double *pp = r.part + row * r.n_chunks * r.n_delta_pad;
 

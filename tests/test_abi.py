@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def header_functions():
     text = open(os.path.join(ROOT, "include", "omega.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(omega_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(omega3?_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_expected_entry_points():
@@ -33,7 +33,7 @@ def test_strerror_and_version():
     assert _abi.strerror(_abi.OMEGA_OK) == "success"
     assert _abi.strerror(_abi.OMEGA_E_WORKSPACE) == "workspace too small"
     assert _abi.strerror(12345) == "unknown error code"
-    assert _abi.load().omega_version() == 1
+    assert _abi.load().omega_version() == 2
 
 
 def _ws(pts, nd=8, nq=3, bands=3, prec=0, grad=0):
@@ -124,6 +124,53 @@ def test_argmin_and_grad_validation_errors():
                         FAKE, None) == _abi.OMEGA_E_INVAL
     assert L.omega_grad(ctypes.byref(m), p, 1, FAKE, FAKE, 3, FAKE, 8, FAKE, FAKE, FAKE,
                         FAKE, None) == _abi.OMEGA_E_WORKSPACE
+
+
+def _grid3(model=None, pts=None, delta=FAKE, nd=8, q=FAKE, nq=3, bands=7, prec=0, ws=FAKE,
+           ws_bytes=1 << 40, out=FAKE):
+    L = _abi.load()
+    m = _abi.make_model3(model or W.DAGHOFER_MODEL)
+    pts = pts if pts is not None else [(0.0, 0.001, 16, 16)]
+    p = _abi.make_points(pts)
+    return L.omega3_grid(ctypes.byref(m), p, len(pts), delta, nd, q, nq, bands, prec, ws,
+                         ws_bytes, out, None)
+
+
+def test_three_band_validation_errors():
+    E = _abi.OMEGA_E_INVAL
+    M3 = W.DAGHOFER_MODEL
+    assert _grid3(bands=0) == E
+    assert _grid3(bands=8) == E
+    assert _grid3(model=dict(M3, V=(0.0, -1.0, -1.0))) == E
+    # V of an unselected band is not used
+    assert _grid3(model=dict(M3, V=(0.0, -1.0, -1.0)), bands=6, ws_bytes=16) == \
+        _abi.OMEGA_E_WORKSPACE
+    assert _grid3(model=dict(M3, eps0=float("inf"))) == E
+    assert _grid3(model=dict(M3, t=(float("nan"),) + tuple(M3["t"][1:]))) == E
+    assert _grid3(pts=[(0.0, 0.01, 1, 16)]) == E
+    assert _grid3(out=None) == E
+    assert _grid3(prec=3) == E
+    assert _grid3(ws_bytes=16) == _abi.OMEGA_E_WORKSPACE
+    L = _abi.load()
+    m = _abi.make_model3(M3)
+    p = _abi.make_points([(0.0, 0.001, 16, 16)])
+    assert L.omega3_argmin(ctypes.byref(m), p, 1, FAKE, 8, FAKE, 3, 7, 0, -1.0, FAKE, 1 << 40,
+                           FAKE, FAKE, None, None, None) == E
+    assert L.omega3_bands(ctypes.byref(m), 1, 16, FAKE, 1 << 20, FAKE, None) == E
+    assert L.omega3_bands(ctypes.byref(m), 16, 16, FAKE, 8, FAKE, None) == \
+        _abi.OMEGA_E_WORKSPACE
+    assert L.omega3_bands(ctypes.byref(m), 16, 16, FAKE, 1 << 20, None, None) == E
+
+
+def test_three_band_workspace_holds_band_table():
+    L = _abi.load()
+    pts = [(0.0, 0.001, 64, 64)]
+    p = _abi.make_points(pts)
+    w3 = L.omega3_workspace_bytes(p, 1, 8, 3, 7, 0)
+    w1 = L.omega3_workspace_bytes(p, 1, 8, 3, 1, 0)
+    assert w3 > w1 > 3 * 64 * 64 * 8
+    assert L.omega3_workspace_bytes(p, 1, 8, 3, 0, 0) == 0
+    assert L.omega3_workspace_bytes(p, 1, 8, 3, 8, 0) == 0
 
 
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
