@@ -68,10 +68,15 @@ def cpu_baseline(cfg, rows_per_band):
     sel = np.unique(np.linspace(0, len(q) - 1, rows_per_band).round().astype(int))
     pts = cfg["pts"]
     t0 = time.perf_counter()
-    oracle.omega_grid(W.DEFAULT_MODEL, pts, cfg["delta"], q[sel], cfg["bands"])
+    if "model" in cfg:       # three-band model (App. B)
+        from oracle import three_band
+        three_band.omega_grid(cfg["model"], pts, cfg["delta"], q[sel], cfg["bands"])
+        nb = len(three_band.band_list(cfg["bands"]))
+    else:
+        oracle.omega_grid(W.DEFAULT_MODEL, pts, cfg["delta"], q[sel], cfg["bands"])
+        nb = 2 if cfg["bands"] == 3 else 1
     dt = time.perf_counter() - t0
     n_k = pts[0][2] * pts[0][3]
-    nb = 2 if cfg["bands"] == 3 else 1
     evals = n_k * len(cfg["delta"]) * len(sel) * nb
     return {"value": evals / dt, "unit": "evals/s", "cores": oracle.max_threads(),
             "kind": "oracle",
@@ -268,26 +273,29 @@ def main():
     L = _abi.load()
 
     cfg = W.config(args.workload)
+    three = "model" in cfg      # three-band model of App. B
     pts = cfg["pts"]
     prec = api.OMEGA_FP64 if args.precision == "fp64" else api.OMEGA_FP32_COMP
     bands = cfg["bands"]
-    nb = _abi.n_bands(bands)
+    nb = _abi.n_bands3(bands) if three else _abi.n_bands(bands)
+    wsb = api.workspace_bytes3 if three else api.workspace_bytes
+    argmin_fn = L.omega3_argmin if three else L.omega_argmin
     delta = torch.as_tensor(cfg["delta"], dtype=torch.float64, device=dev)
     q = torch.as_tensor(cfg["q"], dtype=torch.float64, device=dev).contiguous()
     n_d, n_q = delta.numel(), q.shape[0]
     n_pts = len(pts)
-    ws_bytes = api.workspace_bytes(pts, n_d, n_q, bands, prec)
+    ws_bytes = wsb(pts, n_d, n_q, bands, prec)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
     idx = torch.empty((n_pts, nb, 2), dtype=torch.int32, device=dev)
     omin = torch.empty((n_pts, nb), dtype=torch.float64, device=dev)
     rows = torch.empty((n_pts, nb, n_q), dtype=torch.int32, device=dev)
     om = torch.empty((n_pts, nb, n_q, n_d), dtype=torch.float64, device=dev)
-    m = _abi.make_model(W.DEFAULT_MODEL)
+    m = _abi.make_model3(cfg["model"]) if three else _abi.make_model(W.DEFAULT_MODEL)
     p = _abi.make_points(pts)
     stream = torch.cuda.current_stream()
 
     def step():
-        rc = L.omega_argmin(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d, q.data_ptr(),
+        rc = argmin_fn(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d, q.data_ptr(),
                             n_q, bands, prec, 1e-11, ws.data_ptr(), ws_bytes, idx.data_ptr(),
                             omin.data_ptr(), rows.data_ptr(), om.data_ptr(), stream.cuda_stream)
         if rc != 0:
@@ -352,9 +360,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: L={pts[0][2]}x{pts[0][3]}, {n_d} Delta in "
-                               f"[0,0.6], {n_q} Q=(j pi/512,0), {nb} bands, h={pts[0][0]}, "
-                               f"T={pts[0][1]}, full grid + argmin",
+        "config": {"workload": f"{args.workload}: "
+                               f"{'three-band (App. B), ' if three else ''}"
+                               f"L={pts[0][2]}x{pts[0][3]}, {n_d} Delta in "
+                               f"[0,{cfg['delta'][-1]:g}], {n_q} Q=(j*{cfg['q'][1][0]:.6g},0), "
+                               f"{nb} bands, h={pts[0][0]}, T={pts[0][1]}, full grid + argmin",
                    "precision": args.precision, "evals_per_step": evals_step,
                    "folded_terms_per_step": evaluated, "direct_terms_per_step": direct},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -369,11 +379,11 @@ def main():
         om64 = om.clone()
         idx64 = idx.clone()
         prec32 = api.OMEGA_FP32_COMP
-        ws32_bytes = api.workspace_bytes(pts, n_d, n_q, bands, prec32)
+        ws32_bytes = wsb(pts, n_d, n_q, bands, prec32)
         ws32 = torch.empty(ws32_bytes, dtype=torch.uint8, device=dev)
 
         def step32():
-            rc = L.omega_argmin(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d,
+            rc = argmin_fn(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d,
                                 q.data_ptr(), n_q, bands, prec32, 1e-11, ws32.data_ptr(),
                                 ws32_bytes, idx.data_ptr(), omin.data_ptr(), rows.data_ptr(),
                                 om.data_ptr(), stream.cuda_stream)

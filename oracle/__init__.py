@@ -88,6 +88,12 @@ def lib():
         L.oracle_omega_row_tab.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            dp, ctypes.c_int, dp]
+        L.oracle_pair_chi_tab.restype = ctypes.c_int
+        L.oracle_pair_chi_tab.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, dp]
+        L.oracle_pair_chi.restype = ctypes.c_int
+        L.oracle_pair_chi.argtypes = [mp, pp, ctypes.c_int, dp, ctypes.c_int, ctypes.c_int, dp]
         L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = L
@@ -217,3 +223,16 @@ def max_threads() -> int:
 
 def set_threads(n: int) -> None:
     lib().oracle_set_threads(int(n))
+
+
+def pair_chi(model, pts, q, bands: int = BAND_BOTH) -> np.ndarray:
+    """Static Cooper-pair susceptibility of App. C, two-band model:
+    [n_pts][nb][nb][n_q] = chi_{eps eps'}(q) over the selected bands."""
+    m = _model(model)
+    p = _points(pts)
+    qq = _f64(q).reshape(-1, 2)
+    nb = n_bands(bands)
+    out = np.empty((len(pts), nb, nb, qq.shape[0]), np.float64)
+    _check(lib().oracle_pair_chi(ctypes.byref(m), p, len(pts), _dp(qq), qq.shape[0], bands,
+                                 _dp(out)))
+    return out

@@ -313,6 +313,105 @@ int oracle_omega_row_tab(const double *ek, const double *eqk, int Lx, int Ly,
     return OR_OK;
 }
 
+/* ------------------------------------------- App. C pair susceptibility */
+
+/* Static Cooper-pair susceptibility of App. C at omega -> 0: with
+ * E1 = E_{eps k up}, E2 = E_{eps',-k-q,down} and f the Fermi function the
+ * retarded pair propagator gives the summand
+ *   F(E1, E2) = (1 - f(E1) - f(E2)) / (E1 + E2)
+ *             = (tanh(E1/2T) + tanh(E2/2T)) / (2 (E1 + E2)),
+ * whose E1 + E2 -> 0 limit is 1 / (4 T cosh^2(E1/2T)).  Near that limit
+ * (|E1 + E2| <= T) the sum of tanh is rewritten with
+ * tanh a + tanh b = sinh(a + b) / (cosh a cosh b).  T = 0: the step
+ * function, (sgn E1 + sgn E2) / (2 (E1 + E2)), and 0 where E1 + E2 = 0. */
+static double pair_term(double E1, double E2, double T)
+{
+    double S = E1 + E2;
+    if (T == 0.0) {
+        if (S == 0.0)
+            return 0.0;
+        double s1 = (E1 > 0.0) - (E1 < 0.0), s2 = (E2 > 0.0) - (E2 < 0.0);
+        return (s1 + s2) / (2.0 * S);
+    }
+    double x1 = E1 / (2.0 * T), x2 = E2 / (2.0 * T), u = x1 + x2;
+    if (fabs(u) > 0.5)
+        return (tanh(x1) + tanh(x2)) / (2.0 * S);
+    double shc = u == 0.0 ? 1.0 : sinh(u) / u;
+    return shc / (4.0 * T * cosh(x1) * cosh(x2));
+}
+
+/* chi_{eps eps'}(q) of App. C from tabulated energies: e1[i*Ly + j] =
+ * E_eps(k), e2[i*Ly + j] = E_eps'(-k - q) at kx = 2 pi i/Lx, ky = 2 pi j/Ly;
+ * structure factor eta(k) = 4 cos kx cos ky evaluated at -k - q.
+ *   chi = (1/N) sum_k eta(-k-q)^2 F(E1 - mu - h, E2 - mu + h). */
+int oracle_pair_chi_tab(const double *e1, const double *e2, int Lx, int Ly,
+                        double mu, double h, double T, double qx, double qy,
+                        double *out)
+{
+    if (!e1 || !e2 || !out || Lx < 2 || Ly < 2)
+        return OR_EINVAL;
+    if (!isfinite(mu) || !isfinite(h) || !isfinite(T) || T < 0.0)
+        return OR_EINVAL;
+    nsum acc = {0.0, 0.0};
+    for (int i = 0; i < Lx; ++i) {
+        double kx = 2.0 * OR_PI * i / Lx;
+        for (int j = 0; j < Ly; ++j) {
+            double ky = 2.0 * OR_PI * j / Ly;
+            long k = (long)i * Ly + j;
+            double eta = 4.0 * cos(-kx - qx) * cos(-ky - qy);
+            nadd(&acc, eta * eta * pair_term(e1[k] - (mu + h), e2[k] - (mu - h), T));
+        }
+    }
+    *out = nval(&acc) / ((double)Lx * Ly);
+    return OR_OK;
+}
+
+/* chi_{eps eps'}(q) of the two-band model for every point, band pair and q:
+ * out[((p * nb + a) * nb + b) * n_q + iq], a = eps, b = eps' over the
+ * selected bands (bands mask as in oracle_omega_grid). */
+int oracle_pair_chi(const or_model *m, const or_point *pts, int n_pts,
+                    const double *q, int n_q, int bands, double *out)
+{
+    if (check_model(m) || !pts || !q || !out || n_pts <= 0 || n_q <= 0)
+        return OR_EINVAL;
+    if (bands < 1 || bands > 3)
+        return OR_EINVAL;
+    for (int p = 0; p < n_pts; ++p)
+        if (check_point(&pts[p]))
+            return OR_EINVAL;
+    int list[2];
+    int nb = band_list(bands, list);
+    for (int p = 0; p < n_pts; ++p) {
+        const int Lx = pts[p].Lx, Ly = pts[p].Ly;
+        const long N = (long)Lx * Ly;
+        double *e1 = (double *)malloc(sizeof(double) * N);
+        double *e2 = (double *)malloc(sizeof(double) * N);
+        int rc = OR_OK;
+        for (int a = 0; a < nb && rc == OR_OK; ++a)
+            for (int b = 0; b < nb && rc == OR_OK; ++b)
+                for (int iq = 0; iq < n_q && rc == OR_OK; ++iq) {
+                    double qx = q[2 * iq], qy = q[2 * iq + 1];
+#pragma omp parallel for schedule(static)
+                    for (int i = 0; i < Lx; ++i) {
+                        double kx = 2.0 * OR_PI * i / Lx;
+                        for (int j = 0; j < Ly; ++j) {
+                            double ky = 2.0 * OR_PI * j / Ly;
+                            e1[(long)i * Ly + j] = oracle_band_energy(m, list[a], kx, ky);
+                            e2[(long)i * Ly + j] =
+                                oracle_band_energy(m, list[b], -kx - qx, -ky - qy);
+                        }
+                    }
+                    rc = oracle_pair_chi_tab(e1, e2, Lx, Ly, m->mu, pts[p].h, pts[p].T, qx,
+                                             qy, out + ((long)(p * nb + a) * nb + b) * n_q + iq);
+                }
+        free(e1);
+        free(e2);
+        if (rc != OR_OK)
+            return rc;
+    }
+    return OR_OK;
+}
+
 /* ------------------------------------------------------ Alg. 1 search */
 
 /* Alg. 1, the two "find and save" steps, on a given grid [n_set][n_q][n_delta]

@@ -99,3 +99,30 @@ def omega_grid(model, pts, delta, q, bands_mask: int = BAND_ALL) -> np.ndarray:
                                               _dp(row)))
                 out[p, ib, iq] = row
     return out
+
+
+def pair_chi(model, pts, q, bands_mask: int = BAND_ALL) -> np.ndarray:
+    """Static Cooper-pair susceptibility of App. C for the three-band model:
+    [n_pts][nb][nb][n_q] = chi_{eps eps'}(q), E_eps'(-k-q) diagonalised at
+    -k-q."""
+    qq = _f64(q).reshape(-1, 2)
+    bl = band_list(bands_mask)
+    out = np.empty((len(pts), len(bl), len(bl), qq.shape[0]), np.float64)
+    L = lib()
+    for p, (h, T, Lx, Ly) in enumerate(pts):
+        kx = 2 * np.pi * np.arange(Lx) / Lx
+        ky = 2 * np.pi * np.arange(Ly) / Ly
+        KX, KY = np.meshgrid(kx, ky, indexing="ij")
+        ek = bands(model, KX, KY)
+        for iq in range(qq.shape[0]):
+            e2 = bands(model, -KX - qq[iq, 0], -KY - qq[iq, 1])
+            for ia, a in enumerate(bl):
+                for ib, b in enumerate(bl):
+                    x = np.ascontiguousarray(ek[..., a])
+                    y = np.ascontiguousarray(e2[..., b])
+                    r = np.empty(1, np.float64)
+                    _check(L.oracle_pair_chi_tab(_dp(x), _dp(y), int(Lx), int(Ly),
+                                                 float(model["mu"]), float(h), float(T),
+                                                 float(qq[iq, 0]), float(qq[iq, 1]), _dp(r)))
+                    out[p, ia, ib, iq] = r[0]
+    return out
