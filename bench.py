@@ -335,10 +335,10 @@ def main():
     sweep_ms = [a.elapsed_time(b) for a, b in ev]
     sweep_avg = sum(sweep_ms) / len(sweep_ms)
     evals_step = sum(pt[2] * pt[3] for pt in pts) * n_d * n_q * nb
-    # terms the sweep evaluates: Q on the kx axis sums ky = 0..Ly/2 only (the
-    # mirror rows are equal); the metric still counts the full grid
-    qy = cfg["q"][:, 1]
-    evaluated = sum(pt[2] * ((pt[3] // 2 + 1) * int((qy == 0).sum()) + pt[3] * int((qy != 0).sum()))
+    # terms the sweep visits: a zero component of Q halves that momentum axis
+    # (mirror momenta give equal terms); the metric still counts the full grid
+    evaluated = sum(sum((pt[2] // 2 + 1 if qx == 0 else pt[2]) *
+                        (pt[3] // 2 + 1 if qy == 0 else pt[3]) for qx, qy in cfg["q"])
                     for pt in pts) * n_d * nb
     value = evals_step / (ms_step * 1e-3)
     achieved = OPS_PER_EVAL * direct / (sweep_avg * 1e-3) / 1e12

@@ -186,10 +186,56 @@ int omega3_argmin(const omega3_model *model, const omega_point *pts, int n_pts,
                   size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
                   int32_t *row_idx_dev, double *omega_dev, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Static Cooper-pair susceptibility, App. C, at omega -> 0:
+ *   chi_{eps eps'}(q) = (1/N) sum_k eta(-k-q)^2
+ *                       (1 - f(E_{eps k up}) - f(E_{eps',-k-q,down}))
+ *                       / (E_{eps k up} + E_{eps',-k-q,down}),
+ * f the Fermi function at T, eta(k) = 4 cos kx cos ky (s+- structure factor),
+ * E_{eps k sigma} = E_eps(k) - (mu + sigma h).  Where the two energies sum
+ * to zero the summand takes its limit 1 / (4 T cosh^2(E/2T)).  T = 0 uses
+ * the step function, with 0 where the energies sum to zero.
+ * Output chi_dev [n_pts][nb][nb][n_q] (eps, eps' over the selected bands, in
+ * the band order of the grid calls).  V of the model is not used.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of omega_pair_chi (bands: OMEGA_BAND_* mask); 0 if the
+ * arguments are invalid. */
+size_t omega_chi_workspace_bytes(const omega_point *pts, int n_pts, int n_q, int bands);
+
+/* chi of the two-band model for every point, band pair and q_dev [n_q][2]. */
+int omega_pair_chi(const omega_model *model, const omega_point *pts, int n_pts,
+                   const double *q_dev, int n_q, int bands, void *ws_dev, size_t ws_bytes,
+                   double *chi_dev, void *stream);
+
+/* Workspace bytes of omega3_pair_chi (bands: OMEGA3_BAND_* mask). */
+size_t omega3_chi_workspace_bytes(const omega_point *pts, int n_pts, int n_q, int bands);
+
+/* chi of the three-band model; E(-k-q) from the band table where q lies on
+ * the lattice, else diagonalised. */
+int omega3_pair_chi(const omega3_model *model, const omega_point *pts, int n_pts,
+                    const double *q_dev, int n_q, int bands, void *ws_dev, size_t ws_bytes,
+                    double *chi_dev, void *stream);
+
+/* Pair momenta of the whole zone reduced by symmetry (host only, no GPU
+ * work).  Algorithm 1 scans every Q of the first Brillouin zone; on the
+ * lattice these are Q = (2 pi m/Lx, 2 pi n/Ly).  k -> -k, kx -> -kx and
+ * ky -> -ky (and kx <-> ky when Lx == Ly) map the lattice onto itself and
+ * leave E(k) and eta(k)^2 of both models invariant, so Omega(Q) =
+ * Omega(-qx, qy) = Omega(qx, -qy) (= Omega(qy, qx) on a square lattice).
+ * Writes one representative per orbit, 0 <= m <= Lx/2 and 0 <= n <= Ly/2
+ * (and n <= m on a square lattice), in (m, n) lexicographic order, to
+ * q_host [count][2], and the orbit size (zone momenta sharing its Omega) to
+ * orbit_host [count]; the orbit sizes add up to Lx*Ly.  With q_host == NULL
+ * it only counts.  Returns the count, OMEGA_E_INVAL for a bad lattice or
+ * OMEGA_E_WORKSPACE if capacity is too small. */
+int omega_q_wedge(int Lx, int Ly, double *q_host, int32_t *orbit_host, int capacity);
+
 /* Static description of an OMEGA_* code (never NULL). */
 const char *omega_strerror(int code);
 
-/* Library interface version, currently 2 (2 added the three-band model). */
+/* Library interface version, currently 3 (2 added the three-band model, 3 the
+ * pair susceptibility). */
 int omega_version(void);
 
 /* Timing hook for benchmarks (the paper times the computation part only,

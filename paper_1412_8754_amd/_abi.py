@@ -16,7 +16,8 @@ OMEGA3_BAND_0, OMEGA3_BAND_1, OMEGA3_BAND_2, OMEGA3_BAND_ALL = 1, 2, 4, 7
 EXPORTS = ("omega_workspace_bytes", "omega_grid", "omega_argmin", "omega_grad",
            "omega_strerror", "omega_version", "omega_set_sweep_events",
            "omega_set_sweep_counter", "omega3_bands", "omega3_workspace_bytes",
-           "omega3_grid", "omega3_argmin")
+           "omega3_grid", "omega3_argmin", "omega_chi_workspace_bytes", "omega_pair_chi",
+           "omega3_chi_workspace_bytes", "omega3_pair_chi", "omega_q_wedge")
 
 
 class Model(ctypes.Structure):
@@ -86,6 +87,16 @@ def load() -> ctypes.CDLL:
     L.omega3_workspace_bytes.argtypes = [pp, i32, i32, i32, i32, i32]
     L.omega3_grid.restype = i32
     L.omega3_grid.argtypes = [m3, pp, i32, vp, i32, vp, i32, i32, i32, vp, sz, vp, vp]
+    L.omega_chi_workspace_bytes.restype = sz
+    L.omega_chi_workspace_bytes.argtypes = [pp, i32, i32, i32]
+    L.omega_pair_chi.restype = i32
+    L.omega_pair_chi.argtypes = [mp, pp, i32, vp, i32, i32, vp, sz, vp, vp]
+    L.omega3_chi_workspace_bytes.restype = sz
+    L.omega3_chi_workspace_bytes.argtypes = [pp, i32, i32, i32]
+    L.omega3_pair_chi.restype = i32
+    L.omega3_pair_chi.argtypes = [m3, pp, i32, vp, i32, i32, vp, sz, vp, vp]
+    L.omega_q_wedge.restype = i32
+    L.omega_q_wedge.argtypes = [i32, i32, vp, vp, i32]
     L.omega3_argmin.restype = i32
     L.omega3_argmin.argtypes = [m3, pp, i32, vp, i32, vp, i32, i32, i32, ctypes.c_double,
                                 vp, sz, vp, vp, vp, vp, vp]

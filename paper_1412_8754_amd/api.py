@@ -197,3 +197,63 @@ def argmin3(model, pts, delta, q, bands: int = OMEGA3_BAND_ALL, precision: int =
                          om.data_ptr() if om is not None else None, _stream_ptr(stream))
     _check(rc, "omega3_argmin")
     return idx, omin, row_idx, om
+
+
+# ------------------------------------------------------------- Q wedge
+
+def q_wedge(Lx: int, Ly: int):
+    """Lattice pair momenta of the whole zone reduced by symmetry (host only):
+    returns (q [n][2] float64 numpy, orbit [n] int32 numpy); the orbit sizes
+    add up to Lx * Ly."""
+    import numpy as np
+    L = _abi.load()
+    n = L.omega_q_wedge(int(Lx), int(Ly), None, None, 0)
+    _check(min(n, 0), "omega_q_wedge")
+    q = np.empty((n, 2), np.float64)
+    orbit = np.empty(n, np.int32)
+    rc = L.omega_q_wedge(int(Lx), int(Ly), q.ctypes.data, orbit.ctypes.data, n)
+    _check(min(rc, 0), "omega_q_wedge")
+    return q, orbit
+
+
+# ------------------------------------------------------------- App. C
+
+def pair_chi(model, pts, q, bands: int = OMEGA_BAND_BOTH, device="cuda", workspace=None,
+             stream=None) -> torch.Tensor:
+    """Static Cooper-pair susceptibility of App. C, two-band model:
+    [n_pts][nb][nb][n_q] = chi_{eps eps'}(q)."""
+    L = _abi.load()
+    qq = _dev_f64(q, device, (-1, 2))
+    nb = n_bands(bands)
+    p = make_points(pts)
+    n = L.omega_chi_workspace_bytes(p, len(pts), qq.shape[0], int(bands))
+    if n == 0:
+        raise OmegaError(_abi.OMEGA_E_INVAL, "omega_chi_workspace_bytes")
+    ws = _workspace(int(n), device, workspace)
+    out = torch.empty((len(pts), nb, nb, qq.shape[0]), dtype=torch.float64, device=device)
+    m = make_model(model)
+    rc = L.omega_pair_chi(ctypes.byref(m), p, len(pts), qq.data_ptr(), qq.shape[0], int(bands),
+                          ws.data_ptr(), ws.numel() * ws.element_size(), out.data_ptr(),
+                          _stream_ptr(stream))
+    _check(rc, "omega_pair_chi")
+    return out
+
+
+def pair_chi3(model, pts, q, bands: int = OMEGA3_BAND_ALL, device="cuda", workspace=None,
+              stream=None) -> torch.Tensor:
+    """Static Cooper-pair susceptibility of App. C, three-band model."""
+    L = _abi.load()
+    qq = _dev_f64(q, device, (-1, 2))
+    nb = n_bands3(bands)
+    p = make_points(pts)
+    n = L.omega3_chi_workspace_bytes(p, len(pts), qq.shape[0], int(bands))
+    if n == 0:
+        raise OmegaError(_abi.OMEGA_E_INVAL, "omega3_chi_workspace_bytes")
+    ws = _workspace(int(n), device, workspace)
+    out = torch.empty((len(pts), nb, nb, qq.shape[0]), dtype=torch.float64, device=device)
+    m = make_model3(model)
+    rc = L.omega3_pair_chi(ctypes.byref(m), p, len(pts), qq.data_ptr(), qq.shape[0],
+                           int(bands), ws.data_ptr(), ws.numel() * ws.element_size(),
+                           out.data_ptr(), _stream_ptr(stream))
+    _check(rc, "omega3_pair_chi")
+    return out

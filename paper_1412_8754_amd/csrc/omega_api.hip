@@ -135,6 +135,13 @@ Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
     return r;
 }
 
+// Per-wave capacity of the series pass's tile lists.
+int list_cap(const Tiles &t)
+{
+    const int span = (t.n_tiles + t.n_chunks - 1) / t.n_chunks;
+    return (span + 3) / 4;
+}
+
 Tiles grad_tiles(int Lx, int Ly)
 {
     Tiles r;
@@ -189,7 +196,7 @@ struct GridPlan {
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_mask, off_etab, off_qlat, sweep_bytes;
+        off_mask, off_tlist, off_tcnt, off_etab, off_qlat, sweep_bytes;
 };
 
 // b3: three-band model, which adds the band table [3][Lx][Ly] of the largest
@@ -204,15 +211,17 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.n_delta_pad = p.n_dtiles * p.td;
     p.nbq = nb * n_q;
     p.groups = group_points(pts, n_pts);
-    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0, etab = 0;
+    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0, etab = 0, tlist = 0,
+           tcnt = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
         if (b3)
             etab = std::max(etab, sizeof(double) * 3 * (size_t)g.Lx * g.Ly);
         const size_t rows = (size_t)p.nbq * t.n_chunks;
+        const size_t lcap = list_cap(t);
         const size_t per_point =
             sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots) +
-            sizeof(unsigned long long) * p.nbq * t.n_tiles;
+            sizeof(unsigned long long) * p.nbq * t.n_tiles + sizeof(int) * rows * 4 * (lcap + 1);
         const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
         p.tiles.push_back(t);
         p.batch.push_back(G);
@@ -222,6 +231,8 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         base = std::max(base, sizeof(double) * rows * G);
         mom = std::max(mom, sizeof(double) * rows * kMomentSlots * G);
         mask = std::max(mask, sizeof(unsigned long long) * p.nbq * t.n_tiles * G);
+        tlist = std::max(tlist, sizeof(int) * rows * 4 * lcap * G);
+        tcnt = std::max(tcnt, sizeof(int) * rows * 4 * G);
     }
     p.off_d2 = 0;
     p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 2));
@@ -232,7 +243,9 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_base = p.off_part + align_up(part);
     p.off_mom = p.off_base + align_up(base);
     p.off_mask = p.off_mom + align_up(mom);
-    p.off_etab = p.off_mask + align_up(mask);
+    p.off_tlist = p.off_mask + align_up(mask);
+    p.off_tcnt = p.off_tlist + align_up(tlist);
+    p.off_etab = p.off_tcnt + align_up(tcnt);
     p.off_qlat = p.off_etab + align_up(etab);
     p.sweep_bytes = p.off_qlat + (b3 ? align_up(sizeof(int) * 2 * (size_t)n_q) : 0);
     return p;
@@ -369,6 +382,8 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     unsigned long long *mask = (unsigned long long *)(ws + P.off_mask);
     double *etab = (double *)(ws + P.off_etab);
     int *qlat = (int *)(ws + P.off_qlat);
+    int *tlist = (int *)(ws + P.off_tlist);
+    int *tcnt = (int *)(ws + P.off_tcnt);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
         return OMEGA_E_HIP;
     if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
@@ -398,6 +413,8 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.base_part = base;
     a.mpart = mom;
     a.mask = mask;
+    a.tlist = tlist;
+    a.tcnt = tcnt;
     a.count = g_sweep_count;
 
     RowArgs r;
@@ -432,6 +449,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         a.TY = t.TY;
         a.n_tiles = t.n_tiles;
         a.n_chunks = t.n_chunks;
+        a.lcap = list_cap(t);
         r.n_k = (double)g.Lx * g.Ly;
         r.n_chunks = t.n_chunks;
         const int n = (int)g.idx.size();
@@ -501,6 +519,111 @@ int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const dou
     a.omin = omin_dev;
     if (launch_argmin(a, n_pts * nb, s) != hipSuccess)
         return OMEGA_E_HIP;
+    return OMEGA_OK;
+}
+
+// Workspace of a pair-susceptibility call: cos/sin and (three-band) band
+// tables of the largest lattice, Q trig / lattice indices, chunk partials of
+// one point.
+struct ChiPlan {
+    std::vector<Group> groups;
+    std::vector<int> n_chunks, span;   // per group
+    size_t off_trig, off_qtrig, off_etab, off_qlat, off_part, bytes;
+};
+
+ChiPlan plan_chi(const omega_point *pts, int n_pts, int n_q, int nb, bool b3)
+{
+    ChiPlan p;
+    p.groups = group_points(pts, n_pts);
+    const long long pairs_q = (long long)nb * nb * n_q;
+    size_t trig = 0, etab = 0, part = 0;
+    for (const Group &g : p.groups) {
+        const long long n = (long long)g.Lx * g.Ly;
+        long long nc = (kMinWorkgroups + pairs_q - 1) / pairs_q;
+        const long long cap = std::min((n + 1023) / 1024, (long long)kMaxGridZ);
+        nc = std::max(1LL, std::min(nc, cap));
+        p.n_chunks.push_back((int)nc);
+        p.span.push_back((int)((n + nc - 1) / nc));
+        trig = std::max(trig, sizeof(double) * 2 * ((size_t)g.Lx + g.Ly));
+        if (b3)
+            etab = std::max(etab, sizeof(double) * 3 * (size_t)n);
+        part = std::max(part, sizeof(double) * (size_t)(pairs_q * nc));
+    }
+    p.off_trig = 0;
+    p.off_qtrig = align_up(trig);
+    p.off_etab = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
+    p.off_qlat = p.off_etab + align_up(etab);
+    p.off_part = p.off_qlat + (b3 ? align_up(sizeof(int) * 2 * (size_t)n_q) : 0);
+    p.bytes = p.off_part + align_up(part);
+    return p;
+}
+
+bool hoppings_ok(const omega_model *m)
+{
+    return m && isfinite(m->t1) && isfinite(m->t2) && isfinite(m->t3) && isfinite(m->t4) &&
+           isfinite(m->mu);
+}
+
+int run_chi(const ModelDesc &md, const omega_point *pts, int n_pts, const double *q_dev,
+            int n_q, void *ws_dev, size_t ws_bytes, double *chi_dev, void *stream)
+{
+    if (!q_dev || !ws_dev || !chi_dev)
+        return OMEGA_E_INVAL;
+    const ChiPlan P = plan_chi(pts, n_pts, n_q, md.nb, md.b3);
+    if (ws_bytes < P.bytes)
+        return OMEGA_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)ws_dev;
+    double *trig = (double *)(ws + P.off_trig);
+    double *qtrig = (double *)(ws + P.off_qtrig);
+    double *etab = (double *)(ws + P.off_etab);
+    int *qlat = (int *)(ws + P.off_qlat);
+    double *part = (double *)(ws + P.off_part);
+    if (launch_qtrig(q_dev, n_q, qtrig, s) != hipSuccess)
+        return OMEGA_E_HIP;
+    ChiArgs a;
+    a.hop = md.hop;
+    a.hop3 = md.hop3;
+    for (int k = 0; k < 3; ++k) {
+        const int b = md.list[k < md.nb ? k : 0];
+        a.eps[k] = b ? 1.0 : -1.0;
+        a.band3[k] = b;
+    }
+    a.nb = md.nb;
+    a.mu = md.mu;
+    a.n_q = n_q;
+    a.trig = trig;
+    a.qtrig = qtrig;
+    a.etab = etab;
+    a.qlat = qlat;
+    a.part = part;
+    const int pairs_q = md.nb * md.nb * n_q;
+    for (size_t gi = 0; gi < P.groups.size(); ++gi) {
+        const Group &g = P.groups[gi];
+        if (launch_trig(g.Lx, g.Ly, trig, s) != hipSuccess)
+            return OMEGA_E_HIP;
+        if (md.b3 && (launch_etab(md.hop3, trig, g.Lx, g.Ly, etab, s) != hipSuccess ||
+                      launch_qlat(q_dev, n_q, g.Lx, g.Ly, qlat, s) != hipSuccess))
+            return OMEGA_E_HIP;
+        a.Lx = g.Lx;
+        a.Ly = g.Ly;
+        a.n_chunks = P.n_chunks[gi];
+        a.span = P.span[gi];
+        for (int idx : g.idx) {
+            a.h = pts[idx].h;
+            a.T = pts[idx].T;
+            if (launch_chi(a, md.b3, s) != hipSuccess)
+                return OMEGA_E_HIP;
+            ChiFinishArgs f;
+            f.part = part;
+            f.n_pairs_q = pairs_q;
+            f.n_chunks = a.n_chunks;
+            f.inv_n = 1.0 / ((double)g.Lx * g.Ly);
+            f.out = chi_dev + (size_t)idx * pairs_q;
+            if (launch_chi_finish(f, s) != hipSuccess)
+                return OMEGA_E_HIP;
+        }
+    }
     return OMEGA_OK;
 }
 
@@ -682,6 +805,95 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
     return OMEGA_OK;
 }
 
+size_t omega_chi_workspace_bytes(const omega_point *pts, int n_pts, int n_q, int bands)
+{
+    if (!points_ok(pts, n_pts) || bands < 1 || bands > 3 || n_q <= 0 || n_q > kMaxQ)
+        return 0;
+    int list[2];
+    return plan_chi(pts, n_pts, n_q, slot_bands(bands, list), false).bytes;
+}
+
+int omega_pair_chi(const omega_model *model, const omega_point *pts, int n_pts,
+                   const double *q_dev, int n_q, int bands, void *ws_dev, size_t ws_bytes,
+                   double *chi_dev, void *stream)
+{
+    if (!hoppings_ok(model) || !points_ok(pts, n_pts) || bands < 1 || bands > 3 ||
+        n_q <= 0 || n_q > kMaxQ)
+        return OMEGA_E_INVAL;
+    ModelDesc md{};
+    md.b3 = false;
+    md.nb = slot_bands(bands, md.list);
+    md.mu = model->mu;
+    md.hop = make_hop(model);
+    return run_chi(md, pts, n_pts, q_dev, n_q, ws_dev, ws_bytes, chi_dev, stream);
+}
+
+size_t omega3_chi_workspace_bytes(const omega_point *pts, int n_pts, int n_q, int bands)
+{
+    if (!points_ok(pts, n_pts) || bands < 1 || bands > 7 || n_q <= 0 || n_q > kMaxQ)
+        return 0;
+    int list[3];
+    return plan_chi(pts, n_pts, n_q, slot_bands3(bands, list), true).bytes;
+}
+
+int omega3_pair_chi(const omega3_model *model, const omega_point *pts, int n_pts,
+                    const double *q_dev, int n_q, int bands, void *ws_dev, size_t ws_bytes,
+                    double *chi_dev, void *stream)
+{
+    if (!model3_ok(model, 0) || !points_ok(pts, n_pts) || bands < 1 || bands > 7 ||
+        n_q <= 0 || n_q > kMaxQ)
+        return OMEGA_E_INVAL;
+    return run_chi(describe3(model, bands), pts, n_pts, q_dev, n_q, ws_dev, ws_bytes, chi_dev,
+                   stream);
+}
+
+int omega_q_wedge(int Lx, int Ly, double *q_host, int32_t *orbit_host, int capacity)
+{
+    const omega_point p{0.0, 0.0, Lx, Ly};
+    if (!point_ok(p) || (q_host && (!orbit_host || capacity < 0)))
+        return OMEGA_E_INVAL;
+    const bool square = Lx == Ly;
+    int count = 0;
+    for (int m = 0; m <= Lx / 2; ++m) {
+        for (int n = 0; n <= Ly / 2; ++n) {
+            if (square && n > m)
+                break;
+            if (q_host) {
+                if (count >= capacity)
+                    return OMEGA_E_WORKSPACE;
+                // orbit of (m, n) under the mirrors (and the swap on a square
+                // lattice), as distinct zone indices
+                int seen[8][2];
+                int ns = 0;
+                for (int g = 0; g < (square ? 8 : 4); ++g) {
+                    int a = (g & 1) ? Lx - m : m;
+                    int b = (g & 2) ? Ly - n : n;
+                    a %= Lx;
+                    b %= Ly;
+                    if (g & 4) {
+                        const int t = a;
+                        a = b;
+                        b = t;
+                    }
+                    bool dup = false;
+                    for (int k = 0; k < ns; ++k)
+                        dup = dup || (seen[k][0] == a && seen[k][1] == b);
+                    if (!dup) {
+                        seen[ns][0] = a;
+                        seen[ns][1] = b;
+                        ++ns;
+                    }
+                }
+                q_host[2 * count] = 2.0 * M_PI * m / Lx;
+                q_host[2 * count + 1] = 2.0 * M_PI * n / Ly;
+                orbit_host[count] = ns;
+            }
+            ++count;
+        }
+    }
+    return count;
+}
+
 const char *omega_strerror(int code)
 {
     switch (code) {
@@ -700,7 +912,7 @@ const char *omega_strerror(int code)
     }
 }
 
-int omega_version(void) { return 2; }
+int omega_version(void) { return 3; }
 
 int omega_set_sweep_counter(unsigned long long *count_dev)
 {

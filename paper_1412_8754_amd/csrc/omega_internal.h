@@ -97,6 +97,10 @@ struct SweepArgs {
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments
     unsigned long long *mask;    // [G*nbq][n_tiles] lanes evaluated per Delta
+    int *tlist;          // [G*nbq][n_chunks][4][lcap] tiles with a nonzero mask,
+                         // listed by the series pass per wave
+    int *tcnt;           // [G*nbq][n_chunks][4] list lengths
+    int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
 };
 
@@ -151,6 +155,33 @@ struct GradFinishArgs {
     double *omega, *dDelta, *dq, *dmu;   // [n_pts][nb] ([n_pts][nb][2])
 };
 
+// Static Cooper-pair susceptibility (App. C) of one point: grid
+// (band pair * n_q, chunk); part[(pair * n_q + iq) * n_chunks + chunk].
+struct ChiArgs {
+    Hop hop;
+    Hop3 hop3;
+    double eps[3];        // two-band: band sign per selected band
+    int band3[3];         // three-band: band index per selected band
+    int nb;
+    double mu, h, T;
+    int Lx, Ly;
+    int n_q, n_chunks, span;   // span: momenta per chunk
+    const double *trig;
+    const double *qtrig;  // [n_q][4]
+    const double *etab;   // three-band table [3][Lx][Ly]
+    const int *qlat;      // three-band: lattice index of q, or -1
+    double *part;
+};
+
+struct ChiFinishArgs {
+    const double *part;
+    int n_pairs_q, n_chunks;
+    double inv_n;
+    double *out;          // [nb * nb * n_q] of this point
+};
+
+hipError_t launch_chi(const ChiArgs &a, bool b3, hipStream_t s);
+hipError_t launch_chi_finish(const ChiFinishArgs &a, hipStream_t s);
 hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s);
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
 hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);

@@ -578,34 +578,70 @@ __device__ __forceinline__ void count_direct(unsigned long long *count, int n)
         atomicAdd(count, (unsigned long long)n);
 }
 
-// Momentum range of one workgroup.  With qy == 0 only ky indices 0..Ly/2
-// are visited (mirror symmetry); the tiles of either layout are spread
-// evenly over the same n_chunks workgroups.
+// Momentum range of one workgroup.  Both models have E(-kx, ky) =
+// E(kx, -ky) = E(kx, ky), and eta^2 is even in each component, so with
+// qy == 0 the term at ky equals the term at -ky and only ky indices 0..Ly/2
+// are visited; likewise kx with qx == 0 (Q = 0: a quarter of the zone).  The
+// tiles of the layout are spread evenly over the same n_chunks workgroups.
 struct KRange {
-    bool fold;
+    bool fx, fy;
     int TYw;        // tiles along ky in this layout
-    int jlim;       // ky index bound
+    int ilim, jlim; // kx / ky index bounds
     int begin, end; // tile range of this workgroup
 };
 
-__device__ __forceinline__ KRange k_range(const SweepArgs &a, double qy, int chunk)
+__device__ __forceinline__ KRange k_range(const SweepArgs &a, double qx, double qy, int chunk)
 {
     KRange k;
-    k.fold = (qy == 0.0);
-    const int jf = a.Ly / 2 + 1;
-    k.TYw = k.fold ? (jf + kTileEdge - 1) / kTileEdge : a.TY;
-    k.jlim = k.fold ? jf : a.Ly;
-    const int nt = a.TX * k.TYw;
+    k.fx = (qx == 0.0);
+    k.fy = (qy == 0.0);
+    k.ilim = k.fx ? a.Lx / 2 + 1 : a.Lx;
+    k.jlim = k.fy ? a.Ly / 2 + 1 : a.Ly;
+    const int TXw = (k.ilim + kTileEdge - 1) / kTileEdge;
+    k.TYw = (k.jlim + kTileEdge - 1) / kTileEdge;
+    const int nt = TXw * k.TYw;
     const int span = (nt + a.n_chunks - 1) / a.n_chunks;
     k.begin = chunk * span;
     k.end = min(k.begin + span, nt);
     return k;
 }
 
-// weight of ky index j: 2 when the mirror row Ly - j is folded onto it
-__device__ __forceinline__ double mirror_weight(const KRange &k, int j, int Ly)
+// weight of momentum (i, j): 2 per folded axis whose mirror index L - i is
+// a different momentum
+__device__ __forceinline__ double mirror_weight(const KRange &k, int i, int j, int Lx, int Ly)
 {
-    return (k.fold && j != 0 && 2 * j != Ly) ? 2.0 : 1.0;
+    const double wx = (k.fx && i != 0 && 2 * i != Lx) ? 2.0 : 1.0;
+    const double wy = (k.fy && j != 0 && 2 * j != Ly) ? 2.0 : 1.0;
+    return wx * wy;
+}
+
+// The listed tiles of one (batch point, band, Q) and chunk: the four wave
+// lists of the series pass, concatenated.
+struct TileList {
+    const int *base;
+    int lcap;
+    int c0, c1, c2, total;   // c0, c0 + c1, c0 + c1 + c2, all four
+};
+
+__device__ __forceinline__ TileList tile_list(const SweepArgs &a, int bz, int chunk)
+{
+    TileList t;
+    const size_t row = (size_t)bz * a.n_chunks + chunk;
+    const int *cnt = a.tcnt + row * 4;
+    t.base = a.tlist + row * 4 * a.lcap;
+    t.lcap = a.lcap;
+    t.c0 = cnt[0];
+    t.c1 = t.c0 + cnt[1];
+    t.c2 = t.c1 + cnt[2];
+    t.total = t.c2 + cnt[3];
+    return t;
+}
+
+__device__ __forceinline__ int listed_tile(const TileList &t, int e)
+{
+    const int seg = (e >= t.c0) + (e >= t.c1) + (e >= t.c2);
+    const int start = seg == 0 ? 0 : (seg == 1 ? t.c0 : (seg == 2 ? t.c1 : t.c2));
+    return t.base[seg * t.lcap + (e - start)];
 }
 
 // Per-(k, Q) pass over one (band, Q, point) and momentum chunk, shared by
@@ -616,7 +652,8 @@ __device__ __forceinline__ double mirror_weight(const KRange &k, int j, int Ly)
 //     sum w (R0 - |s|), as |s| - |d| is part of P(0)) and
 //     M_n = sum w R0 (eta^2/R0^2)^n;
 //   - for every 8 x 8 tile, the ballot of lanes the per-Delta sweep must
-//     evaluate directly.
+//     evaluate directly, and per wave the list of tiles with a nonzero ballot
+//     (the sweeps walk these lists instead of scanning every mask).
 // Grid (chunk, band*Q + nbq*g).
 template <bool B3>
 __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
@@ -630,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const double qy = a.q[2 * iq + 1];
-    const KRange kr = k_range(a, qy, chunk);
+    const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
     const PointRec pt = a.pts[g];
     const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
     const double T = pt.T;
@@ -645,6 +682,8 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
     const double *cyt = a.trig + 2 * a.Lx;
     const double *syt = cyt + a.Ly;
     unsigned long long *mask = a.mask + (size_t)blockIdx.y * a.n_tiles;
+    int *tl = a.tlist + (((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave) * a.lcap;
+    int n_listed = 0;
     double mom[kMomentSlots];
 #pragma unroll
     for (int n = 0; n < kMomentSlots; ++n)
@@ -657,10 +696,10 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
         const int i = ti * kTileEdge + li;
         const int j = tj * kTileEdge + lj;
         bool direct = false;
-        if (i < a.Lx && j < kr.jlim) {
+        if (i < kr.ilim && j < kr.jlim) {
             const KQ r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy,
                                       sqy, cxt[i], sxt[i], cyt[j], syt[j]);
-            const double w = mirror_weight(kr, j, a.Ly);
+            const double w = mirror_weight(kr, i, j, a.Lx, a.Ly);
             const double A0 = r.as - r.m;
             double base = r.base;
             if (!fp64) {
@@ -692,7 +731,14 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
         const unsigned long long ballot = __ballot(direct);
         if (lane == 0)
             mask[tile] = ballot;
+        if (ballot != 0ull) {
+            if (lane == 0)
+                tl[n_listed] = tile;
+            ++n_listed;
+        }
     }
+    if (lane == 0)
+        a.tcnt[((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave] = n_listed;
     __shared__ double red[4][64];
     __shared__ double bred[4];
     const double bv = wave_sum(bs + bc);
@@ -738,7 +784,7 @@ void sweep_f64_kernel(const SweepArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const double qy = a.q[2 * iq + 1];
-    const KRange kr = k_range(a, qy, chunk);
+    const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
     const PointRec pt = a.pts[g];
     const double mu_up = a.mu + pt.h;          // spin up: E - mu - h
     const double mu_dn = a.mu - pt.h;          // spin down: E - mu + h
@@ -772,10 +818,10 @@ void sweep_f64_kernel(const SweepArgs a)
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
 
-    for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+    const TileList tl = tile_list(a, blockIdx.z, chunk);
+    for (int e = wave; e < tl.total; e += 4) {
+        const int tile = listed_tile(tl, e);
         const unsigned long long mk = mask[tile];
-        if (mk == 0ull)
-            continue;
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
@@ -788,7 +834,7 @@ void sweep_f64_kernel(const SweepArgs a)
         if ((mk >> lane) & 1ull) {
             KQ r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
                                 cxt[i], sxt[i], cyt[j], syt[j]);
-            const double w = mirror_weight(kr, j, a.Ly);
+            const double w = mirror_weight(kr, i, j, a.Lx, a.Ly);
             const double wT = w * T;
             ++n_direct;
             // R^2 >= 1e-300 keeps the reciprocal square root finite; the
@@ -905,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const double qy = a.q[2 * iq + 1];
-    const KRange kr = k_range(a, qy, chunk);
+    const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
     const PointRec pt = a.pts[g];
     const double mu_up = a.mu + pt.h;
     const double mu_dn = a.mu - pt.h;
@@ -940,10 +986,10 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
     const int li = lane >> 3, lj = lane & 7;
 
-    for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+    const TileList tl = tile_list(a, blockIdx.z, chunk);
+    for (int e = wave; e < tl.total; e += 4) {
+        const int tile = listed_tile(tl, e);
         const unsigned long long mk = mask[tile];
-        if (mk == 0ull)
-            continue;
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
@@ -955,7 +1001,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
             const KQ q64 = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx,
                                         cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
             const KQf r = kq_setup_f32(q64, T, invT);
-            const float wf = (float)mirror_weight(kr, j, a.Ly);
+            const float wf = (float)mirror_weight(kr, i, j, a.Lx, a.Ly);
             ++n_direct;
             const bool hot0 = r.P0 != 0.0f;
             const bool pos = r.A0 >= 0.0f;
@@ -1014,6 +1060,133 @@ hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bo
         hipLaunchKernelGGL((sweep_f32c_kernel<32, true>), grid, dim3(kBlock), 0, s, a);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- pair susceptibility
+
+// Summand of the static Cooper-pair susceptibility of App. C,
+// F = (1 - f(E1) - f(E2)) / (E1 + E2), f the Fermi function.  With
+// a = |E1|/2T, b = |E2|/2T and u = (E1 + E2)/2T, |u| <= a + b, and
+// tanh x1 + tanh x2 = sinh(u) sech x1 sech x2,
+//   F = (e^{|u|-a-b} - e^{-|u|-a-b}) / (2|u|) / (T (1 + e^{-2a}) (1 + e^{-2b})),
+// every exponent <= 0; for |u| < 1/2 the difference is e^{-|u|-a-b}
+// expm1(2|u|) (the limit |u| -> 0 is e^{-a-b}).  T = 0: the step function,
+// (sgn E1 + sgn E2) / (2 (E1 + E2)), 0 where E1 + E2 = 0.
+__device__ __forceinline__ double pair_summand(double E1, double E2, double T, double invT)
+{
+    if (T == 0.0) {
+        const double S = E1 + E2;
+        if (S == 0.0)
+            return 0.0;
+        const double sg = (double)((E1 > 0.0) - (E1 < 0.0)) + (double)((E2 > 0.0) - (E2 < 0.0));
+        return sg / (2.0 * S);
+    }
+    const double a = 0.5 * fabs(E1) * invT;
+    const double b = 0.5 * fabs(E2) * invT;
+    const double au = fabs(0.5 * (E1 + E2) * invT);
+    double num;
+    if (au < 0.5)
+        num = au == 0.0 ? exp(-a - b) : exp(-au - a - b) * (expm1(2.0 * au) / (2.0 * au));
+    else
+        num = (exp(au - a - b) - exp(-au - a - b)) / (2.0 * au);
+    return num / (T * (1.0 + exp(-2.0 * a)) * (1.0 + exp(-2.0 * b)));
+}
+
+// chi_{eps eps'}(q) partial sums over one chunk of momenta:
+//   sum_k eta(-k-q)^2 F(E_eps(k) - mu - h, E_eps'(-k-q) - mu + h),
+// eta = 4 cos kx cos ky (App. C).  E(-p) = E(p) for both models, so the
+// partner energy is taken at p = k + q (angle addition; three-band: table
+// index of k + q on the lattice, else diagonalised).
+template <bool B3>
+__global__ __launch_bounds__(kBlock) void chi_kernel(const ChiArgs a)
+{
+    const int pq = blockIdx.x;                 // (pair, q)
+    const int chunk = blockIdx.y;
+    const int pair = pq / a.n_q;
+    const int iq = pq - pair * a.n_q;
+    const int ia = pair / a.nb, ib = pair - (pair / a.nb) * a.nb;
+    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+    const double invT = a.T > 0.0 ? 1.0 / a.T : 0.0;
+    const double mu_up = a.mu + a.h, mu_dn = a.mu - a.h;
+    const double *cxt = a.trig, *sxt = a.trig + a.Lx;
+    const double *cyt = a.trig + 2 * a.Lx, *syt = cyt + a.Ly;
+    const long long n = (long long)a.Lx * a.Ly;
+    const long long k0 = (long long)chunk * a.span;
+    const long long k1 = k0 + a.span < n ? k0 + a.span : n;
+    double s = 0.0, c = 0.0;
+    for (long long k = k0 + threadIdx.x; k < k1; k += kBlock) {
+        const int i = (int)(k / a.Ly);
+        const int j = (int)(k - (long long)i * a.Ly);
+        const double cx = cxt[i], sx = sxt[i], cy = cyt[j], sy = syt[j];
+        // p = k + q
+        const double cpx = fma(cx, cqx, -(sx * sqx));
+        const double spx = fma(sx, cqx, cx * sqx);
+        const double cpy = fma(cy, cqy, -(sy * sqy));
+        const double spy = fma(sy, cqy, cy * sqy);
+        double E1, E2;
+        if constexpr (!B3) {
+            E1 = band_energy(a.hop, a.eps[ia], cx, sx, cy, sy);
+            E2 = band_energy(a.hop, a.eps[ib], cpx, spx, cpy, spy);
+        } else {
+            const double *Ea = a.etab + (size_t)a.band3[ia] * n;
+            const double *Eb = a.etab + (size_t)a.band3[ib] * n;
+            E1 = Ea[k];
+            const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
+            if (mx >= 0 && my >= 0) {
+                int ii = i + mx;
+                ii -= ii >= a.Lx ? a.Lx : 0;
+                int jj = j + my;
+                jj -= jj >= a.Ly ? a.Ly : 0;
+                E2 = Eb[(size_t)ii * a.Ly + jj];
+            } else {
+                double ev[3];
+                eig3(a.hop3, cpx, spx, cpy, spy, (cpx - spx) * (cpx + spx),
+                     (cpy - spy) * (cpy + spy), ev);
+                const int bb = a.band3[ib];
+                E2 = bb == 0 ? ev[0] : (bb == 1 ? ev[1] : ev[2]);
+            }
+        }
+        const double eta = 4.0 * cpx * cpy;
+        neumaier(s, c, eta * eta * pair_summand(E1 - mu_up, E2 - mu_dn, a.T, invT));
+    }
+    __shared__ double red[4];
+    const double v = wave_sum(s + c);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        a.part[(size_t)pq * a.n_chunks + chunk] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+hipError_t launch_chi(const ChiArgs &a, bool b3, hipStream_t s)
+{
+    const dim3 grid(a.nb * a.nb * a.n_q, a.n_chunks);
+    if (b3)
+        hipLaunchKernelGGL(chi_kernel<true>, grid, dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(chi_kernel<false>, grid, dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+// Fixed-order Neumaier sum of the chunk partials of every (pair, q), / N.
+__global__ void chi_finish_kernel(const ChiFinishArgs a)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n_pairs_q)
+        return;
+    double s = 0.0, c = 0.0;
+    const double *p = a.part + (size_t)t * a.n_chunks;
+    for (int ch = 0; ch < a.n_chunks; ++ch)
+        neumaier(s, c, p[ch]);
+    a.out[t] = (s + c) * a.inv_n;
+}
+
+hipError_t launch_chi_finish(const ChiFinishArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(chi_finish_kernel, dim3((a.n_pairs_q + kBlock - 1) / kBlock),
+                       dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ def test_strerror_and_version():
     assert _abi.strerror(_abi.OMEGA_OK) == "success"
     assert _abi.strerror(_abi.OMEGA_E_WORKSPACE) == "workspace too small"
     assert _abi.strerror(12345) == "unknown error code"
-    assert _abi.load().omega_version() == 2
+    assert _abi.load().omega_version() == 3
 
 
 def _ws(pts, nd=8, nq=3, bands=3, prec=0, grad=0):
@@ -171,6 +171,31 @@ def test_three_band_workspace_holds_band_table():
     assert w3 > w1 > 3 * 64 * 64 * 8
     assert L.omega3_workspace_bytes(p, 1, 8, 3, 0, 0) == 0
     assert L.omega3_workspace_bytes(p, 1, 8, 3, 8, 0) == 0
+
+
+def test_pair_chi_validation_errors():
+    L = _abi.load()
+    m = _abi.make_model(W.DEFAULT_MODEL)
+    m3 = _abi.make_model3(W.DAGHOFER_MODEL)
+    pts = [(0.0, 0.01, 16, 16)]
+    p = _abi.make_points(pts)
+    E = _abi.OMEGA_E_INVAL
+    need = L.omega_chi_workspace_bytes(p, 1, 3, 3)
+    assert need > 0 and L.omega3_chi_workspace_bytes(p, 1, 3, 7) > need
+    assert L.omega_chi_workspace_bytes(p, 1, 0, 3) == 0
+    assert L.omega_chi_workspace_bytes(p, 1, 3, 4) == 0
+    assert L.omega_pair_chi(ctypes.byref(m), p, 1, FAKE, 3, 0, FAKE, 1 << 40, FAKE, None) == E
+    assert L.omega_pair_chi(ctypes.byref(m), p, 1, None, 3, 3, FAKE, 1 << 40, FAKE, None) == E
+    assert L.omega_pair_chi(ctypes.byref(m), p, 1, FAKE, 3, 3, FAKE, 1 << 40, None, None) == E
+    assert L.omega_pair_chi(ctypes.byref(m), p, 1, FAKE, 3, 3, FAKE, 8, FAKE, None) == \
+        _abi.OMEGA_E_WORKSPACE
+    bad = _abi.make_points([(0.0, -1.0, 16, 16)])
+    assert L.omega_pair_chi(ctypes.byref(m), bad, 1, FAKE, 3, 3, FAKE, 1 << 40, FAKE, None) == E
+    # V is not used: a zero coupling is accepted (fails only on the workspace here)
+    mz = _abi.make_model(dict(W.DEFAULT_MODEL, V=(0.0, 0.0)))
+    assert L.omega_pair_chi(ctypes.byref(mz), p, 1, FAKE, 3, 3, FAKE, 8, FAKE, None) == \
+        _abi.OMEGA_E_WORKSPACE
+    assert L.omega3_pair_chi(ctypes.byref(m3), p, 1, FAKE, 3, 8, FAKE, 1 << 40, FAKE, None) == E
 
 
 def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -112,14 +112,16 @@ def test_random_ragged_cases(seed):
     np.testing.assert_array_equal(rows, rrows)
 
 
-@pytest.mark.parametrize("Lx,Ly", [(17, 9), (24, 30), (13, 2), (40, 3)])
+@pytest.mark.parametrize("Lx,Ly", [(17, 9), (24, 30), (13, 2), (40, 3), (2, 15), (8, 8)])
 def test_mirror_folded_rows_match_oracle(Lx, Ly):
-    # Q on the kx axis takes the mirror-folded ky sum (odd and even Ly, the
-    # self-mirrored rows ky = 0 and ky = pi); a Q off the axis in the same
-    # launch takes the full sum.
+    # A zero component of Q folds that momentum axis (odd and even sides, the
+    # self-mirrored indices 0 and L/2): Q on the kx axis folds ky, Q on the ky
+    # axis folds kx, Q = 0 folds both; a Q off the axes in the same launch
+    # takes the full sum.
     pts = [(0.07, 0.004, Lx, Ly), (-0.12, 0.0, Lx, Ly)]
     delta = np.linspace(0.0, 0.6, 35)
-    q = np.array([[0.0, 0.0], [0.3, 0.0], [-0.7, 0.0], [2 * np.pi * 3 / Lx, 0.0], [0.2, 0.1]])
+    q = np.array([[0.0, 0.0], [0.3, 0.0], [-0.7, 0.0], [2 * np.pi * 3 / Lx, 0.0], [0.2, 0.1],
+                  [0.0, 0.45], [0.0, -2 * np.pi / Ly], [-0.0, 0.0]])
     for prec, rel, floor in ((OMEGA_FP64, 1e-12, 1e-13), (OMEGA_FP32_COMP, 1e-7, 1e-8)):
         idx, omin, rows, om = run_argmin(pts, delta, q, 3, prec)
         ref = oracle.omega_grid(M, pts, delta, q, 3)
@@ -307,3 +309,25 @@ def test_gradient_against_oracle(seed):
         for got, ref in ((gd[:, b], rgd), (gq[:, b, 0], rgq[:, 0]), (gq[:, b, 1], rgq[:, 1]),
                          (gm[:, b], rgm)):
             assert (np.abs(got - ref) <= 1e-12 * np.abs(ref) + 1e-13 * N).all(), (got, ref)
+
+
+@pytest.mark.parametrize("Lx,Ly", [(8, 8), (6, 5)])
+def test_zone_from_symmetry_wedge(Lx, Ly):
+    # Algorithm 1 over every lattice pair momentum of the zone, and over the
+    # symmetry wedge: each orbit member has its representative's Omega (to
+    # rounding), and the zone's global minimum is the wedge's
+    from test_q_wedge import orbit
+    pts = [(0.05, 0.003, Lx, Ly)]
+    delta = np.linspace(0.0, 0.6, 25)
+    qw, w = api.q_wedge(Lx, Ly)
+    mn = np.rint(qw * np.array([Lx, Ly]) / (2 * np.pi)).astype(int)
+    full_q = np.array([[2 * np.pi * m / Lx, 2 * np.pi * n / Ly]
+                       for m in range(Lx) for n in range(Ly)])
+    say(f"case: wedge vs full zone {Lx}x{Ly}")
+    idx_f, omin_f, _, g_full = run_argmin(pts, delta, full_q, 3)
+    idx_w, omin_w, _, g_w = run_argmin(pts, delta, qw, 3)
+    assert_close(g_w, oracle.omega_grid(M, pts, delta, qw, 3), pts)
+    for r, (m, n) in enumerate(mn.tolist()):
+        for (a, b) in orbit(m, n, Lx, Ly):
+            np.testing.assert_allclose(g_full[0, :, a * Ly + b], g_w[0, :, r], rtol=1e-12)
+    np.testing.assert_allclose(omin_w, omin_f, rtol=1e-11)

@@ -103,3 +103,24 @@ def test_three_band_workload_sampled_rows():
     np.testing.assert_array_equal(rows[:, :, pick], rr)
     # every band has its minimum at Delta > 0 here (V puts them inside the range)
     assert (idx[0, :, 0] > 0).all()
+
+
+def test_three_band_zone_from_symmetry_wedge():
+    # Omega over every lattice pair momentum of the zone equals the wedge
+    # result expanded over each orbit (GPU against GPU, and the wedge rows
+    # against the oracle)
+    from test_q_wedge import orbit
+    Lx = Ly = 8
+    pts = [(0.02, 0.002, Lx, Ly)]
+    delta = np.linspace(0.0, 0.1, 12)
+    qw, w = api.q_wedge(Lx, Ly)
+    mn = np.rint(qw * Lx / (2 * np.pi)).astype(int)
+    full_q = np.array([[2 * np.pi * m / Lx, 2 * np.pi * n / Ly]
+                       for m in range(Lx) for n in range(Ly)])
+    say("case: three-band wedge vs full zone 8x8")
+    g_full = api.grid3(M3, pts, delta, full_q).cpu().numpy()[0]
+    g_w = api.grid3(M3, pts, delta, qw).cpu().numpy()[0]
+    assert_close(g_w[None], tb.omega_grid(M3, pts, delta, qw, tb.BAND_ALL), pts)
+    for r, (m, n) in enumerate(mn.tolist()):
+        for (a, b) in orbit(m, n, Lx, Ly):
+            np.testing.assert_allclose(g_full[:, a * Ly + b], g_w[:, r], rtol=1e-12)

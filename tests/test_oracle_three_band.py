@@ -120,6 +120,21 @@ def test_three_band_normal_state_is_free_fermion_grand_potential():
         np.testing.assert_allclose(grid[0, band, :, 0], ref, rtol=1e-13)
 
 
+def test_three_band_symmetries_in_q():
+    # k -> -k, kx <-> ky and kx -> -kx map the App. B spectrum onto itself
+    # (conjugation by diag(1,1,-1), the orbital swap 1 <-> 2, diag(-1,1,1)),
+    # so Omega(q) = Omega(-q) = Omega(qy, qx) = Omega(-qx, qy) on a square
+    # lattice, on or off the lattice momenta.
+    L, h, T = 10, 0.02, 0.002
+    rng = np.random.default_rng(8)
+    delta = [0.0, 0.03, 0.08]
+    for qx, qy in rng.uniform(-1, 1, size=(2, 2)):
+        qs = [[qx, qy], [-qx, -qy], [qy, qx], [-qx, qy]]
+        g = tb.omega_grid(M3, [(h, T, L, L)], delta, qs, tb.BAND_ALL)
+        for j in range(1, 4):
+            np.testing.assert_allclose(g[0, :, j, :], g[0, :, 0, :], rtol=1e-13)
+
+
 def test_band_mask_selects_bands():
     pts = [(0.01, 0.001, 8, 6)]
     delta, q = [0.0, 0.04], [[0.0, 0.0], [2 * np.pi / 8, 0.0]]
