@@ -196,7 +196,7 @@ struct GridPlan {
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_mask, off_tlist, off_tcnt, off_etab, off_qlat, sweep_bytes;
+        off_mask, off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, sweep_bytes;
 };
 
 // b3: three-band model, which adds the band table [3][Lx][Ly] of the largest
@@ -212,7 +212,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.nbq = nb * n_q;
     p.groups = group_points(pts, n_pts);
     size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0, etab = 0, tlist = 0,
-           tcnt = 0;
+           tcnt = 0, tpart = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
         if (b3)
@@ -220,7 +220,8 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         const size_t rows = (size_t)p.nbq * t.n_chunks;
         const size_t lcap = list_cap(t);
         const size_t per_point =
-            sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots) +
+            sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots +
+                                     (size_t)p.n_dtiles * kTileSlots) +
             sizeof(unsigned long long) * p.nbq * t.n_tiles + sizeof(int) * rows * 4 * (lcap + 1);
         const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
         p.tiles.push_back(t);
@@ -233,6 +234,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         mask = std::max(mask, sizeof(unsigned long long) * p.nbq * t.n_tiles * G);
         tlist = std::max(tlist, sizeof(int) * rows * 4 * lcap * G);
         tcnt = std::max(tcnt, sizeof(int) * rows * 4 * G);
+        tpart = std::max(tpart, sizeof(double) * rows * p.n_dtiles * kTileSlots * G);
     }
     p.off_d2 = 0;
     p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 2));
@@ -245,7 +247,8 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_mask = p.off_mom + align_up(mom);
     p.off_tlist = p.off_mask + align_up(mask);
     p.off_tcnt = p.off_tlist + align_up(tlist);
-    p.off_etab = p.off_tcnt + align_up(tcnt);
+    p.off_tpart = p.off_tcnt + align_up(tcnt);
+    p.off_etab = p.off_tpart + align_up(tpart);
     p.off_qlat = p.off_etab + align_up(etab);
     p.sweep_bytes = p.off_qlat + (b3 ? align_up(sizeof(int) * 2 * (size_t)n_q) : 0);
     return p;
@@ -384,6 +387,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     int *qlat = (int *)(ws + P.off_qlat);
     int *tlist = (int *)(ws + P.off_tlist);
     int *tcnt = (int *)(ws + P.off_tcnt);
+    double *tpart = (double *)(ws + P.off_tpart);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
         return OMEGA_E_HIP;
     if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
@@ -415,6 +419,8 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.mask = mask;
     a.tlist = tlist;
     a.tcnt = tcnt;
+    a.tpart = tpart;
+    a.n_dtiles = P.n_dtiles;
     a.count = g_sweep_count;
 
     RowArgs r;
@@ -422,6 +428,10 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     r.base_part = base;
     r.mpart = mom;
     r.d2c = d2 + P.n_delta_pad;
+    r.tpart = precision == OMEGA_FP64 ? tpart : nullptr;
+    r.d2 = d2;
+    r.td = P.td;
+    r.n_dtiles = P.n_dtiles;
     r.pts = table;
     r.delta = delta;
     r.q = q;

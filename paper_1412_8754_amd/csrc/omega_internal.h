@@ -51,6 +51,21 @@ constexpr double kSeriesRho = 1.0 / 3.0;
 constexpr int kSeriesTerms = 31;
 constexpr int kMomentSlots = 32;   // C0, M_1..M_31
 
+// Tile series of the FP64 sweep.  Within one Delta tile (the TD Delta of a
+// sweep workgroup; x = Delta^2 in [x_lo, x_hi], centre xc, half-width ht), a
+// direct term that is cold and positive over the whole tile
+// (R(x_lo) >= |d| + 36 T: R - |d| >= 36 T for every Delta of the tile, no
+// thermal part) has R - |d| = (Rc - |d|) + Rc sum_{n>=1} c_n z^n with
+// Rc^2 = s^2 + xc eta^2 and z = (x - xc) eta^2 / Rc^2.  Where
+// ht eta^2 <= kTileRho Rc^2 it is summed through kTileSlots moments per tile
+// (C0 = sum w (Rc - |d|), M_n = sum w Rc (eta^2/Rc^2)^n, n <= kTileTerms);
+// the truncation is below |c_16| 0.15^16 / 0.85 = 3.5e-16 of Rc.  Terms with
+// R(x_hi) <= |d| - 36 T are exactly zero over the tile.
+constexpr double kTileRho = 0.15;
+constexpr int kTileTerms = 15;
+constexpr int kTileSlots = 16;
+constexpr int kTileBatch = 64;   // Delta tiles per LDS batch of the rows kernel
+
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
 
@@ -100,6 +115,8 @@ struct SweepArgs {
     int *tlist;          // [G*nbq][n_chunks][4][lcap] tiles with a nonzero mask,
                          // listed by the series pass per wave
     int *tcnt;           // [G*nbq][n_chunks][4] list lengths
+    double *tpart;       // FP64: [G*nbq][n_chunks][n_dtiles][kTileSlots] tile-series moments
+    int n_dtiles;
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
 };
@@ -111,6 +128,9 @@ struct RowArgs {
     const double *base_part;
     const double *mpart;   // [G*nbq][n_chunks][kMomentSlots] series moments
     const double *d2c;     // centre of the Delta^2 range (series variable x - x0)
+    const double *tpart;   // tile-series moments (FP64 sweep) or nullptr
+    const double *d2;      // [n_delta_pad] Delta^2 (tile centres)
+    int td, n_dtiles;
     const PointRec *pts;   // [G]
     const double *delta;   // [n_delta]
     const double *q;       // [n_q][2]

@@ -800,11 +800,25 @@ void sweep_f64_kernel(const SweepArgs a)
     // the look-ahead read of the last iteration), and the thermal tables
     __shared__ double d2s[TD + 1];
     __shared__ double2 gt[kGTabN];
+    __shared__ double trange[2];
     if (threadIdx.x <= TD)
         d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
     for (int n = threadIdx.x; n < kGTabN; n += kBlock)
         gt[n] = a.gtab[n];
     __syncthreads();
+    if (threadIdx.x == 0) {
+        double lo = d2s[0], hi = d2s[0];
+        for (int t = 1; t < TD; ++t) {
+            lo = fmin(lo, d2s[t]);
+            hi = fmax(hi, d2s[t]);
+        }
+        trange[0] = lo;
+        trange[1] = hi;
+    }
+    __syncthreads();
+    // Delta^2 range of the tile: centre and half-width of the tile series
+    const double x_lo = trange[0], x_hi = trange[1];
+    const double xc = 0.5 * (x_lo + x_hi), ht = 0.5 * (x_hi - x_lo);
 
     const double *cxt = a.trig;
     const double *sxt = a.trig + a.Lx;
@@ -815,6 +829,10 @@ void sweep_f64_kernel(const SweepArgs a)
 #pragma unroll
     for (int t = 0; t < TD; ++t)
         acc[t] = 0.0;
+    // per-wave sums of the tile-series moments, added tile by tile in order
+    __shared__ double wtm[4][kTileSlots];
+    if (lane < kTileSlots)
+        wtm[wave][lane] = 0.0;
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
 
@@ -831,10 +849,50 @@ void sweep_f64_kernel(const SweepArgs a)
         int zoff = 0;
         asm volatile("" : "+v"(zoff));
         const double *dp = d2s + zoff;
+        bool loop = false, tser = false;
+        KQ r;
+        double w = 0.0, Rc2 = 0.0;
         if ((mk >> lane) & 1ull) {
-            KQ r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
-                                cxt[i], sxt[i], cyt[j], syt[j]);
-            const double w = mirror_weight(kr, i, j, a.Lx, a.Ly);
+            r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
+                             cxt[i], sxt[i], cyt[j], syt[j]);
+            w = mirror_weight(kr, i, j, a.Lx, a.Ly);
+            const double up = r.m + cutT, dn = r.m - cutT;
+            Rc2 = fma(xc, r.eta2, r.s2);
+            // cold and positive over the tile, and the tile series converges
+            tser = fma(x_lo, r.eta2, r.s2) >= up * up && ht * r.eta2 <= kTileRho * Rc2;
+            // exactly zero over the tile where R(x_hi) <= |d| - 36 T
+            loop = !tser && !(dn > 0.0 && fma(x_hi, r.eta2, r.s2) <= dn * dn);
+        }
+        if (__ballot(tser) != 0ull) {
+            // moments of the tile series of this wave's momenta, summed over
+            // the wave in two halves of kTileHalf slots (register budget)
+            constexpr int kTileHalf = kTileSlots / 2;
+            constexpr int TSHIFT = 6 - Log2<kTileHalf>::value;
+            double Rc = 0.0, ratio = 0.0;
+            if (tser) {
+                Rc = sqrt_rn(Rc2);
+                // Rc = 0 only with s = 0 and xc eta^2 = 0: the powers vanish
+                ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
+            }
+            double tp = w * Rc;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                double tm[kTileHalf];
+#pragma unroll
+                for (int n = 0; n < kTileHalf; ++n) {
+                    if (half == 0 && n == 0) {
+                        tm[0] = tser ? w * (Rc - r.m) : 0.0;
+                    } else {
+                        tp *= ratio;
+                        tm[n] = tser ? tp : 0.0;
+                    }
+                }
+                wave_reduce_halving<kTileHalf>(tm, lane);
+                if ((lane & ((1 << TSHIFT) - 1)) == 0)
+                    wtm[wave][half * kTileHalf + (lane >> TSHIFT)] += tm[0];
+            }
+        }
+        if (loop) {
             const double wT = w * T;
             ++n_direct;
             // R^2 >= 1e-300 keeps the reciprocal square root finite; the
@@ -873,6 +931,11 @@ void sweep_f64_kernel(const SweepArgs a)
         double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
         a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
                dtile * TD + threadIdx.x] = v;
+    }
+    if (threadIdx.x < kTileSlots) {
+        const int n = threadIdx.x;
+        a.tpart[(((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_dtiles + dtile) * kTileSlots +
+                n] = ((wtm[0][n] + wtm[1][n]) + wtm[2][n]) + wtm[3][n];
     }
 }
 
@@ -1282,21 +1345,63 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     double *out = r.omega + orow * r.n_delta;
     const double *pp = r.part + row * r.n_chunks * r.n_delta_pad;
 
+    // tile series of the FP64 sweep, per Delta tile: c_n times the
+    // fixed-order chunk sums of its moments, and the tile centre, a batch of
+    // kTileBatch tiles at a time
+    __shared__ double sh_tm[kTileBatch][kTileSlots];
+    __shared__ double sh_tc[kTileBatch];
     double best = __longlong_as_double(0x7ff8000000000000LL);
-    for (int id = threadIdx.x; id < r.n_delta; id += kBlock) {
-        double s = 0.0, c = 0.0;
-        for (int ch = 0; ch < r.n_chunks; ++ch)
-            neumaier(s, c, pp[(size_t)ch * r.n_delta_pad + id]);
-        const double D = r.delta[id];
-        // series part: C0 + sum_n c_n M_n (Delta^2 - x0)^n by Horner
-        const double x = D * D - x0;
-        double ser = sh_mom[kSeriesTerms];
-        for (int n = kSeriesTerms - 1; n >= 1; --n)
-            ser = fma(ser, x, sh_mom[n]);
-        ser = fma(ser, x, sh_mom[0]);
-        const double om = (base - ((s + c) + ser)) + r.n_k * (-2.0 * D * D / V) + qpoison;
-        out[id] = om;
-        best = nan_min(best, om);
+    for (int b0 = 0; b0 < r.n_dtiles; b0 += kTileBatch) {
+        const int nbt = min(kTileBatch, r.n_dtiles - b0);
+        if (r.tpart) {
+            __syncthreads();
+            for (int u = threadIdx.x; u < nbt * kTileSlots; u += kBlock) {
+                const int dt = b0 + u / kTileSlots, n = u % kTileSlots;
+                double s = 0.0, c = 0.0;
+                const double *tp = r.tpart + (row * r.n_chunks * r.n_dtiles + dt) * kTileSlots + n;
+                for (int ch = 0; ch < r.n_chunks; ++ch)
+                    neumaier(s, c, tp[(size_t)ch * r.n_dtiles * kTileSlots]);
+                double cn = 1.0;
+                for (int k = 0; k < n; ++k)
+                    cn = cn * (0.5 - k) / (k + 1);
+                sh_tm[u / kTileSlots][n] = cn * (s + c);
+            }
+            for (int u = threadIdx.x; u < nbt; u += kBlock) {
+                // same arithmetic as the sweep's tile range
+                const double *dt2 = r.d2 + (size_t)(b0 + u) * r.td;
+                double lo = dt2[0], hi = dt2[0];
+                for (int t = 1; t < r.td; ++t) {
+                    lo = fmin(lo, dt2[t]);
+                    hi = fmax(hi, dt2[t]);
+                }
+                sh_tc[u] = 0.5 * (lo + hi);
+            }
+            __syncthreads();
+        }
+        const int id_end = min(r.n_delta, (b0 + nbt) * r.td);
+        for (int id = b0 * r.td + threadIdx.x; id < id_end; id += kBlock) {
+            double s = 0.0, c = 0.0;
+            for (int ch = 0; ch < r.n_chunks; ++ch)
+                neumaier(s, c, pp[(size_t)ch * r.n_delta_pad + id]);
+            const double D = r.delta[id];
+            // series part: C0 + sum_n c_n M_n (Delta^2 - x0)^n by Horner
+            const double x = D * D - x0;
+            double ser = sh_mom[kSeriesTerms];
+            for (int n = kSeriesTerms - 1; n >= 1; --n)
+                ser = fma(ser, x, sh_mom[n]);
+            ser = fma(ser, x, sh_mom[0]);
+            if (r.tpart) {
+                const int u = id / r.td - b0;
+                const double z = D * D - sh_tc[u];
+                double ts = sh_tm[u][kTileSlots - 1];
+                for (int n = kTileSlots - 2; n >= 0; --n)
+                    ts = fma(ts, z, sh_tm[u][n]);
+                s += ts;
+            }
+            const double om = (base - ((s + c) + ser)) + r.n_k * (-2.0 * D * D / V) + qpoison;
+            out[id] = om;
+            best = nan_min(best, om);
+        }
     }
     if (!r.row_idx)
         return;

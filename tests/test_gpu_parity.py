@@ -329,5 +329,6 @@ def test_zone_from_symmetry_wedge(Lx, Ly):
     assert_close(g_w, oracle.omega_grid(M, pts, delta, qw, 3), pts)
     for r, (m, n) in enumerate(mn.tolist()):
         for (a, b) in orbit(m, n, Lx, Ly):
-            np.testing.assert_allclose(g_full[0, :, a * Ly + b], g_w[0, :, r], rtol=1e-12)
+            np.testing.assert_allclose(g_full[0, :, a * Ly + b], g_w[0, :, r], rtol=1e-12,
+                                       atol=1e-13 * Lx * Ly)
     np.testing.assert_allclose(omin_w, omin_f, rtol=1e-11)
