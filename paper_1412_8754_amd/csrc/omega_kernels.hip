@@ -771,7 +771,7 @@ hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStrea
 // Per-Delta FP64 sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.
 template <int TD, bool B3>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void sweep_f64_kernel(const SweepArgs a)
 {
     const int chunk = blockIdx.x;
@@ -829,10 +829,10 @@ void sweep_f64_kernel(const SweepArgs a)
 #pragma unroll
     for (int t = 0; t < TD; ++t)
         acc[t] = 0.0;
-    // per-wave sums of the tile-series moments, added tile by tile in order
-    __shared__ double wtm[4][kTileSlots];
-    if (lane < kTileSlots)
-        wtm[wave][lane] = 0.0;
+    double tm[kTileSlots];
+#pragma unroll
+    for (int n = 0; n < kTileSlots; ++n)
+        tm[n] = 0.0;
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
 
@@ -863,33 +863,17 @@ void sweep_f64_kernel(const SweepArgs a)
             // exactly zero over the tile where R(x_hi) <= |d| - 36 T
             loop = !tser && !(dn > 0.0 && fma(x_hi, r.eta2, r.s2) <= dn * dn);
         }
-        if (__ballot(tser) != 0ull) {
-            // moments of the tile series of this wave's momenta, summed over
-            // the wave in two halves of kTileHalf slots (register budget)
-            constexpr int kTileHalf = kTileSlots / 2;
-            constexpr int TSHIFT = 6 - Log2<kTileHalf>::value;
-            double Rc = 0.0, ratio = 0.0;
-            if (tser) {
-                Rc = sqrt_rn(Rc2);
-                // Rc = 0 only with s = 0 and xc eta^2 = 0: the powers vanish
-                ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
-            }
+        if (tser) {
+            // moments of the tile series, accumulated per lane
+            const double Rc = sqrt_rn(Rc2);
+            // Rc = 0 only with s = 0 and xc eta^2 = 0: the powers vanish
+            const double ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
+            tm[0] = fma(w, Rc - r.m, tm[0]);
             double tp = w * Rc;
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                double tm[kTileHalf];
-#pragma unroll
-                for (int n = 0; n < kTileHalf; ++n) {
-                    if (half == 0 && n == 0) {
-                        tm[0] = tser ? w * (Rc - r.m) : 0.0;
-                    } else {
-                        tp *= ratio;
-                        tm[n] = tser ? tp : 0.0;
-                    }
-                }
-                wave_reduce_halving<kTileHalf>(tm, lane);
-                if ((lane & ((1 << TSHIFT) - 1)) == 0)
-                    wtm[wave][half * kTileHalf + (lane >> TSHIFT)] += tm[0];
+            for (int n = 1; n < kTileSlots; ++n) {
+                tp *= ratio;
+                tm[n] += tp;
             }
         }
         if (loop) {
@@ -932,10 +916,15 @@ void sweep_f64_kernel(const SweepArgs a)
         a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
                dtile * TD + threadIdx.x] = v;
     }
+    __syncthreads();
+    wave_reduce_halving<kTileSlots>(tm, lane);
+    red[wave][lane] = tm[0];
+    __syncthreads();
+    constexpr int TSHIFT = 6 - Log2<kTileSlots>::value;
     if (threadIdx.x < kTileSlots) {
-        const int n = threadIdx.x;
+        const int src = threadIdx.x << TSHIFT;
         a.tpart[(((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_dtiles + dtile) * kTileSlots +
-                n] = ((wtm[0][n] + wtm[1][n]) + wtm[2][n]) + wtm[3][n];
+                threadIdx.x] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
     }
 }
 
