@@ -37,6 +37,12 @@ sys.path.insert(0, ROOT)
 OPS_PER_EVAL = 16
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 
+# HBM bytes per launch of the timed sweep kernel, from rocprofv3 FETCH_SIZE
+# (x2.0) and WRITE_SIZE (x1.0) passes, scaled by the same counters on a plain
+# 256 MiB device copy (profiles/sweep_f64_paper_L1024.md).  Valid for the
+# kernel build those counters were taken on; None for other workloads.
+TRAFFIC_BYTES = {("paper", "fp64"): (3422 * 2 + 24576) * 1024}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -368,7 +374,8 @@ def main():
                    "precision": args.precision, "evals_per_step": evals_step,
                    "folded_terms_per_step": evaluated, "direct_terms_per_step": direct},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": TRAFFIC_BYTES.get((args.workload, args.precision)),
                      "kernel": "sweep_%s_kernel<32>" % ("f64" if args.precision == "fp64"
                                                         else "f32c"),
                      "kernel_ms": sweep_avg, "ops_per_eval": OPS_PER_EVAL},

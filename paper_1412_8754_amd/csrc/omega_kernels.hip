@@ -1294,6 +1294,22 @@ __device__ __forceinline__ double tie_threshold(double best, double tie_rel)
 // One workgroup per (band slot, Q) row of one point: fixed-order chunk sums,
 // the epilogue of Eq. (5) (+ N (-2 Delta^2 / V)), and the row search of
 // Algorithm 1 ("find and save Delta for this q").
+// binomial(1/2, n), n = 0..kMomentSlots-1, by the recurrence
+// c_{n+1} = c_n (1/2 - n) / (n + 1), evaluated at compile time
+struct HalfBinomial {
+    double c[kMomentSlots];
+    constexpr HalfBinomial() : c()
+    {
+        double v = 1.0;
+        for (int n = 0; n < kMomentSlots; ++n) {
+            c[n] = v;
+            v = v * (0.5 - n) / (n + 1);
+        }
+    }
+};
+__constant__ constexpr HalfBinomial kHalfBinomial{};
+static_assert(kTileSlots <= kMomentSlots, "tile series uses the same coefficients");
+
 __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
 {
     const int bq = blockIdx.x;
@@ -1319,11 +1335,8 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
         const double *mp = r.mpart + row * r.n_chunks * kMomentSlots + threadIdx.x;
         for (int ch = 0; ch < r.n_chunks; ++ch)
             neumaier(s, c, mp[(size_t)ch * kMomentSlots]);
-        // binomial(1/2, n) by its recurrence, c_1 = 1/2 (c_0 = 1 is in C0)
-        double cn = 1.0;
-        for (int n = 0; n < (int)threadIdx.x; ++n)
-            cn = cn * (0.5 - n) / (n + 1);
-        sh_mom[threadIdx.x] = threadIdx.x == 0 ? (s + c) : cn * (s + c);
+        // times binomial(1/2, n) (c_0 = 1: C0 as it is)
+        sh_mom[threadIdx.x] = threadIdx.x == 0 ? (s + c) : kHalfBinomial.c[threadIdx.x] * (s + c);
     }
     __syncthreads();
     const double base = sh_base;
@@ -1350,10 +1363,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
                 const double *tp = r.tpart + (row * r.n_chunks * r.n_dtiles + dt) * kTileSlots + n;
                 for (int ch = 0; ch < r.n_chunks; ++ch)
                     neumaier(s, c, tp[(size_t)ch * r.n_dtiles * kTileSlots]);
-                double cn = 1.0;
-                for (int k = 0; k < n; ++k)
-                    cn = cn * (0.5 - k) / (k + 1);
-                sh_tm[u / kTileSlots][n] = cn * (s + c);
+                sh_tm[u / kTileSlots][n] = kHalfBinomial.c[n] * (s + c);
             }
             for (int u = threadIdx.x; u < nbt; u += kBlock) {
                 // same arithmetic as the sweep's tile range
