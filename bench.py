@@ -228,7 +228,9 @@ def differentiation(args):
         fm = api.grad(M, sp, d0 - shift_d * e, qm)[0]
         return (fp - fm) / (2 * e)
 
-    def richardson(sd, sq, e=1e-3):
+    # Omega varies on the scale of T (>= 1e-3 here) in Delta and q, so the
+    # difference step is well below it
+    def richardson(sd, sq, e=2e-5):
         return (4 * cdiff(sd, sq, e / 2) - cdiff(sd, sq, e)) / 3
 
     fd_d = ((richardson(1, 0) - gd0).abs().max() / gd0.abs().max()).item()
