@@ -83,11 +83,28 @@ def cpu_baseline(cfg, rows_per_band):
         nb = 2 if cfg["bands"] == 3 else 1
     dt = time.perf_counter() - t0
     n_k = pts[0][2] * pts[0][3]
+    # one thread, a smaller sample: 1 band x 1 Q row x 32 Delta
+    threads = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        d1 = cfg["delta"][:32]
+        t1 = time.perf_counter()
+        if "model" in cfg:
+            three_band.omega_grid(cfg["model"], pts, d1, q[sel[:1]], 1)
+        else:
+            oracle.omega_grid(W.DEFAULT_MODEL, pts, d1, q[sel[:1]], 1)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(threads)
+    evals1 = n_k * len(d1)
     evals = n_k * len(cfg["delta"]) * len(sel) * nb
-    return {"value": evals / dt, "unit": "evals/s", "cores": oracle.max_threads(),
+    return {"value": evals / dt, "unit": "evals/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{nb} bands x {len(sel)} of {len(q)} Q rows x {len(cfg['delta'])} Delta "
-                      f"at L={pts[0][2]} ({evals:.3e} evals, {dt:.1f} s)"}
+                      f"at L={pts[0][2]} ({evals:.3e} evals, {dt:.1f} s)",
+            "single_thread": {"value": evals1 / dt1, "unit": "evals/s", "cores": 1,
+                              "sample": f"1 band x 1 Q row x {len(d1)} Delta at "
+                                        f"L={pts[0][2]} ({evals1:.3e} evals, {dt1:.1f} s)"}}
 
 
 def calibrate_copy(mib):
