@@ -196,7 +196,7 @@ struct GridPlan {
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_mask, off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, sweep_bytes;
+        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, sweep_bytes;
 };
 
 // b3: three-band model, which adds the band table [3][Lx][Ly] of the largest
@@ -211,7 +211,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.n_delta_pad = p.n_dtiles * p.td;
     p.nbq = nb * n_q;
     p.groups = group_points(pts, n_pts);
-    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, mask = 0, etab = 0, tlist = 0,
+    size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, etab = 0, tlist = 0,
            tcnt = 0, tpart = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
@@ -222,7 +222,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         const size_t per_point =
             sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots +
                                      (size_t)p.n_dtiles * kTileSlots) +
-            sizeof(unsigned long long) * p.nbq * t.n_tiles + sizeof(int) * rows * 4 * (lcap + 1);
+            sizeof(unsigned long long) * rows * 4 * lcap * 2 + sizeof(int) * rows * 4;
         const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
         p.tiles.push_back(t);
         p.batch.push_back(G);
@@ -231,8 +231,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         part = std::max(part, sizeof(double) * rows * p.n_delta_pad * G);
         base = std::max(base, sizeof(double) * rows * G);
         mom = std::max(mom, sizeof(double) * rows * kMomentSlots * G);
-        mask = std::max(mask, sizeof(unsigned long long) * p.nbq * t.n_tiles * G);
-        tlist = std::max(tlist, sizeof(int) * rows * 4 * lcap * G);
+        tlist = std::max(tlist, sizeof(unsigned long long) * rows * 4 * lcap * 2 * G);
         tcnt = std::max(tcnt, sizeof(int) * rows * 4 * G);
         tpart = std::max(tpart, sizeof(double) * rows * p.n_dtiles * kTileSlots * G);
     }
@@ -244,8 +243,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_part = p.off_table + align_up(table);
     p.off_base = p.off_part + align_up(part);
     p.off_mom = p.off_base + align_up(base);
-    p.off_mask = p.off_mom + align_up(mom);
-    p.off_tlist = p.off_mask + align_up(mask);
+    p.off_tlist = p.off_mom + align_up(mom);
     p.off_tcnt = p.off_tlist + align_up(tlist);
     p.off_tpart = p.off_tcnt + align_up(tcnt);
     p.off_etab = p.off_tpart + align_up(tpart);
@@ -382,10 +380,9 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     double *part = (double *)(ws + P.off_part);
     double *base = (double *)(ws + P.off_base);
     double *mom = (double *)(ws + P.off_mom);
-    unsigned long long *mask = (unsigned long long *)(ws + P.off_mask);
     double *etab = (double *)(ws + P.off_etab);
     int *qlat = (int *)(ws + P.off_qlat);
-    int *tlist = (int *)(ws + P.off_tlist);
+    unsigned long long *tlist = (unsigned long long *)(ws + P.off_tlist);
     int *tcnt = (int *)(ws + P.off_tcnt);
     double *tpart = (double *)(ws + P.off_tpart);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
@@ -416,7 +413,6 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.part = part;
     a.base_part = base;
     a.mpart = mom;
-    a.mask = mask;
     a.tlist = tlist;
     a.tcnt = tcnt;
     a.tpart = tpart;

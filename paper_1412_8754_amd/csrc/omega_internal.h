@@ -111,9 +111,9 @@ struct SweepArgs {
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments
-    unsigned long long *mask;    // [G*nbq][n_tiles] lanes evaluated per Delta
-    int *tlist;          // [G*nbq][n_chunks][4][lcap] tiles with a nonzero mask,
-                         // listed by the series pass per wave
+    unsigned long long *tlist;   // [G*nbq][n_chunks][4][lcap][2] (tile, lane mask) of
+                                 // the tiles with lanes evaluated per Delta, listed
+                                 // by the series pass per wave
     int *tcnt;           // [G*nbq][n_chunks][4] list lengths
     double *tpart;       // FP64: [G*nbq][n_chunks][n_dtiles][kTileSlots] tile-series moments
     int n_dtiles;

@@ -616,9 +616,14 @@ __device__ __forceinline__ double mirror_weight(const KRange &k, int i, int j, i
 }
 
 // The listed tiles of one (batch point, band, Q) and chunk: the four wave
-// lists of the series pass, concatenated.
+// lists of the series pass, concatenated.  Entries are (tile, lane mask).
+// The lists are written by an earlier kernel and only read here, so they are
+// read through the constant address space (scalar loads of wave-uniform
+// entries).
+typedef const __attribute__((address_space(4))) unsigned long long *ConstU64Ptr;
+
 struct TileList {
-    const int *base;
+    ConstU64Ptr base;
     int lcap;
     int c0, c1, c2, total;   // c0, c0 + c1, c0 + c1 + c2, all four
 };
@@ -627,8 +632,9 @@ __device__ __forceinline__ TileList tile_list(const SweepArgs &a, int bz, int ch
 {
     TileList t;
     const size_t row = (size_t)bz * a.n_chunks + chunk;
-    const int *cnt = a.tcnt + row * 4;
-    t.base = a.tlist + row * 4 * a.lcap;
+    const __attribute__((address_space(4))) int *cnt =
+        (const __attribute__((address_space(4))) int *)(a.tcnt + row * 4);
+    t.base = (ConstU64Ptr)(a.tlist + row * 4 * a.lcap * 2);
     t.lcap = a.lcap;
     t.c0 = cnt[0];
     t.c1 = t.c0 + cnt[1];
@@ -637,11 +643,15 @@ __device__ __forceinline__ TileList tile_list(const SweepArgs &a, int bz, int ch
     return t;
 }
 
-__device__ __forceinline__ int listed_tile(const TileList &t, int e)
+// Entry e (wave-uniform) of the concatenated lists: (tile, lane mask).
+__device__ __forceinline__ void listed_tile(const TileList &t, int e, int &tile,
+                                            unsigned long long &mask)
 {
     const int seg = (e >= t.c0) + (e >= t.c1) + (e >= t.c2);
     const int start = seg == 0 ? 0 : (seg == 1 ? t.c0 : (seg == 2 ? t.c1 : t.c2));
-    return t.base[seg * t.lcap + (e - start)];
+    const size_t k = 2 * ((size_t)seg * t.lcap + (e - start));
+    tile = (int)t.base[k];
+    mask = t.base[k + 1];
 }
 
 // Per-(k, Q) pass over one (band, Q, point) and momentum chunk, shared by
@@ -651,9 +661,9 @@ __device__ __forceinline__ int listed_tile(const TileList &t, int e)
 //   - the Delta^2 series moments C0 = sum w (R0 - |d|) (for the FP32 sweep
 //     sum w (R0 - |s|), as |s| - |d| is part of P(0)) and
 //     M_n = sum w R0 (eta^2/R0^2)^n;
-//   - for every 8 x 8 tile, the ballot of lanes the per-Delta sweep must
-//     evaluate directly, and per wave the list of tiles with a nonzero ballot
-//     (the sweeps walk these lists instead of scanning every mask).
+//   - per wave, the list of 8 x 8 tiles with lanes the per-Delta sweep must
+//     evaluate directly, with the ballot of those lanes (the sweeps walk
+//     these lists).
 // Grid (chunk, band*Q + nbq*g).
 template <bool B3>
 __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
@@ -681,8 +691,8 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
     const double *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx;
     const double *syt = cyt + a.Ly;
-    unsigned long long *mask = a.mask + (size_t)blockIdx.y * a.n_tiles;
-    int *tl = a.tlist + (((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave) * a.lcap;
+    unsigned long long *tl =
+        a.tlist + (((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave) * a.lcap * 2;
     int n_listed = 0;
     double mom[kMomentSlots];
 #pragma unroll
@@ -729,11 +739,11 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
             }
         }
         const unsigned long long ballot = __ballot(direct);
-        if (lane == 0)
-            mask[tile] = ballot;
         if (ballot != 0ull) {
-            if (lane == 0)
-                tl[n_listed] = tile;
+            if (lane == 0) {
+                tl[2 * n_listed] = (unsigned long long)tile;
+                tl[2 * n_listed + 1] = ballot;
+            }
             ++n_listed;
         }
     }
@@ -791,7 +801,6 @@ void sweep_f64_kernel(const SweepArgs a)
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
     const double cutT = kCutFp64 * T;
-    const unsigned long long *mask = a.mask + (size_t)blockIdx.z * a.n_tiles;
 
     const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
@@ -837,9 +846,17 @@ void sweep_f64_kernel(const SweepArgs a)
     const int li = lane >> 3, lj = lane & 7;
 
     const TileList tl = tile_list(a, blockIdx.z, chunk);
-    for (int e = wave; e < tl.total; e += 4) {
-        const int tile = listed_tile(tl, e);
-        const unsigned long long mk = mask[tile];
+    // the next entry of this wave's walk is fetched one tile ahead
+    int e = __builtin_amdgcn_readfirstlane(wave);
+    int nt_tile = 0;
+    unsigned long long nt_mask = 0ull;
+    if (e < tl.total)
+        listed_tile(tl, e, nt_tile, nt_mask);
+    for (; e < tl.total; e += 4) {
+        const int tile = nt_tile;
+        const unsigned long long mk = nt_mask;
+        if (e + 4 < tl.total)
+            listed_tile(tl, e + 4, nt_tile, nt_mask);
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
@@ -1009,7 +1026,6 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const double mu_dn = a.mu - pt.h;
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
-    const unsigned long long *mask = a.mask + (size_t)blockIdx.z * a.n_tiles;
 
     const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
@@ -1039,9 +1055,17 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
     const int li = lane >> 3, lj = lane & 7;
 
     const TileList tl = tile_list(a, blockIdx.z, chunk);
-    for (int e = wave; e < tl.total; e += 4) {
-        const int tile = listed_tile(tl, e);
-        const unsigned long long mk = mask[tile];
+    // the next entry of this wave's walk is fetched one tile ahead
+    int e = __builtin_amdgcn_readfirstlane(wave);
+    int nt_tile = 0;
+    unsigned long long nt_mask = 0ull;
+    if (e < tl.total)
+        listed_tile(tl, e, nt_tile, nt_mask);
+    for (; e < tl.total; e += 4) {
+        const int tile = nt_tile;
+        const unsigned long long mk = nt_mask;
+        if (e + 4 < tl.total)
+            listed_tile(tl, e + 4, nt_tile, nt_mask);
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
