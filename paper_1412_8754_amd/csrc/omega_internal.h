@@ -34,7 +34,7 @@ constexpr float kCutFp32 = 17.0f;
 
 // Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 36: entry N
 // holds (G(a0), 1/(1 + e^a0)) at a0 = N / kGStep.
-constexpr int kGStep = 32;
+constexpr int kGStep = 64;
 constexpr int kGTabN = 36 * kGStep + 1;
 static_assert(kCutFp64 == 36.0, "the thermal table ends at the FP64 cut");
 
