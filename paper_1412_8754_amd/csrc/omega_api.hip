@@ -199,8 +199,9 @@ struct GridPlan {
         off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, sweep_bytes;
 };
 
-// b3: three-band model, which adds the band table [3][Lx][Ly] of the largest
-// lattice and the lattice indices of the pair momenta.
+// b3: three-band model.  The band table of the largest lattice holds 3 bands
+// for it and 2 for the two-band model; the lattice indices of the pair momenta
+// follow it.
 GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb,
                    bool b3 = false)
 {
@@ -215,8 +216,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
            tcnt = 0, tpart = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
-        if (b3)
-            etab = std::max(etab, sizeof(double) * 3 * (size_t)g.Lx * g.Ly);
+        etab = std::max(etab, sizeof(double) * (b3 ? 3 : 2) * (size_t)g.Lx * g.Ly);
         const size_t rows = (size_t)p.nbq * t.n_chunks;
         const size_t lcap = list_cap(t);
         const size_t per_point =
@@ -248,7 +248,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_tpart = p.off_tcnt + align_up(tcnt);
     p.off_etab = p.off_tpart + align_up(tpart);
     p.off_qlat = p.off_etab + align_up(etab);
-    p.sweep_bytes = p.off_qlat + (b3 ? align_up(sizeof(int) * 2 * (size_t)n_q) : 0);
+    p.sweep_bytes = p.off_qlat + align_up(sizeof(int) * 2 * (size_t)n_q);
     return p;
 }
 
@@ -446,8 +446,9 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         const Tiles &t = P.tiles[gi];
         if (launch_trig(g.Lx, g.Ly, trig, s) != hipSuccess)
             return OMEGA_E_HIP;
-        if (md.b3 && (launch_etab(md.hop3, trig, g.Lx, g.Ly, etab, s) != hipSuccess ||
-                      launch_qlat(q, n_q, g.Lx, g.Ly, qlat, s) != hipSuccess))
+        const hipError_t te = md.b3 ? launch_etab(md.hop3, trig, g.Lx, g.Ly, etab, s)
+                                    : launch_etab2(md.hop, trig, g.Lx, g.Ly, etab, s);
+        if (te != hipSuccess || launch_qlat(q, n_q, g.Lx, g.Ly, qlat, s) != hipSuccess)
             return OMEGA_E_HIP;
         a.Lx = g.Lx;
         a.Ly = g.Ly;

@@ -90,9 +90,9 @@ struct SweepArgs {
     Hop hop;
     double eps[2];       // two-band: band sign per output slot (-1: E_-, +1: E_+)
     Hop3 hop3;           // three-band: model, for momenta off the lattice
-    int band3[3];        // three-band: band index per output slot
-    const double *etab;  // three-band: E_b(k) [3][Lx][Ly]
-    const int *qlat;     // three-band: [n_q][2] lattice index of Q, or -1 if off it
+    int band3[3];        // band index per output slot (0, 1 two-band; 0..2 three-band)
+    const double *etab;  // E_b(k) over the lattice, [2 or 3][Lx][Ly]
+    const int *qlat;     // [n_q][2] lattice index of Q, or -1 if off it
     double mu;           // chemical potential
     const PointRec *pts; // [G] this batch
     int Lx, Ly;
@@ -208,6 +208,8 @@ hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
 hipError_t launch_gtable(double2 *gtab, hipStream_t s);
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s);
+hipError_t launch_etab2(const Hop &h, const double *trig, int Lx, int Ly, double *etab,
+                        hipStream_t s);
 hipError_t launch_etab(const Hop3 &h, const double *trig, int Lx, int Ly, double *etab,
                        hipStream_t s);
 hipError_t launch_qlat(const double *q, int n_q, int Lx, int Ly, int *qlat, hipStream_t s);

@@ -461,40 +461,62 @@ __device__ __forceinline__ double eig3_band(const Hop3 &h, double c, double sn, 
 }
 
 // E(k) and E(Q - k) of one momentum for output slot `slot` and pair momentum
-// iq.  Two-band: (A.4) in closed form, with cos/sin of Q - k by angle
-// subtraction.  Three-band: E(k) from the lattice table; E(Q - k) from the
-// same table at the lattice index of Q - k when Q lies on the lattice, else
-// by diagonalising at Q - k.
+// iq.  E(k) comes from the lattice table of either model, and so does
+// E(Q - k) when Q lies on the lattice.  Otherwise E(Q - k) is computed at
+// Q - k, with cos/sin of Q - k by angle subtraction: (A.4) in closed form for
+// the two-band model, by diagonalising for the three-band model.
 template <bool B3>
 __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int iq, int i, int j,
                                        double eps, double mu_up, double mu_dn, double cqx,
                                        double sqx, double cqy, double sqy, double cx,
                                        double sx, double cy, double sy)
 {
-    const double cpx = fma(cqx, cx, sqx * sx);
-    const double spx = fma(sqx, cx, -(cqx * sx));
-    const double cpy = fma(cqy, cy, sqy * sy);
-    const double spy = fma(sqy, cy, -(cqy * sy));
-    double Ek, Eq;
-    if constexpr (!B3) {
-        Ek = band_energy(a.hop, eps, cx, sx, cy, sy);
-        Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
+    const int b = a.band3[slot];
+    const double *E = a.etab + (size_t)b * a.Lx * a.Ly;
+    const double Ek = E[(size_t)i * a.Ly + j];
+    double Eq;
+    const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
+    if (mx >= 0 && my >= 0) {
+        int ii = mx - i;
+        ii += ii < 0 ? a.Lx : 0;
+        int jj = my - j;
+        jj += jj < 0 ? a.Ly : 0;
+        Eq = E[(size_t)ii * a.Ly + jj];
     } else {
-        const int b = a.band3[slot];
-        const double *E = a.etab + (size_t)b * a.Lx * a.Ly;
-        Ek = E[(size_t)i * a.Ly + j];
-        const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
-        if (mx >= 0 && my >= 0) {
-            int ii = mx - i;
-            ii += ii < 0 ? a.Lx : 0;
-            int jj = my - j;
-            jj += jj < 0 ? a.Ly : 0;
-            Eq = E[(size_t)ii * a.Ly + jj];
-        } else {
+        const double cpx = fma(cqx, cx, sqx * sx);
+        const double spx = fma(sqx, cx, -(cqx * sx));
+        const double cpy = fma(cqy, cy, sqy * sy);
+        const double spy = fma(sqy, cy, -(cqy * sy));
+        if constexpr (!B3)
+            Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
+        else
             Eq = eig3_band(a.hop3, cpx, spx, cpy, spy, b);
-        }
     }
     return kq_from(Ek, Eq, mu_up, mu_dn, cx, cy);
+}
+
+// Band table of the two-band model over the lattice, [2][Lx][Ly]: E_- then
+// E_+ of (A.4), from the cos/sin table.
+__global__ void etab2_kernel(const Hop h, const double *trig, int Lx, int Ly, double *E)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)Lx * Ly;
+    if (t >= n)
+        return;
+    const int i = (int)(t / Ly);
+    const int j = (int)(t - (long long)i * Ly);
+    const double *cxt = trig, *sxt = trig + Lx, *cyt = trig + 2 * Lx, *syt = cyt + Ly;
+    E[t] = band_energy(h, -1.0, cxt[i], sxt[i], cyt[j], syt[j]);
+    E[n + t] = band_energy(h, 1.0, cxt[i], sxt[i], cyt[j], syt[j]);
+}
+
+hipError_t launch_etab2(const Hop &h, const double *trig, int Lx, int Ly, double *etab,
+                        hipStream_t s)
+{
+    const long long n = (long long)Lx * Ly;
+    hipLaunchKernelGGL(etab2_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+                       0, s, h, trig, Lx, Ly, etab);
+    return hipGetLastError();
 }
 
 // Band table of the three-band model over the lattice, [3][Lx][Ly], from the
