@@ -196,7 +196,7 @@ struct GridPlan {
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, sweep_bytes;
+        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, off_queue, sweep_bytes;
 };
 
 // b3: three-band model.  The band table of the largest lattice holds 3 bands
@@ -248,7 +248,8 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_tpart = p.off_tcnt + align_up(tcnt);
     p.off_etab = p.off_tpart + align_up(tpart);
     p.off_qlat = p.off_etab + align_up(etab);
-    p.sweep_bytes = p.off_qlat + align_up(sizeof(int) * 2 * (size_t)n_q);
+    p.off_queue = p.off_qlat + align_up(sizeof(int) * 2 * (size_t)n_q);
+    p.sweep_bytes = p.off_queue + align_up(sizeof(unsigned long long));
     return p;
 }
 
@@ -385,6 +386,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     unsigned long long *tlist = (unsigned long long *)(ws + P.off_tlist);
     int *tcnt = (int *)(ws + P.off_tcnt);
     double *tpart = (double *)(ws + P.off_tpart);
+    unsigned long long *queue = (unsigned long long *)(ws + P.off_queue);
     if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
         return OMEGA_E_HIP;
     if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
@@ -418,6 +420,8 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.tpart = tpart;
     a.n_dtiles = P.n_dtiles;
     a.count = g_sweep_count;
+    a.queue = queue;
+    a.n_rows = 0;
 
     RowArgs r;
     r.part = part;

@@ -85,7 +85,8 @@ struct PointPack {
 };
 
 // Arguments of one Delta-sweep launch: a batch of G points of one lattice
-// size; grid (chunk, Delta tile, band*Q + nbq*g).
+// size.  The work splits into (chunk, Delta tile, band*Q + nbq*g) units: the
+// grid of series_kernel and the f32c sweep, the work queue of the FP64 sweep.
 struct SweepArgs {
     Hop hop;
     double eps[2];       // two-band: band sign per output slot (-1: E_-, +1: E_+)
@@ -119,6 +120,8 @@ struct SweepArgs {
     int n_dtiles;
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
+    unsigned long long *queue;   // work queue of the persistent FP64 sweep
+    int n_rows;          // G * nbq rows of this launch
 };
 
 // Arguments of the per-row reduction / epilogue / row search: grid

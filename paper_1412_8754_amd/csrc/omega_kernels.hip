@@ -686,9 +686,34 @@ __device__ __forceinline__ void listed_tile(const TileList &t, int e, int &tile,
 //     evaluate directly, with the ballot of those lanes (the sweeps walk
 //     these lists).
 // Grid (chunk, band*Q + nbq*g).
+// Work queue of the persistent sweeps: one 64-bit counter in the workspace,
+// zeroed by series_kernel (which runs before every sweep launch).  Units are
+// numbered chunk fastest, then Delta tile, then row (point of the batch,
+// band, Q).  Writes (chunk, Delta tile, row) of the next unit into unit[],
+// or row -1 once every unit has been taken; each workgroup stops at its
+// first -1, so every one of them ends.
+__device__ __forceinline__ void next_unit(const SweepArgs &a, int *unit)
+{
+    const unsigned long long u = atomicAdd(a.queue, 1ull);
+    const unsigned long long per_row = (unsigned long long)a.n_chunks * a.n_dtiles;
+    if (u >= per_row * (unsigned long long)a.n_rows) {
+        unit[2] = -1;
+        return;
+    }
+    const unsigned long long row = u / per_row;
+    const unsigned long long rest = u - row * per_row;
+    const unsigned long long dtile = rest / (unsigned long long)a.n_chunks;
+    unit[0] = (int)(rest - dtile * (unsigned long long)a.n_chunks);
+    unit[1] = (int)dtile;
+    unit[2] = (int)row;
+}
+
 template <bool B3>
 __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
 {
+    // reset the work queue of the sweep that follows on the stream
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
+        a.queue[0] = 0ull;
     const int chunk = blockIdx.x;
     const int g = blockIdx.y / a.nbq;
     const int bq = blockIdx.y - g * a.nbq;
@@ -800,187 +825,248 @@ hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStrea
 }
 
 // Per-Delta FP64 sweep over the lanes series_kernel marked for direct
-// evaluation; tiles without such lanes are skipped whole.
+// evaluation; tiles without such lanes are skipped whole.  The kernel is
+// persistent: each workgroup takes (chunk, Delta tile, row) units from the
+// work queue until it runs dry (see next_unit) and loads the thermal table
+// into LDS once.
+// The argument block of a kernel whose only parameter is a SweepArgs: the
+// kernarg segment starts with it.  Reading the fields through this pointer,
+// made opaque once per unit of a persistent kernel, reloads them with scalar
+// loads instead of holding them in registers across the whole unit.
+typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
+
+// A wave-uniform double copied into scalar registers.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-void sweep_f64_kernel(const SweepArgs a)
+void sweep_f64_kernel(const SweepArgs args)
 {
-    const int chunk = blockIdx.x;
-    const int dtile = blockIdx.y;
-    const int g = blockIdx.z / a.nbq;          // point within the batch
-    const int bq = blockIdx.z - g * a.nbq;
-    const int slot = bq / a.n_q;
-    const int iq = bq - slot * a.n_q;
-    const double eps = slot ? a.eps[1] : a.eps[0];
+    const SweepArgs &a0 = args;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const double qy = a.q[2 * iq + 1];
-    const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
-    const PointRec pt = a.pts[g];
-    const double mu_up = a.mu + pt.h;          // spin up: E - mu - h
-    const double mu_dn = a.mu - pt.h;          // spin down: E - mu + h
-    const double T = pt.T;
-    const double invT = T > 0.0 ? 1.0 / T : 0.0;
-    const double cutT = kCutFp64 * T;
-
-    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
-
-    // Delta^2 of this tile, read from LDS inside the loop (one extra slot for
-    // the look-ahead read of the last iteration), and the thermal tables
+    // Delta^2 of the unit's tile, read from LDS inside the loop (one extra
+    // slot for the look-ahead read of the last iteration), the thermal
+    // table, the tile's Delta^2 range and the next unit
     __shared__ double d2s[TD + 1];
     __shared__ double2 gt[kGTabN];
     __shared__ double trange[2];
-    if (threadIdx.x <= TD)
-        d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+    __shared__ double red[4][64];
+    __shared__ int unit[3];
     for (int n = threadIdx.x; n < kGTabN; n += kBlock)
-        gt[n] = a.gtab[n];
+        gt[n] = a0.gtab[n];
+    if (threadIdx.x == 0)
+        next_unit(a0, unit);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double lo = d2s[0], hi = d2s[0];
-        for (int t = 1; t < TD; ++t) {
-            lo = fmin(lo, d2s[t]);
-            hi = fmax(hi, d2s[t]);
-        }
-        trange[0] = lo;
-        trange[1] = hi;
-    }
-    __syncthreads();
-    // Delta^2 range of the tile: centre and half-width of the tile series
-    const double x_lo = trange[0], x_hi = trange[1];
-    const double xc = 0.5 * (x_lo + x_hi), ht = 0.5 * (x_hi - x_lo);
-
-    const double *cxt = a.trig;
-    const double *sxt = a.trig + a.Lx;
-    const double *cyt = a.trig + 2 * a.Lx;
-    const double *syt = cyt + a.Ly;
-
-    double acc[TD];
-#pragma unroll
-    for (int t = 0; t < TD; ++t)
-        acc[t] = 0.0;
-    double tm[kTileSlots];
-#pragma unroll
-    for (int n = 0; n < kTileSlots; ++n)
-        tm[n] = 0.0;
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
+    for (;;) {
+        ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(ap));
+        const SweepArgs &a = *(const SweepArgs *)ap;   // the argument, reloaded per unit
+        const int bz = __builtin_amdgcn_readfirstlane(unit[2]);
+        if (bz < 0)
+            break;
+        const int chunk = __builtin_amdgcn_readfirstlane(unit[0]);
+        const int dtile = __builtin_amdgcn_readfirstlane(unit[1]);
+        const int g = bz / a.nbq;                  // point within the batch
+        const int bq = bz - g * a.nbq;
+        const int slot = bq / a.n_q;
+        const int iq = bq - slot * a.n_q;
+        const double eps = slot ? a.eps[1] : a.eps[0];
+        const double qy = a.q[2 * iq + 1];
+        const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
+        const PointRec pt = a.pts[g];
+        const double mu_up = wave_uniform(a.mu + pt.h);   // spin up: E - mu - h
+        const double mu_dn = wave_uniform(a.mu - pt.h);   // spin down: E - mu + h
+        const double T = pt.T;
+        const double invT = wave_uniform(T > 0.0 ? 1.0 / T : 0.0);
+        const double cutT = wave_uniform(kCutFp64 * T);
 
-    const TileList tl = tile_list(a, blockIdx.z, chunk);
-    // the next entry of this wave's walk is fetched one tile ahead
-    int e = __builtin_amdgcn_readfirstlane(wave);
-    int nt_tile = 0;
-    unsigned long long nt_mask = 0ull;
-    if (e < tl.total)
-        listed_tile(tl, e, nt_tile, nt_mask);
-    for (; e < tl.total; e += 4) {
-        const int tile = nt_tile;
-        const unsigned long long mk = nt_mask;
-        if (e + 4 < tl.total)
-            listed_tile(tl, e + 4, nt_tile, nt_mask);
-        const int ti = tile / kr.TYw;
-        const int tj = tile - ti * kr.TYw;
-        const int i = ti * kTileEdge + li;
-        const int j = tj * kTileEdge + lj;
-        // an opaque zero offset keeps the Delta^2 reads from being hoisted
-        // out of the loop into (scarce) scalar registers
-        int zoff = 0;
-        asm volatile("" : "+v"(zoff));
-        const double *dp = d2s + zoff;
-        bool loop = false, tser = false;
-        KQ r;
-        double w = 0.0, Rc2 = 0.0;
-        if ((mk >> lane) & 1ull) {
-            r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
-                             cxt[i], sxt[i], cyt[j], syt[j]);
-            w = mirror_weight(kr, i, j, a.Lx, a.Ly);
-            const double up = r.m + cutT, dn = r.m - cutT;
-            Rc2 = fma(xc, r.eta2, r.s2);
-            // cold and positive over the tile, and the tile series converges
-            tser = fma(x_lo, r.eta2, r.s2) >= up * up && ht * r.eta2 <= kTileRho * Rc2;
-            // exactly zero over the tile where R(x_hi) <= |d| - 36 T
-            loop = !tser && !(dn > 0.0 && fma(x_hi, r.eta2, r.s2) <= dn * dn);
-        }
-        if (tser) {
-            // moments of the tile series, accumulated per lane
-            const double Rc = sqrt_rn(Rc2);
-            // Rc = 0 only with s = 0 and xc eta^2 = 0: the powers vanish
-            const double ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
-            tm[0] = fma(w, Rc - r.m, tm[0]);
-            double tp = w * Rc;
-#pragma unroll
-            for (int n = 1; n < kTileSlots; ++n) {
-                tp *= ratio;
-                tm[n] += tp;
+        const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+        const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+
+        if (threadIdx.x <= TD)
+            d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double lo = d2s[0], hi = d2s[0];
+            for (int t = 1; t < TD; ++t) {
+                lo = fmin(lo, d2s[t]);
+                hi = fmax(hi, d2s[t]);
             }
+            trange[0] = lo;
+            trange[1] = hi;
+            // every thread has read this unit: fetch the next one
+            next_unit(a, unit);
         }
-        if (loop) {
-            const double wT = w * T;
-            ++n_direct;
-            // R^2 >= 1e-300 keeps the reciprocal square root finite; the
-            // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
-            const double s2p = r.s2 + 1e-300;
-            double dcur = dp[0];
-#pragma unroll
-            for (int t = 0; t < TD; ++t) {
-                const double dnext = dp[t + 1];
-                const double R = sqrt_1s(fma(dcur, r.eta2, s2p));
-                const double x = R - r.m;
-                acc[t] = fma(w, fmax(x, 0.0), acc[t]);
-                const double ax = fabs(x);
-                if (ax < cutT) {
-                    // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
-                    double L = log1p_exp_tab(ax * invT, gt);
-                    const double y = R + r.m;
-                    if (y < cutT)
-                        L += log1p_exp_tab(y * invT, gt);
-                    acc[t] = fma(wT, L, acc[t]);
+        __syncthreads();
+        // Delta^2 range of the tile: centre and half-width of the tile series
+        const double x_lo = wave_uniform(trange[0]), x_hi = wave_uniform(trange[1]);
+        const double xc = wave_uniform(0.5 * (x_lo + x_hi));
+        const double ht = wave_uniform(0.5 * (x_hi - x_lo));
+
+        const double *cxt = a.trig;
+        const double *sxt = a.trig + a.Lx;
+        const double *cyt = a.trig + 2 * a.Lx;
+        const double *syt = cyt + a.Ly;
+
+        double acc[TD];
+    #pragma unroll
+        for (int t = 0; t < TD; ++t)
+            acc[t] = 0.0;
+        double tm[kTileSlots];
+    #pragma unroll
+        for (int n = 0; n < kTileSlots; ++n)
+            tm[n] = 0.0;
+
+        const TileList tl = tile_list(a, bz, chunk);
+        // the next entry of this wave's walk is fetched one tile ahead
+        int e = __builtin_amdgcn_readfirstlane(wave);
+        int nt_tile = 0;
+        unsigned long long nt_mask = 0ull;
+        if (e < tl.total)
+            listed_tile(tl, e, nt_tile, nt_mask);
+        for (; e < tl.total; e += 4) {
+            const int tile = nt_tile;
+            const unsigned long long mk = nt_mask;
+            if (e + 4 < tl.total)
+                listed_tile(tl, e + 4, nt_tile, nt_mask);
+            const int ti = tile / kr.TYw;
+            const int tj = tile - ti * kr.TYw;
+            const int i = ti * kTileEdge + li;
+            const int j = tj * kTileEdge + lj;
+            // an opaque zero offset keeps the Delta^2 reads from being hoisted
+            // out of the loop into (scarce) scalar registers
+            int zoff = 0;
+            asm volatile("" : "+v"(zoff));
+            const double *dp = d2s + zoff;
+            bool loop = false, tser = false;
+            KQ r;
+            double w = 0.0, Rc2 = 0.0;
+            if ((mk >> lane) & 1ull) {
+                r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
+                                 cxt[i], sxt[i], cyt[j], syt[j]);
+                w = mirror_weight(kr, i, j, a.Lx, a.Ly);
+                const double up = r.m + cutT, dn = r.m - cutT;
+                Rc2 = fma(xc, r.eta2, r.s2);
+                // cold and positive over the tile, and the tile series converges
+                tser = fma(x_lo, r.eta2, r.s2) >= up * up && ht * r.eta2 <= kTileRho * Rc2;
+                // exactly zero over the tile where R(x_hi) <= |d| - 36 T
+                loop = !tser && !(dn > 0.0 && fma(x_hi, r.eta2, r.s2) <= dn * dn);
+            }
+            if (tser) {
+                // moments of the tile series, accumulated per lane
+                const double Rc = sqrt_rn(Rc2);
+                // Rc = 0 only with s = 0 and xc eta^2 = 0: the powers vanish
+                const double ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
+                tm[0] = fma(w, Rc - r.m, tm[0]);
+                double tp = w * Rc;
+    #pragma unroll
+                for (int n = 1; n < kTileSlots; ++n) {
+                    tp *= ratio;
+                    tm[n] += tp;
                 }
-                dcur = dnext;
+            }
+            n_direct += __popcll(__ballot(loop));
+            if (loop) {
+                const double wT = w * T;
+                // R^2 >= 1e-300 keeps the reciprocal square root finite; the
+                // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
+                const double s2p = r.s2 + 1e-300;
+                double dcur = dp[0];
+    #pragma unroll
+                for (int t = 0; t < TD; ++t) {
+                    const double dnext = dp[t + 1];
+                    const double R = sqrt_1s(fma(dcur, r.eta2, s2p));
+                    const double x = R - r.m;
+                    acc[t] = fma(w, fmax(x, 0.0), acc[t]);
+                    const double ax = fabs(x);
+                    if (ax < cutT) {
+                        // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
+                        double L = log1p_exp_tab(ax * invT, gt);
+                        const double y = R + r.m;
+                        if (y < cutT)
+                            L += log1p_exp_tab(y * invT, gt);
+                        acc[t] = fma(wT, L, acc[t]);
+                    }
+                    dcur = dnext;
+                }
             }
         }
-    }
 
-    if (a.count)
-        count_direct(a.count, n_direct * TD);
-    __shared__ double red[4][64];
-    wave_reduce_halving<TD>(acc, lane);
-    red[wave][lane] = acc[0];
-    __syncthreads();
-    constexpr int SHIFT = 6 - Log2<TD>::value;
-    if (threadIdx.x < TD) {
-        const int src = threadIdx.x << SHIFT;
-        double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-        a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
-               dtile * TD + threadIdx.x] = v;
+        wave_reduce_halving<TD>(acc, lane);
+        red[wave][lane] = acc[0];
+        __syncthreads();
+        constexpr int SHIFT = 6 - Log2<TD>::value;
+        if (threadIdx.x < TD) {
+            const int src = threadIdx.x << SHIFT;
+            double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD + threadIdx.x] = v;
+        }
+        __syncthreads();
+        wave_reduce_halving<kTileSlots>(tm, lane);
+        red[wave][lane] = tm[0];
+        __syncthreads();
+        constexpr int TSHIFT = 6 - Log2<kTileSlots>::value;
+        if (threadIdx.x < kTileSlots) {
+            const int src = threadIdx.x << TSHIFT;
+            a.tpart[(((size_t)bz * a.n_chunks + chunk) * a.n_dtiles + dtile) * kTileSlots +
+                    threadIdx.x] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+        }
+        // the next unit is visible, and red and d2s are free again
+        __syncthreads();
     }
-    __syncthreads();
-    wave_reduce_halving<kTileSlots>(tm, lane);
-    red[wave][lane] = tm[0];
-    __syncthreads();
-    constexpr int TSHIFT = 6 - Log2<kTileSlots>::value;
-    if (threadIdx.x < kTileSlots) {
-        const int src = threadIdx.x << TSHIFT;
-        a.tpart[(((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_dtiles + dtile) * kTileSlots +
-                threadIdx.x] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-    }
+    if (a0.count && lane == 0 && n_direct)
+        atomicAdd(a0.count, (unsigned long long)n_direct * TD);
+}
+
+// Workgroups of a persistent launch: as many as stay resident at once on the
+// current device, but no more than there are units.
+template <typename K>
+static int persistent_blocks(K kernel, unsigned long long units)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
+        return -1;
+    const unsigned long long n = (unsigned long long)cus * (per_cu > 0 ? per_cu : 1);
+    return (int)(n < units ? n : units);
+}
+
+template <int TD, bool B3>
+static hipError_t launch_persistent_f64(const SweepArgs &a, hipStream_t s)
+{
+    const unsigned long long units =
+        (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
+    const int blocks = persistent_blocks(sweep_f64_kernel<TD, B3>, units);
+    if (blocks <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_f64_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                             hipStream_t s)
 {
-    dim3 grid(a.n_chunks, n_dtiles, a.nbq * G);
+    SweepArgs p = a;
+    p.n_dtiles = n_dtiles;
+    p.n_rows = a.nbq * G;
     if (td == 16 && !b3)
-        hipLaunchKernelGGL((sweep_f64_kernel<16, false>), grid, dim3(kBlock), 0, s, a);
-    else if (td == 32 && !b3)
-        hipLaunchKernelGGL((sweep_f64_kernel<32, false>), grid, dim3(kBlock), 0, s, a);
-    else if (td == 16)
-        hipLaunchKernelGGL((sweep_f64_kernel<16, true>), grid, dim3(kBlock), 0, s, a);
-    else if (td == 32)
-        hipLaunchKernelGGL((sweep_f64_kernel<32, true>), grid, dim3(kBlock), 0, s, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return launch_persistent_f64<16, false>(p, s);
+    if (td == 32 && !b3)
+        return launch_persistent_f64<32, false>(p, s);
+    if (td == 16)
+        return launch_persistent_f64<16, true>(p, s);
+    if (td == 32)
+        return launch_persistent_f64<32, true>(p, s);
+    return hipErrorInvalidValue;
 }
 
 // FP32-compensated sweep.  With P(Delta) = max(R - |d|, 0) + T ln((1+u1)(1+u2))
