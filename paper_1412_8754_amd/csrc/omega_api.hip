@@ -306,8 +306,9 @@ void band_signs(int nb, const int *list, double *eps)
 }
 
 // Write the records of points idx[0..G) into the device table.
+// queue (optional): the work-queue counters of the batch, zeroed on the way.
 int upload_points(const omega_point *pts, const int *idx, int G, PointRec *table,
-                  hipStream_t s)
+                  unsigned long long *queue, hipStream_t s)
 {
     for (int b = 0; b < G; b += kFillMax) {
         PointPack pk;
@@ -320,7 +321,7 @@ int upload_points(const omega_point *pts, const int *idx, int G, PointRec *table
             pk.rec[i].out = idx[b + i];
             pk.rec[i].pad = 0;
         }
-        if (launch_fill_points(pk, table + b, s) != hipSuccess)
+        if (launch_fill_points(pk, table + b, queue, s) != hipSuccess)
             return OMEGA_E_HIP;
     }
     return OMEGA_OK;
@@ -466,7 +467,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         const int n = (int)g.idx.size();
         for (int b0 = 0; b0 < n; b0 += P.batch[gi]) {
             const int G = n - b0 < P.batch[gi] ? n - b0 : P.batch[gi];
-            int rc = upload_points(pts, g.idx.data() + b0, G, table, s);
+            int rc = upload_points(pts, g.idx.data() + b0, G, table, queue, s);
             if (rc != OMEGA_OK)
                 return rc;
             if (launch_series(a, G, precision == OMEGA_FP64, md.b3, s) != hipSuccess)
@@ -804,7 +805,7 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
         const int n = (int)g.idx.size();
         for (int b0 = 0; b0 < n; b0 += P.batch[gi]) {
             const int G = n - b0 < P.batch[gi] ? n - b0 : P.batch[gi];
-            int rc = upload_points(pts, g.idx.data() + b0, G, table, s);
+            int rc = upload_points(pts, g.idx.data() + b0, G, table, nullptr, s);
             if (rc != OMEGA_OK)
                 return rc;
             if (launch_grad(a, G, s) != hipSuccess)

@@ -85,8 +85,8 @@ struct PointPack {
 };
 
 // Arguments of one Delta-sweep launch: a batch of G points of one lattice
-// size.  The work splits into (chunk, Delta tile, band*Q + nbq*g) units: the
-// grid of series_kernel and the f32c sweep, the work queue of the FP64 sweep.
+// size.  series_kernel runs on the grid (chunk, band*Q + nbq*g); the sweeps
+// take (chunk, Delta tile, band*Q + nbq*g) units from a work queue.
 struct SweepArgs {
     Hop hop;
     double eps[2];       // two-band: band sign per output slot (-1: E_-, +1: E_+)
@@ -120,7 +120,7 @@ struct SweepArgs {
     int n_dtiles;
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
-    unsigned long long *queue;   // work queue of the persistent FP64 sweep
+    unsigned long long *queue;   // work queue of the persistent sweeps
     int n_rows;          // G * nbq rows of this launch
 };
 
@@ -205,7 +205,8 @@ struct ChiFinishArgs {
 
 hipError_t launch_chi(const ChiArgs &a, bool b3, hipStream_t s);
 hipError_t launch_chi_finish(const ChiFinishArgs &a, hipStream_t s);
-hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s);
+hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, unsigned long long *queue,
+                              hipStream_t s);
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
 hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
 hipError_t launch_gtable(double2 *gtab, hipStream_t s);

@@ -226,16 +226,22 @@ __device__ __forceinline__ void wave_reduce_halving(double (&acc)[TD], int lane)
 // ------------------------------------------------------------------ prep
 
 // Point records of a batch, from kernel arguments into the workspace.
-__global__ void fill_points_kernel(const PointPack pk, PointRec *dst)
+// Also zeroes the work-queue counter of the persistent sweep (queue may be
+// null), which runs after it on the stream.
+__global__ void fill_points_kernel(const PointPack pk, PointRec *dst,
+                                   unsigned long long *queue)
 {
     const int t = threadIdx.x;
     if (t < pk.n)
         dst[t] = pk.rec[t];
+    if (queue && t == 0)
+        queue[0] = 0ull;
 }
 
-hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, hipStream_t s)
+hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, unsigned long long *queue,
+                              hipStream_t s)
 {
-    hipLaunchKernelGGL(fill_points_kernel, dim3(1), dim3(kFillMax), 0, s, pk, dst);
+    hipLaunchKernelGGL(fill_points_kernel, dim3(1), dim3(kFillMax), 0, s, pk, dst, queue);
     return hipGetLastError();
 }
 
@@ -675,23 +681,27 @@ __device__ __forceinline__ void listed_tile(const TileList &t, int e, int &tile,
     mask = t.base[k + 1];
 }
 
-// Per-(k, Q) pass over one (band, Q, point) and momentum chunk, shared by
-// both precisions:
-//   - the Delta-independent part of the term, Neumaier-summed (for the FP32
-//     sweep minus P(0), the full Delta-dependent part at Delta = 0);
-//   - the Delta^2 series moments C0 = sum w (R0 - |d|) (for the FP32 sweep
-//     sum w (R0 - |s|), as |s| - |d| is part of P(0)) and
-//     M_n = sum w R0 (eta^2/R0^2)^n;
-//   - per wave, the list of 8 x 8 tiles with lanes the per-Delta sweep must
-//     evaluate directly, with the ballot of those lanes (the sweeps walk
-//     these lists).
-// Grid (chunk, band*Q + nbq*g).
+// The argument block of a kernel whose only parameter is a SweepArgs: the
+// kernarg segment starts with it.  Reading the fields through this pointer,
+// made opaque once per unit of a persistent kernel, reloads them with scalar
+// loads instead of holding them in registers across the whole unit.
+typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
+
+// A wave-uniform double copied into scalar registers.
+__device__ __forceinline__ double wave_uniform(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Work queue of the persistent sweeps: one 64-bit counter in the workspace,
-// zeroed by series_kernel (which runs before every sweep launch).  Units are
-// numbered chunk fastest, then Delta tile, then row (point of the batch,
-// band, Q).  Writes (chunk, Delta tile, row) of the next unit into unit[],
-// or row -1 once every unit has been taken; each workgroup stops at its
-// first -1, so every one of them ends.
+// zeroed by fill_points_kernel before every batch.  Units are (chunk, Delta
+// tile, row), chunk fastest, then Delta tile.  A workgroup writes the unit
+// it takes into unit[] (in LDS): {chunk, Delta tile, row}, with row -1 once
+// every unit has been taken; it stops at the first -1, so every workgroup
+// ends.
 __device__ __forceinline__ void next_unit(const SweepArgs &a, int *unit)
 {
     const unsigned long long u = atomicAdd(a.queue, 1ull);
@@ -708,12 +718,20 @@ __device__ __forceinline__ void next_unit(const SweepArgs &a, int *unit)
     unit[2] = (int)row;
 }
 
+// Per-(k, Q) pass over one (band, Q, point) and momentum chunk, shared by
+// both precisions:
+//   - the Delta-independent part of the term, Neumaier-summed (for the FP32
+//     sweep minus P(0), the full Delta-dependent part at Delta = 0);
+//   - the Delta^2 series moments C0 = sum w (R0 - |d|) (for the FP32 sweep
+//     sum w (R0 - |s|), as |s| - |d| is part of P(0)) and
+//     M_n = sum w R0 (eta^2/R0^2)^n;
+//   - per wave, the list of 8 x 8 tiles with lanes the per-Delta sweep must
+//     evaluate directly, with the ballot of those lanes (the sweeps walk
+//     these lists).
+// Grid (chunk, band*Q + nbq*g).
 template <bool B3>
 __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
 {
-    // reset the work queue of the sweep that follows on the stream
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-        a.queue[0] = 0ull;
     const int chunk = blockIdx.x;
     const int g = blockIdx.y / a.nbq;
     const int bq = blockIdx.y - g * a.nbq;
@@ -824,25 +842,25 @@ hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStrea
     return hipGetLastError();
 }
 
+// Workgroups of a persistent launch: as many as stay resident at once on the
+// current device, but no more than there are units.
+template <typename K>
+static int persistent_blocks(K kernel, unsigned long long units)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
+        return -1;
+    const unsigned long long n = (unsigned long long)cus * (per_cu > 0 ? per_cu : 1);
+    return (int)(n < units ? n : units);
+}
+
 // Per-Delta FP64 sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.  The kernel is
 // persistent: each workgroup takes (chunk, Delta tile, row) units from the
 // work queue until it runs dry (see next_unit) and loads the thermal table
 // into LDS once.
-// The argument block of a kernel whose only parameter is a SweepArgs: the
-// kernarg segment starts with it.  Reading the fields through this pointer,
-// made opaque once per unit of a persistent kernel, reloads them with scalar
-// loads instead of holding them in registers across the whole unit.
-typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
-
-// A wave-uniform double copied into scalar registers.
-__device__ __forceinline__ double wave_uniform(double v)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void sweep_f64_kernel(const SweepArgs args)
@@ -917,11 +935,11 @@ void sweep_f64_kernel(const SweepArgs args)
         const double *syt = cyt + a.Ly;
 
         double acc[TD];
-    #pragma unroll
+#pragma unroll
         for (int t = 0; t < TD; ++t)
             acc[t] = 0.0;
         double tm[kTileSlots];
-    #pragma unroll
+#pragma unroll
         for (int n = 0; n < kTileSlots; ++n)
             tm[n] = 0.0;
 
@@ -967,7 +985,7 @@ void sweep_f64_kernel(const SweepArgs args)
                 const double ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
                 tm[0] = fma(w, Rc - r.m, tm[0]);
                 double tp = w * Rc;
-    #pragma unroll
+#pragma unroll
                 for (int n = 1; n < kTileSlots; ++n) {
                     tp *= ratio;
                     tm[n] += tp;
@@ -980,7 +998,7 @@ void sweep_f64_kernel(const SweepArgs args)
                 // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
                 const double s2p = r.s2 + 1e-300;
                 double dcur = dp[0];
-    #pragma unroll
+#pragma unroll
                 for (int t = 0; t < TD; ++t) {
                     const double dnext = dp[t + 1];
                     const double R = sqrt_1s(fma(dcur, r.eta2, s2p));
@@ -1026,19 +1044,6 @@ void sweep_f64_kernel(const SweepArgs args)
         atomicAdd(a0.count, (unsigned long long)n_direct * TD);
 }
 
-// Workgroups of a persistent launch: as many as stay resident at once on the
-// current device, but no more than there are units.
-template <typename K>
-static int persistent_blocks(K kernel, unsigned long long units)
-{
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
-        return -1;
-    const unsigned long long n = (unsigned long long)cus * (per_cu > 0 ? per_cu : 1);
-    return (int)(n < units ? n : units);
-}
 
 template <int TD, bool B3>
 static hipError_t launch_persistent_f64(const SweepArgs &a, hipStream_t s)
@@ -1114,136 +1119,166 @@ __device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
     return r;
 }
 
+// The FP32-compensated per-Delta sweep; persistent like the FP64 sweep, with
+// the same work queue and units.
 template <int TD, bool B3>
-__global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs a)
+__global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args)
 {
-    const int chunk = blockIdx.x;
-    const int dtile = blockIdx.y;
-    const int g = blockIdx.z / a.nbq;          // point within the batch
-    const int bq = blockIdx.z - g * a.nbq;
-    const int slot = bq / a.n_q;
-    const int iq = bq - slot * a.n_q;
-    const double eps = slot ? a.eps[1] : a.eps[0];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const double qy = a.q[2 * iq + 1];
-    const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
-    const PointRec pt = a.pts[g];
-    const double mu_up = a.mu + pt.h;
-    const double mu_dn = a.mu - pt.h;
-    const double T = pt.T;
-    const double invT = T > 0.0 ? 1.0 / T : 0.0;
-
-    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
-
     // Delta^2 as an unevaluated FP32 pair hi + lo: rounding Delta^2 to one
     // float would shift every momentum's term at that Delta the same way
     // (a systematic 6e-8), which the sum would not average out
     __shared__ float2 d2s[TD + 1];
-    if (threadIdx.x <= TD) {
-        const double v = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
-        const float hi = (float)v;
-        d2s[threadIdx.x] = make_float2(hi, (float)(v - (double)hi));
-    }
+    __shared__ double red[4][64];
+    __shared__ int unit[3];
+    if (threadIdx.x == 0)
+        next_unit(args, unit);
     __syncthreads();
-
-    const double *cxt = a.trig;
-    const double *sxt = a.trig + a.Lx;
-    const double *cyt = a.trig + 2 * a.Lx;
-    const double *syt = cyt + a.Ly;
-
-    float acc[TD];
-#pragma unroll
-    for (int t = 0; t < TD; ++t)
-        acc[t] = 0.0f;
     int n_direct = 0;
-    const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
     const int li = lane >> 3, lj = lane & 7;
+    for (;;) {
+        const int bz = __builtin_amdgcn_readfirstlane(unit[2]);
+        if (bz < 0)
+            break;
+        ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(ap));
+        const SweepArgs &a = *(const SweepArgs *)ap;   // the argument, reloaded per unit
+        const int chunk = __builtin_amdgcn_readfirstlane(unit[0]);
+        const int dtile = __builtin_amdgcn_readfirstlane(unit[1]);
+        const int g = bz / a.nbq;                  // point within the batch
+        const int bq = bz - g * a.nbq;
+        const int slot = bq / a.n_q;
+        const int iq = bq - slot * a.n_q;
+        const double eps = slot ? a.eps[1] : a.eps[0];
+        const double qy = a.q[2 * iq + 1];
+        const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
+        const PointRec pt = a.pts[g];
+        const double mu_up = a.mu + pt.h;
+        const double mu_dn = a.mu - pt.h;
+        const double T = pt.T;
+        const double invT = T > 0.0 ? 1.0 / T : 0.0;
 
-    const TileList tl = tile_list(a, blockIdx.z, chunk);
-    // the next entry of this wave's walk is fetched one tile ahead
-    int e = __builtin_amdgcn_readfirstlane(wave);
-    int nt_tile = 0;
-    unsigned long long nt_mask = 0ull;
-    if (e < tl.total)
-        listed_tile(tl, e, nt_tile, nt_mask);
-    for (; e < tl.total; e += 4) {
-        const int tile = nt_tile;
-        const unsigned long long mk = nt_mask;
-        if (e + 4 < tl.total)
-            listed_tile(tl, e + 4, nt_tile, nt_mask);
-        const int ti = tile / kr.TYw;
-        const int tj = tile - ti * kr.TYw;
-        const int i = ti * kTileEdge + li;
-        const int j = tj * kTileEdge + lj;
-        int zoff = 0;
-        asm volatile("" : "+v"(zoff));
-        const float2 *dp = d2s + zoff;
-        if ((mk >> lane) & 1ull) {
-            const KQ q64 = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx,
-                                        cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
-            const KQf r = kq_setup_f32(q64, T, invT);
-            const float wf = (float)mirror_weight(kr, i, j, a.Lx, a.Ly);
-            ++n_direct;
-            const bool hot0 = r.P0 != 0.0f;
-            const bool pos = r.A0 >= 0.0f;
-            float2 dcur = dp[0];
+        const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+        const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+
+        if (threadIdx.x <= TD) {
+            const double v = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+            const float hi = (float)v;
+            d2s[threadIdx.x] = make_float2(hi, (float)(v - (double)hi));
+        }
+        __syncthreads();
+        // every thread has read this unit: fetch the next one
+        if (threadIdx.x == 0)
+            next_unit(a, unit);
+
+        const double *cxt = a.trig;
+        const double *sxt = a.trig + a.Lx;
+        const double *cyt = a.trig + 2 * a.Lx;
+        const double *syt = cyt + a.Ly;
+
+        float acc[TD];
 #pragma unroll
-            for (int t = 0; t < TD; ++t) {
-                const float2 dnext = dp[t + 1];
-                float g2 = fmaf(dcur.x, r.eta2, dcur.y * r.eta2);
-                float R = __builtin_amdgcn_sqrtf(r.s2 + g2);
-                float del = g2 * __builtin_amdgcn_rcpf(R + r.as);
-                float x = r.A0 + del;
-                float piece = pos ? del : fmaxf(x, 0.0f);
-                float ax = fabsf(x);
-                if (ax < cutTf || hot0) {
-                    float L = ax < cutTf ? thermal_log_f32(ax, R + r.m, invTf, cutTf)
-                                         : 0.0f;
-                    piece += fmaf(Tf, L, -r.P0);
+        for (int t = 0; t < TD; ++t)
+            acc[t] = 0.0f;
+        const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
+
+        const TileList tl = tile_list(a, bz, chunk);
+        // the next entry of this wave's walk is fetched one tile ahead
+        int e = __builtin_amdgcn_readfirstlane(wave);
+        int nt_tile = 0;
+        unsigned long long nt_mask = 0ull;
+        if (e < tl.total)
+            listed_tile(tl, e, nt_tile, nt_mask);
+        for (; e < tl.total; e += 4) {
+            const int tile = nt_tile;
+            const unsigned long long mk = nt_mask;
+            if (e + 4 < tl.total)
+                listed_tile(tl, e + 4, nt_tile, nt_mask);
+            const int ti = tile / kr.TYw;
+            const int tj = tile - ti * kr.TYw;
+            const int i = ti * kTileEdge + li;
+            const int j = tj * kTileEdge + lj;
+            int zoff = 0;
+            asm volatile("" : "+v"(zoff));
+            const float2 *dp = d2s + zoff;
+            n_direct += __popcll(mk);
+            if ((mk >> lane) & 1ull) {
+                const KQ q64 = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx,
+                                            cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
+                const KQf r = kq_setup_f32(q64, T, invT);
+                const float wf = (float)mirror_weight(kr, i, j, a.Lx, a.Ly);
+                const bool hot0 = r.P0 != 0.0f;
+                const bool pos = r.A0 >= 0.0f;
+                float2 dcur = dp[0];
+#pragma unroll
+                for (int t = 0; t < TD; ++t) {
+                    const float2 dnext = dp[t + 1];
+                    float g2 = fmaf(dcur.x, r.eta2, dcur.y * r.eta2);
+                    float R = __builtin_amdgcn_sqrtf(r.s2 + g2);
+                    float del = g2 * __builtin_amdgcn_rcpf(R + r.as);
+                    float x = r.A0 + del;
+                    float piece = pos ? del : fmaxf(x, 0.0f);
+                    float ax = fabsf(x);
+                    if (ax < cutTf || hot0) {
+                        float L = ax < cutTf ? thermal_log_f32(ax, R + r.m, invTf, cutTf)
+                                             : 0.0f;
+                        piece += fmaf(Tf, L, -r.P0);
+                    }
+                    acc[t] = fmaf(wf, piece, acc[t]);
+                    dcur = dnext;
                 }
-                acc[t] = fmaf(wf, piece, acc[t]);
-                dcur = dnext;
             }
         }
-    }
 
-    // Delta = 0 slots: the FP32 difference is zero by construction
-    double accd[TD];
+        // Delta = 0 slots: the FP32 difference is zero by construction
+        double accd[TD];
 #pragma unroll
-    for (int t = 0; t < TD; ++t)
-        accd[t] = (d2s[t].x == 0.0f && d2s[t].y == 0.0f) ? 0.0 : (double)acc[t];
-    if (a.count)
-        count_direct(a.count, n_direct * TD);
-    __shared__ double red[4][64];
-    wave_reduce_halving<TD>(accd, lane);
-    red[wave][lane] = accd[0];
-    __syncthreads();
-    constexpr int SHIFT = 6 - Log2<TD>::value;
-    if (threadIdx.x < TD) {
-        const int src = threadIdx.x << SHIFT;
-        double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-        a.part[((size_t)blockIdx.z * a.n_chunks + chunk) * a.n_delta_pad +
-               dtile * TD + threadIdx.x] = v;
+        for (int t = 0; t < TD; ++t)
+            accd[t] = (d2s[t].x == 0.0f && d2s[t].y == 0.0f) ? 0.0 : (double)acc[t];
+        wave_reduce_halving<TD>(accd, lane);
+        red[wave][lane] = accd[0];
+        __syncthreads();
+        constexpr int SHIFT = 6 - Log2<TD>::value;
+        if (threadIdx.x < TD) {
+            const int src = threadIdx.x << SHIFT;
+            double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
+            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD + threadIdx.x] = v;
+        }
+        // the next unit is visible, and red and d2s are free again
+        __syncthreads();
     }
+    if (args.count && lane == 0 && n_direct)
+        atomicAdd(args.count, (unsigned long long)n_direct * TD);
+}
+
+template <int TD, bool B3>
+static hipError_t launch_persistent_f32c(const SweepArgs &a, hipStream_t s)
+{
+    const unsigned long long units =
+        (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
+    const int blocks = persistent_blocks(sweep_f32c_kernel<TD, B3>, units);
+    if (blocks <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_f32c_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
 }
 
 hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                              hipStream_t s)
 {
-    dim3 grid(a.n_chunks, n_dtiles, a.nbq * G);
+    SweepArgs p = a;
+    p.n_dtiles = n_dtiles;
+    p.n_rows = a.nbq * G;
     if (td == 16 && !b3)
-        hipLaunchKernelGGL((sweep_f32c_kernel<16, false>), grid, dim3(kBlock), 0, s, a);
-    else if (td == 32 && !b3)
-        hipLaunchKernelGGL((sweep_f32c_kernel<32, false>), grid, dim3(kBlock), 0, s, a);
-    else if (td == 16)
-        hipLaunchKernelGGL((sweep_f32c_kernel<16, true>), grid, dim3(kBlock), 0, s, a);
-    else if (td == 32)
-        hipLaunchKernelGGL((sweep_f32c_kernel<32, true>), grid, dim3(kBlock), 0, s, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+        return launch_persistent_f32c<16, false>(p, s);
+    if (td == 32 && !b3)
+        return launch_persistent_f32c<32, false>(p, s);
+    if (td == 16)
+        return launch_persistent_f32c<16, true>(p, s);
+    if (td == 32)
+        return launch_persistent_f32c<32, true>(p, s);
+    return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------- pair susceptibility
