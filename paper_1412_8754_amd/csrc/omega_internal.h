@@ -51,6 +51,54 @@ constexpr double kSeriesRho = 1.0 / 3.0;
 constexpr int kSeriesTerms = 31;
 constexpr int kMomentSlots = 32;   // C0, M_1..M_31
 
+// A wave whose series terms all have a smaller ratio rho = hw eta^2 / R0^2
+// needs fewer terms for the same bound: N terms suffice while
+// |c_{N+1}| rho^{N+1} / (1 - rho) stays below the bound above.  The wave
+// takes the smallest of the levels kSeriesLevel[] that covers all its lanes;
+// series_level_rho(N) is the largest rho that N terms cover (by bisection).
+// With the paper-scale workload a wave needs 7 terms on average.
+constexpr int kSeriesLevels = 4;
+constexpr int kSeriesLevel[kSeriesLevels] = {6, 10, 16, kSeriesTerms};
+
+constexpr double abs_half_binomial(int n)
+{
+    double c = 1.0;
+    for (int k = 1; k <= n; ++k)
+        c *= (k - 1.5 < 0.0 ? 1.5 - k : k - 1.5) / k;
+    return c;
+}
+
+constexpr double series_tail(int N, double rho)
+{
+    double p = 1.0;
+    for (int k = 0; k <= N; ++k)
+        p *= rho;
+    return abs_half_binomial(N + 1) * p / (1.0 - rho);
+}
+
+constexpr double series_level_rho(int N)
+{
+    const double bound = series_tail(kSeriesTerms, kSeriesRho);
+    double lo = 0.0, hi = kSeriesRho;
+    for (int it = 0; it < 80; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (series_tail(N, mid) <= bound)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return N >= kSeriesTerms ? kSeriesRho : lo;
+}
+
+struct SeriesLevelRho {
+    double v[kSeriesLevels];
+    constexpr SeriesLevelRho() : v()
+    {
+        for (int k = 0; k < kSeriesLevels; ++k)
+            v[k] = series_level_rho(kSeriesLevel[k]);
+    }
+};
+
 // Tile series of the FP64 sweep.  Within one Delta tile (the TD Delta of a
 // sweep workgroup; x = Delta^2 in [x_lo, x_hi], centre xc, half-width ht), a
 // direct term that is cold and positive over the whole tile

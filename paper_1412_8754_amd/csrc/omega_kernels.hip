@@ -718,6 +718,18 @@ __device__ __forceinline__ void next_unit(const SweepArgs &a, int *unit)
     unit[2] = (int)row;
 }
 
+// Largest ratio of each series level (see kSeriesLevel).
+__constant__ constexpr SeriesLevelRho kLevelRho{};
+
+// Whether m terms is one of the series levels short of the full count.
+__device__ constexpr bool is_series_level(int m)
+{
+    for (int k = 0; k + 1 < kSeriesLevels; ++k)
+        if (kSeriesLevel[k] == m)
+            return true;
+    return false;
+}
+
 // Per-(k, Q) pass over one (band, Q, point) and momentum chunk, shared by
 // both precisions:
 //   - the Delta-independent part of the term, Neumaier-summed (for the FP32
@@ -729,8 +741,11 @@ __device__ __forceinline__ void next_unit(const SweepArgs &a, int *unit)
 //     evaluate directly, with the ballot of those lanes (the sweeps walk
 //     these lists).
 // Grid (chunk, band*Q + nbq*g).
+// Two-band: 4 waves/SIMD (a few spills outside the moment loop beat the
+// 3-wave occupancy its registers would otherwise give); three-band: 3.
 template <bool B3>
-__global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int fp64)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B3 ? 3 : 4)))
+void series_kernel(const SweepArgs a, int fp64)
 {
     const int chunk = blockIdx.x;
     const int g = blockIdx.y / a.nbq;
@@ -792,9 +807,19 @@ __global__ __launch_bounds__(kBlock) void series_kernel(const SweepArgs a, int f
                 mom[0] = fma(w, c0, mom[0]);
                 // R0 = 0 only with s = 0 and eta^2 x0 = 0: then the powers vanish
                 const double ratio = R02 > 0.0 ? r.eta2 * rcp_nr(R02) : 0.0;
+                // terms this wave needs: the smallest level that covers the
+                // ratio of every series lane (the active lanes here)
+                const double rho = hw * ratio;
+                int nt = kSeriesTerms;
+#pragma unroll
+                for (int k = kSeriesLevels - 2; k >= 0; --k)
+                    if (__ballot(rho > kLevelRho.v[k]) == 0ull)
+                        nt = kSeriesLevel[k];
                 double t = w * R0;
 #pragma unroll
                 for (int n = 1; n <= kSeriesTerms; ++n) {
+                    if (is_series_level(n - 1) && n > nt)
+                        break;
                     t *= ratio;
                     mom[n] += t;
                 }
