@@ -696,6 +696,12 @@ __device__ __forceinline__ double wave_uniform(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Per-unit constants of the FP64 sweep, in LDS: the tile's Delta^2 range
+// [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T and the cut 36 T.
+enum {
+    kUcXlo, kUcXhi, kUcXc, kUcHt, kUcMuUp, kUcMuDn, kUcT, kUcInvT, kUcCutT, kUnitConsts
+};
+
 // Work queue of the persistent sweeps: one 64-bit counter in the workspace,
 // zeroed by fill_points_kernel before every batch.  Units are (chunk, Delta
 // tile, row), chunk fastest, then Delta tile.  A workgroup writes the unit
@@ -895,10 +901,11 @@ void sweep_f64_kernel(const SweepArgs args)
     const int wave = threadIdx.x >> 6;
     // Delta^2 of the unit's tile, read from LDS inside the loop (one extra
     // slot for the look-ahead read of the last iteration), the thermal
-    // table, the tile's Delta^2 range and the next unit
+    // table, the unit's constants (kept in LDS rather than in registers
+    // across the tile loop) and the next unit
     __shared__ double d2s[TD + 1];
     __shared__ double2 gt[kGTabN];
-    __shared__ double trange[2];
+    __shared__ double uc[kUnitConsts];
     __shared__ double red[4][64];
     __shared__ int unit[3];
     for (int n = threadIdx.x; n < kGTabN; n += kBlock)
@@ -924,12 +931,6 @@ void sweep_f64_kernel(const SweepArgs args)
         const double eps = slot ? a.eps[1] : a.eps[0];
         const double qy = a.q[2 * iq + 1];
         const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
-        const PointRec pt = a.pts[g];
-        const double mu_up = wave_uniform(a.mu + pt.h);   // spin up: E - mu - h
-        const double mu_dn = wave_uniform(a.mu - pt.h);   // spin down: E - mu + h
-        const double T = pt.T;
-        const double invT = wave_uniform(T > 0.0 ? 1.0 / T : 0.0);
-        const double cutT = wave_uniform(kCutFp64 * T);
 
         const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
         const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
@@ -943,16 +944,21 @@ void sweep_f64_kernel(const SweepArgs args)
                 lo = fmin(lo, d2s[t]);
                 hi = fmax(hi, d2s[t]);
             }
-            trange[0] = lo;
-            trange[1] = hi;
+            // Delta^2 range of the tile, centre and half-width of the tile series
+            uc[kUcXlo] = lo;
+            uc[kUcXhi] = hi;
+            uc[kUcXc] = 0.5 * (lo + hi);
+            uc[kUcHt] = 0.5 * (hi - lo);
+            const PointRec pt = a.pts[g];
+            uc[kUcMuUp] = a.mu + pt.h;   // spin up: E - mu - h
+            uc[kUcMuDn] = a.mu - pt.h;   // spin down: E - mu + h
+            uc[kUcT] = pt.T;
+            uc[kUcInvT] = pt.T > 0.0 ? 1.0 / pt.T : 0.0;
+            uc[kUcCutT] = kCutFp64 * pt.T;
             // every thread has read this unit: fetch the next one
             next_unit(a, unit);
         }
         __syncthreads();
-        // Delta^2 range of the tile: centre and half-width of the tile series
-        const double x_lo = wave_uniform(trange[0]), x_hi = wave_uniform(trange[1]);
-        const double xc = wave_uniform(0.5 * (x_lo + x_hi));
-        const double ht = wave_uniform(0.5 * (x_hi - x_lo));
 
         const double *cxt = a.trig;
         const double *sxt = a.trig + a.Lx;
@@ -984,20 +990,24 @@ void sweep_f64_kernel(const SweepArgs args)
             const int tj = tile - ti * kr.TYw;
             const int i = ti * kTileEdge + li;
             const int j = tj * kTileEdge + lj;
-            // an opaque zero offset keeps the Delta^2 reads from being hoisted
-            // out of the loop into (scarce) scalar registers
+            // an opaque zero offset keeps the Delta^2 and unit-constant reads
+            // in LDS, read per tile, instead of hoisting them out of the loop
+            // into (scarce) registers
             int zoff = 0;
             asm volatile("" : "+v"(zoff));
             const double *dp = d2s + zoff;
+            const double *cp = uc + zoff;
+            const double cutT = cp[kUcCutT];
             bool loop = false, tser = false;
             KQ r;
             double w = 0.0, Rc2 = 0.0;
             if ((mk >> lane) & 1ull) {
-                r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy, sqy,
-                                 cxt[i], sxt[i], cyt[j], syt[j]);
+                r = kq_setup<B3>(a, slot, iq, i, j, eps, cp[kUcMuUp], cp[kUcMuDn], cqx, sqx,
+                                 cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
                 w = mirror_weight(kr, i, j, a.Lx, a.Ly);
                 const double up = r.m + cutT, dn = r.m - cutT;
-                Rc2 = fma(xc, r.eta2, r.s2);
+                const double x_lo = cp[kUcXlo], x_hi = cp[kUcXhi], ht = cp[kUcHt];
+                Rc2 = fma(cp[kUcXc], r.eta2, r.s2);
                 // cold and positive over the tile, and the tile series converges
                 tser = fma(x_lo, r.eta2, r.s2) >= up * up && ht * r.eta2 <= kTileRho * Rc2;
                 // exactly zero over the tile where R(x_hi) <= |d| - 36 T
@@ -1018,7 +1028,8 @@ void sweep_f64_kernel(const SweepArgs args)
             }
             n_direct += __popcll(__ballot(loop));
             if (loop) {
-                const double wT = w * T;
+                const double wT = w * cp[kUcT];
+                const double invT = cp[kUcInvT];
                 // R^2 >= 1e-300 keeps the reciprocal square root finite; the
                 // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
                 const double s2p = r.s2 + 1e-300;
