@@ -28,6 +28,7 @@ constexpr int kMaxDelta = 1 << 20;
 constexpr int kMaxQ = 16384;
 constexpr int kMaxPoints = 1 << 24;
 constexpr int kMinWorkgroups = 4096;       // per point, below this chunks split finer
+constexpr int kMinLaunchUnits = 24576;     // per point: 8 sweep units per resident wave
 constexpr size_t kBatchBytes = 512u << 20; // chunk partials of one batch
 constexpr int kMaxGridZ = 65535;
 constexpr int kGradTilesPerChunk = 64;
@@ -119,8 +120,11 @@ struct Tiles {
     int TX, TY, n_tiles, n_chunks;
 };
 
-// Sweep chunking of one point: 256 tiles per chunk, fewer while a single
-// point would give less than kMinWorkgroups workgroups.
+// Sweep chunking of one point: 256 tiles per chunk, fewer while the point
+// would give less than kMinWorkgroups series workgroups (chunks times the
+// other grid dimensions), down to 4 tiles, or less than kMinLaunchUnits
+// units to the persistent sweep, down to 64 tiles.  It depends on the point
+// and the call's Delta/Q/band counts only.
 Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
 {
     Tiles r;
@@ -128,9 +132,12 @@ Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
     r.TY = (Ly + kTileEdge - 1) / kTileEdge;
     r.n_tiles = r.TX * r.TY;
     int tpw = 256;
-    while (tpw > 4 &&
-           (long long)((r.n_tiles + tpw - 1) / tpw) * other_blocks < kMinWorkgroups)
+    for (;;) {
+        const long long units = (long long)((r.n_tiles + tpw - 1) / tpw) * other_blocks;
+        if (!((tpw > 4 && units < kMinWorkgroups) || (tpw > 64 && units < kMinLaunchUnits)))
+            break;
         tpw /= 2;
+    }
     r.n_chunks = (r.n_tiles + tpw - 1) / tpw;
     return r;
 }
@@ -249,7 +256,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_etab = p.off_tpart + align_up(tpart);
     p.off_qlat = p.off_etab + align_up(etab);
     p.off_queue = p.off_qlat + align_up(sizeof(int) * 2 * (size_t)n_q);
-    p.sweep_bytes = p.off_queue + align_up(sizeof(unsigned long long));
+    p.sweep_bytes = p.off_queue + align_up(sizeof(unsigned long long) * kQueues * kQueueStride);
     return p;
 }
 

@@ -115,6 +115,12 @@ constexpr int kTileSlots = 16;
 constexpr int kTileBatch = 64;   // Delta tiles per LDS batch of the rows kernel
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+
+// Work queues of the persistent sweeps: kQueues counters, each on its own
+// 256-byte line (one counter sustains about 80 device-scope atomics per
+// microsecond, eight on separate lines about 500).
+constexpr int kQueues = 8;
+constexpr int kQueueStride = 32;   // unsigned long long
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
 
 // Per-point record of a batch, written into the workspace by fill_points.
@@ -168,7 +174,8 @@ struct SweepArgs {
     int n_dtiles;
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
-    unsigned long long *queue;   // work queue of the persistent sweeps
+    unsigned long long *queue;   // work-queue counters of the persistent sweeps,
+                                 // kQueues of them kQueueStride apart
     int n_rows;          // G * nbq rows of this launch
 };
 

@@ -226,16 +226,17 @@ __device__ __forceinline__ void wave_reduce_halving(double (&acc)[TD], int lane)
 // ------------------------------------------------------------------ prep
 
 // Point records of a batch, from kernel arguments into the workspace.
-// Also zeroes the work-queue counter of the persistent sweep (queue may be
+// Also zeroes the work-queue counters of the persistent sweep (queue may be
 // null), which runs after it on the stream.
+static_assert(kQueues <= kFillMax, "fill_points_kernel zeroes the queues");
 __global__ void fill_points_kernel(const PointPack pk, PointRec *dst,
                                    unsigned long long *queue)
 {
     const int t = threadIdx.x;
     if (t < pk.n)
         dst[t] = pk.rec[t];
-    if (queue && t == 0)
-        queue[0] = 0ull;
+    if (queue && t < kQueues)
+        queue[(size_t)t * kQueueStride] = 0ull;
 }
 
 hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, unsigned long long *queue,
@@ -702,26 +703,36 @@ enum {
     kUcXlo, kUcXhi, kUcXc, kUcHt, kUcMuUp, kUcMuDn, kUcT, kUcInvT, kUcCutT, kUnitConsts
 };
 
-// Work queue of the persistent sweeps: one 64-bit counter in the workspace,
-// zeroed by fill_points_kernel before every batch.  Units are (chunk, Delta
-// tile, row), chunk fastest, then Delta tile.  A workgroup writes the unit
-// it takes into unit[] (in LDS): {chunk, Delta tile, row}, with row -1 once
-// every unit has been taken; it stops at the first -1, so every workgroup
-// ends.
-__device__ __forceinline__ void next_unit(const SweepArgs &a, int *unit)
+// Work queues of the persistent sweeps: kQueues 64-bit counters in the
+// workspace, zeroed by fill_points_kernel before every batch.  Units are
+// (chunk, Delta tile, row), numbered chunk fastest, then Delta tile; queue q
+// hands out the units u = q, q + nq, q + 2 nq, ... and is served by the
+// workgroups with blockIdx.x = q mod nq, nq = kQueues (1 for a grid of
+// fewer workgroups), so every unit has a taker whatever the placement of
+// the workgroups.  take_unit returns the next unit of queue q as {chunk,
+// Delta tile, row}, with row -1 once the queue is empty; a wave stops at the
+// first -1, so every wave ends.
+__device__ __forceinline__ int sweep_queues()
 {
-    const unsigned long long u = atomicAdd(a.queue, 1ull);
+    return gridDim.x < (unsigned)kQueues ? 1 : kQueues;
+}
+
+__device__ __forceinline__ int3 take_unit(const SweepArgs &a, int q, int nq)
+{
+    const unsigned long long k = atomicAdd(a.queue + (size_t)q * kQueueStride, 1ull);
+    const unsigned long long u = (unsigned long long)q + (unsigned long long)nq * k;
     const unsigned long long per_row = (unsigned long long)a.n_chunks * a.n_dtiles;
-    if (u >= per_row * (unsigned long long)a.n_rows) {
-        unit[2] = -1;
-        return;
-    }
+    if (u >= per_row * (unsigned long long)a.n_rows)
+        return make_int3(0, 0, -1);
     const unsigned long long row = u / per_row;
     const unsigned long long rest = u - row * per_row;
     const unsigned long long dtile = rest / (unsigned long long)a.n_chunks;
-    unit[0] = (int)(rest - dtile * (unsigned long long)a.n_chunks);
-    unit[1] = (int)dtile;
-    unit[2] = (int)row;
+    // the chunk index rotated by Delta tile and row (a bijection for each of
+    // them), so that every queue sees chunks from the whole zone
+    const unsigned long long chunk =
+        (rest - dtile * (unsigned long long)a.n_chunks + dtile + row) %
+        (unsigned long long)a.n_chunks;
+    return make_int3((int)chunk, (int)dtile, (int)row);
 }
 
 // Largest ratio of each series level (see kSeriesLevel).
@@ -889,9 +900,11 @@ static int persistent_blocks(K kernel, unsigned long long units)
 
 // Per-Delta FP64 sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.  The kernel is
-// persistent: each workgroup takes (chunk, Delta tile, row) units from the
-// work queue until it runs dry (see next_unit) and loads the thermal table
-// into LDS once.
+// persistent and each wave works on its own: it takes (chunk, Delta tile,
+// row) units from the work queue until it runs dry (see take_unit), walks
+// all listed tiles of the unit's chunk and writes the unit's sums itself, so
+// no wave waits for another.  The workgroup only shares the thermal table,
+// loaded into LDS once.
 template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
 void sweep_f64_kernel(const SweepArgs args)
@@ -899,31 +912,32 @@ void sweep_f64_kernel(const SweepArgs args)
     const SweepArgs &a0 = args;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    // Delta^2 of the unit's tile, read from LDS inside the loop (one extra
-    // slot for the look-ahead read of the last iteration), the thermal
-    // table, the unit's constants (kept in LDS rather than in registers
-    // across the tile loop) and the next unit
-    __shared__ double d2s[TD + 1];
+    // per wave: Delta^2 of the unit's tile, read from LDS inside the loop
+    // (one extra slot for the look-ahead read of the last iteration), and
+    // the unit's constants (kept in LDS rather than in registers across the
+    // tile loop); per workgroup: the thermal table
+    __shared__ double d2s[4][TD + 1];
+    __shared__ double uc[4][kUnitConsts];
     __shared__ double2 gt[kGTabN];
-    __shared__ double uc[kUnitConsts];
-    __shared__ double red[4][64];
-    __shared__ int unit[3];
     for (int n = threadIdx.x; n < kGTabN; n += kBlock)
         gt[n] = a0.gtab[n];
-    if (threadIdx.x == 0)
-        next_unit(a0, unit);
     __syncthreads();
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
+    const int nq = sweep_queues();
+    const int q = (int)(blockIdx.x % (unsigned)nq);
     for (;;) {
         ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
         asm volatile("" : "+s"(ap));
         const SweepArgs &a = *(const SweepArgs *)ap;   // the argument, reloaded per unit
-        const int bz = __builtin_amdgcn_readfirstlane(unit[2]);
+        int3 un = make_int3(0, 0, -1);
+        if (lane == 0)
+            un = take_unit(a, q, nq);
+        const int bz = __builtin_amdgcn_readfirstlane(un.z);
         if (bz < 0)
             break;
-        const int chunk = __builtin_amdgcn_readfirstlane(unit[0]);
-        const int dtile = __builtin_amdgcn_readfirstlane(unit[1]);
+        const int chunk = __builtin_amdgcn_readfirstlane(un.x);
+        const int dtile = __builtin_amdgcn_readfirstlane(un.y);
         const int g = bz / a.nbq;                  // point within the batch
         const int bq = bz - g * a.nbq;
         const int slot = bq / a.n_q;
@@ -931,34 +945,37 @@ void sweep_f64_kernel(const SweepArgs args)
         const double eps = slot ? a.eps[1] : a.eps[0];
         const double qy = a.q[2 * iq + 1];
         const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
-
         const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
         const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
 
-        if (threadIdx.x <= TD)
-            d2s[threadIdx.x] = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double lo = d2s[0], hi = d2s[0];
-            for (int t = 1; t < TD; ++t) {
-                lo = fmin(lo, d2s[t]);
-                hi = fmax(hi, d2s[t]);
-            }
-            // Delta^2 range of the tile, centre and half-width of the tile series
-            uc[kUcXlo] = lo;
-            uc[kUcXhi] = hi;
-            uc[kUcXc] = 0.5 * (lo + hi);
-            uc[kUcHt] = 0.5 * (hi - lo);
-            const PointRec pt = a.pts[g];
-            uc[kUcMuUp] = a.mu + pt.h;   // spin up: E - mu - h
-            uc[kUcMuDn] = a.mu - pt.h;   // spin down: E - mu + h
-            uc[kUcT] = pt.T;
-            uc[kUcInvT] = pt.T > 0.0 ? 1.0 / pt.T : 0.0;
-            uc[kUcCutT] = kCutFp64 * pt.T;
-            // every thread has read this unit: fetch the next one
-            next_unit(a, unit);
+        // the tile's Delta^2 (the padding repeats the last value) and range
+        const double dl = a.d2[dtile * TD + (lane < TD ? lane : TD - 1)];
+        double lo = dl, hi = dl;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off, 64));
+            hi = fmax(hi, __shfl_xor(hi, off, 64));
         }
-        __syncthreads();
+        if (lane <= TD)
+            d2s[wave][lane] = dl;
+        if (lane == 0) {
+            // centre and half-width of the tile series
+            double *u = uc[wave];
+            u[kUcXlo] = lo;
+            u[kUcXhi] = hi;
+            u[kUcXc] = 0.5 * (lo + hi);
+            u[kUcHt] = 0.5 * (hi - lo);
+            const PointRec pt = a.pts[g];
+            u[kUcMuUp] = a.mu + pt.h;   // spin up: E - mu - h
+            u[kUcMuDn] = a.mu - pt.h;   // spin down: E - mu + h
+            u[kUcT] = pt.T;
+            u[kUcInvT] = pt.T > 0.0 ? 1.0 / pt.T : 0.0;
+            u[kUcCutT] = kCutFp64 * pt.T;
+        }
+        // the wave's LDS writes above are visible to all of its lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         const double *cxt = a.trig;
         const double *sxt = a.trig + a.Lx;
@@ -975,17 +992,17 @@ void sweep_f64_kernel(const SweepArgs args)
             tm[n] = 0.0;
 
         const TileList tl = tile_list(a, bz, chunk);
-        // the next entry of this wave's walk is fetched one tile ahead
-        int e = __builtin_amdgcn_readfirstlane(wave);
+        // the next entry of the walk is fetched one tile ahead
+        int e = 0;
         int nt_tile = 0;
         unsigned long long nt_mask = 0ull;
         if (e < tl.total)
             listed_tile(tl, e, nt_tile, nt_mask);
-        for (; e < tl.total; e += 4) {
+        for (; e < tl.total; ++e) {
             const int tile = nt_tile;
             const unsigned long long mk = nt_mask;
-            if (e + 4 < tl.total)
-                listed_tile(tl, e + 4, nt_tile, nt_mask);
+            if (e + 1 < tl.total)
+                listed_tile(tl, e + 1, nt_tile, nt_mask);
             const int ti = tile / kr.TYw;
             const int tj = tile - ti * kr.TYw;
             const int i = ti * kTileEdge + li;
@@ -995,8 +1012,8 @@ void sweep_f64_kernel(const SweepArgs args)
             // into (scarce) registers
             int zoff = 0;
             asm volatile("" : "+v"(zoff));
-            const double *dp = d2s + zoff;
-            const double *cp = uc + zoff;
+            const double *dp = d2s[wave] + zoff;
+            const double *cp = uc[wave] + zoff;
             const double cutT = cp[kUcCutT];
             bool loop = false, tser = false;
             KQ r;
@@ -1054,32 +1071,22 @@ void sweep_f64_kernel(const SweepArgs args)
             }
         }
 
+        // the unit's sums: lane t << SHIFT holds Delta t, lane n << TSHIFT
+        // moment n
         wave_reduce_halving<TD>(acc, lane);
-        red[wave][lane] = acc[0];
-        __syncthreads();
         constexpr int SHIFT = 6 - Log2<TD>::value;
-        if (threadIdx.x < TD) {
-            const int src = threadIdx.x << SHIFT;
-            double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD + threadIdx.x] = v;
-        }
-        __syncthreads();
+        if ((lane & ((1 << SHIFT) - 1)) == 0)
+            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD +
+                   (lane >> SHIFT)] = acc[0];
         wave_reduce_halving<kTileSlots>(tm, lane);
-        red[wave][lane] = tm[0];
-        __syncthreads();
         constexpr int TSHIFT = 6 - Log2<kTileSlots>::value;
-        if (threadIdx.x < kTileSlots) {
-            const int src = threadIdx.x << TSHIFT;
+        if ((lane & ((1 << TSHIFT) - 1)) == 0)
             a.tpart[(((size_t)bz * a.n_chunks + chunk) * a.n_dtiles + dtile) * kTileSlots +
-                    threadIdx.x] = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-        }
-        // the next unit is visible, and red and d2s are free again
-        __syncthreads();
+                    (lane >> TSHIFT)] = tm[0];
     }
     if (a0.count && lane == 0 && n_direct)
         atomicAdd(a0.count, (unsigned long long)n_direct * TD);
 }
-
 
 template <int TD, bool B3>
 static hipError_t launch_persistent_f64(const SweepArgs &a, hipStream_t s)
@@ -1156,32 +1163,33 @@ __device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
 }
 
 // The FP32-compensated per-Delta sweep; persistent like the FP64 sweep, with
-// the same work queue and units.
+// the same work queue and units, one unit per wave at a time.
 template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    // Delta^2 as an unevaluated FP32 pair hi + lo: rounding Delta^2 to one
-    // float would shift every momentum's term at that Delta the same way
-    // (a systematic 6e-8), which the sum would not average out
-    __shared__ float2 d2s[TD + 1];
-    __shared__ double red[4][64];
-    __shared__ int unit[3];
-    if (threadIdx.x == 0)
-        next_unit(args, unit);
-    __syncthreads();
+    // per wave: Delta^2 of the unit's tile as an unevaluated FP32 pair
+    // hi + lo (rounding Delta^2 to one float would shift every momentum's
+    // term at that Delta the same way, a systematic 6e-8 that the sum would
+    // not average out)
+    __shared__ float2 d2s[4][TD + 1];
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
+    const int nq = sweep_queues();
+    const int q = (int)(blockIdx.x % (unsigned)nq);
     for (;;) {
-        const int bz = __builtin_amdgcn_readfirstlane(unit[2]);
-        if (bz < 0)
-            break;
         ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
         asm volatile("" : "+s"(ap));
         const SweepArgs &a = *(const SweepArgs *)ap;   // the argument, reloaded per unit
-        const int chunk = __builtin_amdgcn_readfirstlane(unit[0]);
-        const int dtile = __builtin_amdgcn_readfirstlane(unit[1]);
+        int3 un = make_int3(0, 0, -1);
+        if (lane == 0)
+            un = take_unit(a, q, nq);
+        const int bz = __builtin_amdgcn_readfirstlane(un.z);
+        if (bz < 0)
+            break;
+        const int chunk = __builtin_amdgcn_readfirstlane(un.x);
+        const int dtile = __builtin_amdgcn_readfirstlane(un.y);
         const int g = bz / a.nbq;                  // point within the batch
         const int bq = bz - g * a.nbq;
         const int slot = bq / a.n_q;
@@ -1198,15 +1206,15 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
         const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
         const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
 
-        if (threadIdx.x <= TD) {
-            const double v = a.d2[dtile * TD + (threadIdx.x < TD ? threadIdx.x : TD - 1)];
+        if (lane <= TD) {
+            const double v = a.d2[dtile * TD + (lane < TD ? lane : TD - 1)];
             const float hi = (float)v;
-            d2s[threadIdx.x] = make_float2(hi, (float)(v - (double)hi));
+            d2s[wave][lane] = make_float2(hi, (float)(v - (double)hi));
         }
-        __syncthreads();
-        // every thread has read this unit: fetch the next one
-        if (threadIdx.x == 0)
-            next_unit(a, unit);
+        // the wave's LDS writes above are visible to all of its lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
         const double *cxt = a.trig;
         const double *sxt = a.trig + a.Lx;
@@ -1220,24 +1228,24 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
         const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
 
         const TileList tl = tile_list(a, bz, chunk);
-        // the next entry of this wave's walk is fetched one tile ahead
-        int e = __builtin_amdgcn_readfirstlane(wave);
+        // the next entry of the walk is fetched one tile ahead
+        int e = 0;
         int nt_tile = 0;
         unsigned long long nt_mask = 0ull;
         if (e < tl.total)
             listed_tile(tl, e, nt_tile, nt_mask);
-        for (; e < tl.total; e += 4) {
+        for (; e < tl.total; ++e) {
             const int tile = nt_tile;
             const unsigned long long mk = nt_mask;
-            if (e + 4 < tl.total)
-                listed_tile(tl, e + 4, nt_tile, nt_mask);
+            if (e + 1 < tl.total)
+                listed_tile(tl, e + 1, nt_tile, nt_mask);
             const int ti = tile / kr.TYw;
             const int tj = tile - ti * kr.TYw;
             const int i = ti * kTileEdge + li;
             const int j = tj * kTileEdge + lj;
             int zoff = 0;
             asm volatile("" : "+v"(zoff));
-            const float2 *dp = d2s + zoff;
+            const float2 *dp = d2s[wave] + zoff;
             n_direct += __popcll(mk);
             if ((mk >> lane) & 1ull) {
                 const KQ q64 = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx,
@@ -1271,18 +1279,14 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
         double accd[TD];
 #pragma unroll
         for (int t = 0; t < TD; ++t)
-            accd[t] = (d2s[t].x == 0.0f && d2s[t].y == 0.0f) ? 0.0 : (double)acc[t];
+            accd[t] = (d2s[wave][t].x == 0.0f && d2s[wave][t].y == 0.0f) ? 0.0
+                                                                         : (double)acc[t];
+        // lane t << SHIFT holds Delta t
         wave_reduce_halving<TD>(accd, lane);
-        red[wave][lane] = accd[0];
-        __syncthreads();
         constexpr int SHIFT = 6 - Log2<TD>::value;
-        if (threadIdx.x < TD) {
-            const int src = threadIdx.x << SHIFT;
-            double v = ((red[0][src] + red[1][src]) + red[2][src]) + red[3][src];
-            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD + threadIdx.x] = v;
-        }
-        // the next unit is visible, and red and d2s are free again
-        __syncthreads();
+        if ((lane & ((1 << SHIFT) - 1)) == 0)
+            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD +
+                   (lane >> SHIFT)] = accd[0];
     }
     if (args.count && lane == 0 && n_direct)
         atomicAdd(args.count, (unsigned long long)n_direct * TD);
