@@ -178,6 +178,28 @@ __device__ __forceinline__ void neumaier(double &s, double &c, double x)
     s = t;
 }
 
+// Neumaier sum of p[0], p[stride], ..., p[(n-1) stride] in that order.  The
+// loads run kAhead elements ahead of the additions, so a sum of chunk
+// partials waits for memory once per kAhead elements, not once per element.
+constexpr int kAhead = 8;
+__device__ __forceinline__ double ordered_sum(const double *p, size_t stride, int n)
+{
+    double s = 0.0, c = 0.0;
+    int k = 0;
+    for (; k + kAhead <= n; k += kAhead) {
+        double v[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            v[u] = p[(size_t)(k + u) * stride];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            neumaier(s, c, v[u]);
+    }
+    for (; k < n; ++k)
+        neumaier(s, c, p[(size_t)k * stride]);
+    return s + c;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -1434,11 +1456,7 @@ __global__ void chi_finish_kernel(const ChiFinishArgs a)
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n_pairs_q)
         return;
-    double s = 0.0, c = 0.0;
-    const double *p = a.part + (size_t)t * a.n_chunks;
-    for (int ch = 0; ch < a.n_chunks; ++ch)
-        neumaier(s, c, p[ch]);
-    a.out[t] = (s + c) * a.inv_n;
+    a.out[t] = ordered_sum(a.part + (size_t)t * a.n_chunks, 1, a.n_chunks) * a.inv_n;
 }
 
 hipError_t launch_chi_finish(const ChiFinishArgs &a, hipStream_t s)
@@ -1528,21 +1546,14 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     __shared__ double shd[4];
     __shared__ int shi[4];
     __shared__ double sh_mom[kMomentSlots];   // C0, c_n M_n
-    if (threadIdx.x == 0) {
-        double s = 0.0, c = 0.0;
-        const double *bp = r.base_part + row * r.n_chunks;
-        for (int ch = 0; ch < r.n_chunks; ++ch)
-            neumaier(s, c, bp[ch]);
-        sh_base = s + c;
-    }
+    if (threadIdx.x == kMomentSlots)
+        sh_base = ordered_sum(r.base_part + row * r.n_chunks, 1, r.n_chunks);
     if (threadIdx.x < kMomentSlots) {
         // fixed-order chunk sum of one moment (positive terms)
-        double s = 0.0, c = 0.0;
-        const double *mp = r.mpart + row * r.n_chunks * kMomentSlots + threadIdx.x;
-        for (int ch = 0; ch < r.n_chunks; ++ch)
-            neumaier(s, c, mp[(size_t)ch * kMomentSlots]);
+        const double m = ordered_sum(r.mpart + row * r.n_chunks * kMomentSlots + threadIdx.x,
+                                     kMomentSlots, r.n_chunks);
         // times binomial(1/2, n) (c_0 = 1: C0 as it is)
-        sh_mom[threadIdx.x] = threadIdx.x == 0 ? (s + c) : kHalfBinomial.c[threadIdx.x] * (s + c);
+        sh_mom[threadIdx.x] = threadIdx.x == 0 ? m : kHalfBinomial.c[threadIdx.x] * m;
     }
     __syncthreads();
     const double base = sh_base;
@@ -1565,11 +1576,10 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
             __syncthreads();
             for (int u = threadIdx.x; u < nbt * kTileSlots; u += kBlock) {
                 const int dt = b0 + u / kTileSlots, n = u % kTileSlots;
-                double s = 0.0, c = 0.0;
-                const double *tp = r.tpart + (row * r.n_chunks * r.n_dtiles + dt) * kTileSlots + n;
-                for (int ch = 0; ch < r.n_chunks; ++ch)
-                    neumaier(s, c, tp[(size_t)ch * r.n_dtiles * kTileSlots]);
-                sh_tm[u / kTileSlots][n] = kHalfBinomial.c[n] * (s + c);
+                const double m =
+                    ordered_sum(r.tpart + (row * r.n_chunks * r.n_dtiles + dt) * kTileSlots + n,
+                                (size_t)r.n_dtiles * kTileSlots, r.n_chunks);
+                sh_tm[u / kTileSlots][n] = kHalfBinomial.c[n] * m;
             }
             for (int u = threadIdx.x; u < nbt; u += kBlock) {
                 // same arithmetic as the sweep's tile range
@@ -1585,9 +1595,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
         }
         const int id_end = min(r.n_delta, (b0 + nbt) * r.td);
         for (int id = b0 * r.td + threadIdx.x; id < id_end; id += kBlock) {
-            double s = 0.0, c = 0.0;
-            for (int ch = 0; ch < r.n_chunks; ++ch)
-                neumaier(s, c, pp[(size_t)ch * r.n_delta_pad + id]);
+            const double sp = ordered_sum(pp + id, r.n_delta_pad, r.n_chunks);
             const double D = r.delta[id];
             // series part: C0 + sum_n c_n M_n (Delta^2 - x0)^n by Horner
             const double x = D * D - x0;
@@ -1595,15 +1603,16 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
             for (int n = kSeriesTerms - 1; n >= 1; --n)
                 ser = fma(ser, x, sh_mom[n]);
             ser = fma(ser, x, sh_mom[0]);
+            double sp_t = 0.0;
             if (r.tpart) {
                 const int u = id / r.td - b0;
                 const double z = D * D - sh_tc[u];
                 double ts = sh_tm[u][kTileSlots - 1];
                 for (int n = kTileSlots - 2; n >= 0; --n)
                     ts = fma(ts, z, sh_tm[u][n]);
-                s += ts;
+                sp_t = ts;
             }
-            const double om = (base - ((s + c) + ser)) + r.n_k * (-2.0 * D * D / V) + qpoison;
+            const double om = (base - ((sp + sp_t) + ser)) + r.n_k * (-2.0 * D * D / V) + qpoison;
             out[id] = om;
             best = nan_min(best, om);
         }
@@ -1824,10 +1833,7 @@ __global__ void grad_finish_kernel(const GradFinishArgs a)
         return;
     const size_t io = (size_t)a.pts[g].out * a.nb + slot;
     const double *pp = a.part + ((size_t)g * a.nb + slot) * a.n_chunks * 5;
-    double s = 0.0, e = 0.0;
-    for (int ch = 0; ch < a.n_chunks; ++ch)
-        neumaier(s, e, pp[(size_t)ch * 5 + c]);
-    double v = s + e;
+    double v = ordered_sum(pp + c, 5, a.n_chunks);
     const double D = a.delta[io];
     const double V = slot ? a.Vs[1] : a.Vs[0];
     switch (c) {
