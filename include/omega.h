@@ -92,8 +92,10 @@ size_t omega_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
 /* Omega grid, Eq. (5), for every point, selected band, Q and Delta
  * (Algorithm 1's two loops, all at once).
  *   pts        host array [n_pts]
- *   delta_dev  device [n_delta] Delta values (any real; Delta >= 0 physical)
- *   q_dev      device [n_q][2] pair momenta Q = (qx, qy), any real values
+ *   delta_dev  device [n_delta] Delta values (any real; Delta >= 0 physical),
+ *              1 <= n_delta <= 2^20
+ *   q_dev      device [n_q][2] pair momenta Q = (qx, qy), any real values,
+ *              1 <= n_q <= 16384 and n_q * n_delta <= 2^30
  *   omega_dev  device output [n_pts][nb][n_q][n_delta], Delta fastest,
  *              nb = number of bands in `bands`; total Omega (not per site). */
 int omega_grid(const omega_model *model, const omega_point *pts, int n_pts,

@@ -26,6 +26,7 @@ constexpr int kMaxL = 16384;
 constexpr long long kMaxK = 1LL << 26;
 constexpr int kMaxDelta = 1 << 20;
 constexpr int kMaxQ = 16384;
+constexpr long long kMaxCells = 1LL << 30;   // n_q * n_delta of one (point, band)
 constexpr int kMaxPoints = 1 << 24;
 constexpr int kMinWorkgroups = 4096;       // per point, below this chunks split finer
 constexpr int kMinLaunchUnits = 24576;     // per point: 8 sweep units per resident wave
@@ -110,6 +111,7 @@ bool points_ok(const omega_point *pts, int n_pts)
 bool sizes_ok(int n_delta, int n_q, int bands, int precision)
 {
     return n_delta > 0 && n_delta <= kMaxDelta && n_q > 0 && n_q <= kMaxQ &&
+           (long long)n_q * n_delta <= kMaxCells &&
            bands >= 1 && bands <= 3 &&
            (precision == OMEGA_FP64 || precision == OMEGA_FP32_COMP);
 }

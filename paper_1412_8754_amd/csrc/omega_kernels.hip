@@ -941,6 +941,11 @@ void sweep_f64_kernel(const SweepArgs args)
     __shared__ double d2s[4][TD + 1];
     __shared__ double uc[4][kUnitConsts];
     __shared__ double2 gt[kGTabN];
+    // per wave: queue of the (k, Q) terms that need the per-Delta loop,
+    // s^2 (floored), |d|, eta^2 and the mirror weight; the loop runs on 64
+    // of them at a time, so that every lane of the wave has a term
+    __shared__ double lq[4][3][2 * 64];   // s^2, |d|, eta^2
+    __shared__ float lqw[4][2 * 64];      // weight
     for (int n = threadIdx.x; n < kGTabN; n += kBlock)
         gt[n] = a0.gtab[n];
     __syncthreads();
@@ -1014,6 +1019,7 @@ void sweep_f64_kernel(const SweepArgs args)
             tm[n] = 0.0;
 
         const TileList tl = tile_list(a, bz, chunk);
+        int pending = 0;   // queued terms of this wave
         // the next entry of the walk is fetched one tile ahead
         int e = 0;
         int nt_tile = 0;
@@ -1065,30 +1071,63 @@ void sweep_f64_kernel(const SweepArgs args)
                     tm[n] += tp;
                 }
             }
-            n_direct += __popcll(__ballot(loop));
+            // queue this tile's loop terms behind the pending ones
+            const unsigned long long lb = __ballot(loop);
+            n_direct += __popcll(lb);
             if (loop) {
-                const double wT = w * cp[kUcT];
-                const double invT = cp[kUcInvT];
                 // R^2 >= 1e-300 keeps the reciprocal square root finite; the
                 // floor is absorbed unless s^2 and Delta^2 eta^2 are both < 1e-284
-                const double s2p = r.s2 + 1e-300;
-                double dcur = dp[0];
+                const int at = pending + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (unsigned)(lb >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((unsigned)lb, 0u));
+                lq[wave][0][at] = r.s2 + 1e-300;
+                lq[wave][1][at] = r.m;
+                lq[wave][2][at] = r.eta2;
+                lqw[wave][at] = (float)w;
+            }
+            pending += __popcll(lb);
+            // run the loop on full waves of queued terms; after the last tile
+            // also on what is left
+            const bool last = e + 1 >= tl.total;
+            while (pending >= 64 || (last && pending > 0)) {
+                // the wave's queue writes above are visible to all its lanes
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int nb = pending < 64 ? pending : 64;
+                if (lane < nb) {
+                    const double s2p = lq[wave][0][lane];
+                    const double m = lq[wave][1][lane];
+                    const double eta2 = lq[wave][2][lane];
+                    const double wq = (double)lqw[wave][lane];
+                    const double wT = wq * cp[kUcT];
+                    const double invT = cp[kUcInvT];
+                    double dcur = dp[0];
 #pragma unroll
-                for (int t = 0; t < TD; ++t) {
-                    const double dnext = dp[t + 1];
-                    const double R = sqrt_1s(fma(dcur, r.eta2, s2p));
-                    const double x = R - r.m;
-                    acc[t] = fma(w, fmax(x, 0.0), acc[t]);
-                    const double ax = fabs(x);
-                    if (ax < cutT) {
-                        // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
-                        double L = log1p_exp_tab(ax * invT, gt);
-                        const double y = R + r.m;
-                        if (y < cutT)
-                            L += log1p_exp_tab(y * invT, gt);
-                        acc[t] = fma(wT, L, acc[t]);
+                    for (int t = 0; t < TD; ++t) {
+                        const double dnext = dp[t + 1];
+                        const double R = sqrt_1s(fma(dcur, eta2, s2p));
+                        const double x = R - m;
+                        acc[t] = fma(wq, fmax(x, 0.0), acc[t]);
+                        const double ax = fabs(x);
+                        if (ax < cutT) {
+                            // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
+                            double L = log1p_exp_tab(ax * invT, gt);
+                            const double y = R + m;
+                            if (y < cutT)
+                                L += log1p_exp_tab(y * invT, gt);
+                            acc[t] = fma(wT, L, acc[t]);
+                        }
+                        dcur = dnext;
                     }
-                    dcur = dnext;
+                }
+                // terms beyond the first 64 move to the front of the queue
+                pending -= nb;
+                if (lane < pending) {
+                    lq[wave][0][lane] = lq[wave][0][64 + lane];
+                    lq[wave][1][lane] = lq[wave][1][64 + lane];
+                    lq[wave][2][lane] = lq[wave][2][64 + lane];
+                    lqw[wave][lane] = lqw[wave][64 + lane];
                 }
             }
         }
@@ -1653,20 +1692,36 @@ __global__ __launch_bounds__(kBlock) void argmin_kernel(const ArgminArgs a)
     const double *g = a.omega + set * (size_t)n;
     __shared__ double shd[4];
     __shared__ int shi[4];
-    double best = __longlong_as_double(0x7ff8000000000000LL);
-    for (int t = threadIdx.x; t < n; t += kBlock)
-        best = nan_min(best, g[t]);
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    // both passes load kAhead values per thread before using them
+    double best = nan;
+    for (int t0 = threadIdx.x; t0 < n; t0 += kBlock * kAhead) {
+        double v[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            v[u] = t0 + u * kBlock < n ? g[t0 + u * kBlock] : nan;
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u)
+            best = nan_min(best, v[u]);
+    }
     best = block_nan_min(best, shd);
     int key = 0x7fffffff;
     if (best == best) {
         const double thr = tie_threshold(best, a.tie_rel);
-        for (int t = threadIdx.x; t < n; t += kBlock) {
-            const double v = g[t];
-            if (v <= thr) {
-                const int iq = t / a.n_delta;
-                const int id = t - iq * a.n_delta;
-                const int k = id * a.n_q + iq;
-                key = k < key ? k : key;
+        for (int t0 = threadIdx.x; t0 < n; t0 += kBlock * kAhead) {
+            double v[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u)
+                v[u] = t0 + u * kBlock < n ? g[t0 + u * kBlock] : nan;
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                if (v[u] <= thr) {
+                    const int t = t0 + u * kBlock;
+                    const int iq = t / a.n_delta;
+                    const int id = t - iq * a.n_delta;
+                    const int k = id * a.n_q + iq;
+                    key = k < key ? k : key;
+                }
             }
         }
     }

@@ -67,6 +67,10 @@ def test_workspace_rejects_bad_sizes():
     assert _ws(pts, bands=4) == 0
     assert _ws(pts, prec=2) == 0
     assert _abi.load().omega_workspace_bytes(None, 1, 8, 3, 3, 0, 0) == 0
+    # n_q * n_delta of one (point, band) is capped at 2^30
+    assert _ws(pts, nd=1 << 20, nq=1024) > 0
+    assert _ws(pts, nd=1 << 20, nq=1025) == 0
+    assert _ws(pts, nd=1 << 17, nq=16384) == 0
 
 
 FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation
