@@ -489,28 +489,41 @@ __device__ __forceinline__ double eig3_band(const Hop3 &h, double c, double sn, 
     return b == 0 ? ev[0] : (b == 1 ? ev[1] : ev[2]);
 }
 
-// E(k) and E(Q - k) of one momentum for output slot `slot` and pair momentum
-// iq.  E(k) comes from the lattice table of either model, and so does
-// E(Q - k) when Q lies on the lattice.  Otherwise E(Q - k) is computed at
-// Q - k, with cos/sin of Q - k by angle subtraction: (A.4) in closed form for
-// the two-band model, by diagonalising for the three-band model.
+// Load of base[idx] with a 32-bit unsigned offset from a wave-uniform base
+// (every table here holds fewer than 2^29 doubles), so that the address is
+// a scalar base plus a 32-bit vector offset rather than 64-bit arithmetic.
+__device__ __forceinline__ double ldg(const double *base, unsigned idx)
+{
+    return *(const double *)((const char *)base + (idx << 3));
+}
+
+// E(k) and E(Q - k) of momentum (i, j) for output slot `slot` and pair
+// momentum iq; rowk = i * Ly.  E(k) comes from the lattice table of either
+// model, and so does E(Q - k) when Q lies on the lattice.  Otherwise E(Q - k)
+// is computed at Q - k, with cos/sin of Q - k by angle subtraction: (A.4) in
+// closed form for the two-band model, by diagonalising for the three-band
+// model.
 template <bool B3>
 __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int iq, int i, int j,
-                                       double eps, double mu_up, double mu_dn, double cqx,
-                                       double sqx, double cqy, double sqy, double cx,
-                                       double sx, double cy, double sy)
+                                       unsigned rowk, double eps, double mu_up, double mu_dn,
+                                       double cqx, double sqx, double cqy, double sqy)
 {
     const int b = a.band3[slot];
-    const double *E = a.etab + (size_t)b * a.Lx * a.Ly;
-    const double Ek = E[(size_t)i * a.Ly + j];
+    const unsigned n = (unsigned)a.Lx * (unsigned)a.Ly;
+    const double *E = a.etab + (size_t)b * n;
+    const double Ek = ldg(E, rowk + (unsigned)j);
+    const double cx = ldg(a.trig, (unsigned)i), sx = ldg(a.trig + a.Lx, (unsigned)i);
+    const double cy = ldg(a.trig + 2 * a.Lx, (unsigned)j);
+    const double sy = ldg(a.trig + 2 * a.Lx + a.Ly, (unsigned)j);
     double Eq;
     const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
     if (mx >= 0 && my >= 0) {
-        int ii = mx - i;
-        ii += ii < 0 ? a.Lx : 0;
-        int jj = my - j;
-        jj += jj < 0 ? a.Ly : 0;
-        Eq = E[(size_t)ii * a.Ly + jj];
+        // ((mx - i) mod Lx) Ly + (my - j) mod Ly, from mx Ly - i Ly
+        const int di = mx - i, dj = my - j;
+        unsigned idx = (unsigned)mx * (unsigned)a.Ly - rowk + (unsigned)dj;
+        idx += di < 0 ? n : 0u;
+        idx += dj < 0 ? (unsigned)a.Ly : 0u;
+        Eq = ldg(E, idx);
     } else {
         const double cpx = fma(cqx, cx, sqx * sx);
         const double spx = fma(sqx, cx, -(cqx * sx));
@@ -793,7 +806,7 @@ void series_kernel(const SweepArgs a, int fp64)
     const int iq = bq - slot * a.n_q;
     const double eps = slot ? a.eps[1] : a.eps[0];
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const double qy = a.q[2 * iq + 1];
     const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
     const PointRec pt = a.pts[g];
@@ -805,10 +818,6 @@ void series_kernel(const SweepArgs a, int fp64)
     const double hw = a.d2[a.n_delta_pad + 1];
     const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
-    const double *cxt = a.trig;
-    const double *sxt = a.trig + a.Lx;
-    const double *cyt = a.trig + 2 * a.Lx;
-    const double *syt = cyt + a.Ly;
     unsigned long long *tl =
         a.tlist + (((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave) * a.lcap * 2;
     int n_listed = 0;
@@ -818,6 +827,7 @@ void series_kernel(const SweepArgs a, int fp64)
         mom[n] = 0.0;
     double bs = 0.0, bc = 0.0;
     const int li = lane >> 3, lj = lane & 7;
+    const unsigned liLy = (unsigned)li * (unsigned)a.Ly;
     for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
         const int ti = tile / kr.TYw;
         const int tj = tile - ti * kr.TYw;
@@ -825,8 +835,9 @@ void series_kernel(const SweepArgs a, int fp64)
         const int j = tj * kTileEdge + lj;
         bool direct = false;
         if (i < kr.ilim && j < kr.jlim) {
-            const KQ r = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx, cqy,
-                                      sqy, cxt[i], sxt[i], cyt[j], syt[j]);
+            const KQ r = kq_setup<B3>(a, slot, iq, i, j,
+                                      (unsigned)(ti * kTileEdge) * (unsigned)a.Ly + liLy, eps,
+                                      mu_up, mu_dn, cqx, sqx, cqy, sqy);
             const double w = mirror_weight(kr, i, j, a.Lx, a.Ly);
             const double A0 = r.as - r.m;
             double base = r.base;
@@ -1004,11 +1015,6 @@ void sweep_f64_kernel(const SweepArgs args)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        const double *cxt = a.trig;
-        const double *sxt = a.trig + a.Lx;
-        const double *cyt = a.trig + 2 * a.Lx;
-        const double *syt = cyt + a.Ly;
-
         double acc[TD];
 #pragma unroll
         for (int t = 0; t < TD; ++t)
@@ -1047,8 +1053,10 @@ void sweep_f64_kernel(const SweepArgs args)
             KQ r;
             double w = 0.0, Rc2 = 0.0;
             if ((mk >> lane) & 1ull) {
-                r = kq_setup<B3>(a, slot, iq, i, j, eps, cp[kUcMuUp], cp[kUcMuDn], cqx, sqx,
-                                 cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
+                r = kq_setup<B3>(a, slot, iq, i, j,
+                                 (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
+                                     (unsigned)li * (unsigned)a.Ly,
+                                 eps, cp[kUcMuUp], cp[kUcMuDn], cqx, sqx, cqy, sqy);
                 w = mirror_weight(kr, i, j, a.Lx, a.Ly);
                 const double up = r.m + cutT, dn = r.m - cutT;
                 const double x_lo = cp[kUcXlo], x_hi = cp[kUcXhi], ht = cp[kUcHt];
@@ -1277,11 +1285,6 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        const double *cxt = a.trig;
-        const double *sxt = a.trig + a.Lx;
-        const double *cyt = a.trig + 2 * a.Lx;
-        const double *syt = cyt + a.Ly;
-
         float acc[TD];
 #pragma unroll
         for (int t = 0; t < TD; ++t)
@@ -1309,8 +1312,10 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
             const float2 *dp = d2s[wave] + zoff;
             n_direct += __popcll(mk);
             if ((mk >> lane) & 1ull) {
-                const KQ q64 = kq_setup<B3>(a, slot, iq, i, j, eps, mu_up, mu_dn, cqx, sqx,
-                                            cqy, sqy, cxt[i], sxt[i], cyt[j], syt[j]);
+                const KQ q64 = kq_setup<B3>(a, slot, iq, i, j,
+                                            (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
+                                                (unsigned)li * (unsigned)a.Ly,
+                                            eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
                 const KQf r = kq_setup_f32(q64, T, invT);
                 const float wf = (float)mirror_weight(kr, i, j, a.Lx, a.Ly);
                 const bool hot0 = r.P0 != 0.0f;
