@@ -498,15 +498,17 @@ __device__ __forceinline__ double ldg(const double *base, unsigned idx)
 }
 
 // E(k) and E(Q - k) of momentum (i, j) for output slot `slot` and pair
-// momentum iq; rowk = i * Ly.  E(k) comes from the lattice table of either
+// momentum iq, whose lattice index (mx, my) (-1 off the lattice) the caller
+// reads once; rowk = i * Ly.  E(k) comes from the lattice table of either
 // model, and so does E(Q - k) when Q lies on the lattice.  Otherwise E(Q - k)
 // is computed at Q - k, with cos/sin of Q - k by angle subtraction: (A.4) in
 // closed form for the two-band model, by diagonalising for the three-band
 // model.
 template <bool B3>
-__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int iq, int i, int j,
-                                       unsigned rowk, double eps, double mu_up, double mu_dn,
-                                       double cqx, double sqx, double cqy, double sqy)
+__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int mx, int my, int i,
+                                       int j, unsigned rowk, double eps, double mu_up,
+                                       double mu_dn, double cqx, double sqx, double cqy,
+                                       double sqy)
 {
     const int b = a.band3[slot];
     const unsigned n = (unsigned)a.Lx * (unsigned)a.Ly;
@@ -516,7 +518,6 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int iq, int
     const double cy = ldg(a.trig + 2 * a.Lx, (unsigned)j);
     const double sy = ldg(a.trig + 2 * a.Lx + a.Ly, (unsigned)j);
     double Eq;
-    const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
     if (mx >= 0 && my >= 0) {
         // ((mx - i) mod Lx) Ly + (my - j) mod Ly, from mx Ly - i Ly
         const int di = mx - i, dj = my - j;
@@ -818,6 +819,8 @@ void series_kernel(const SweepArgs a, int fp64)
     const double hw = a.d2[a.n_delta_pad + 1];
     const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+    const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+    const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
     unsigned long long *tl =
         a.tlist + (((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave) * a.lcap * 2;
     int n_listed = 0;
@@ -835,7 +838,7 @@ void series_kernel(const SweepArgs a, int fp64)
         const int j = tj * kTileEdge + lj;
         bool direct = false;
         if (i < kr.ilim && j < kr.jlim) {
-            const KQ r = kq_setup<B3>(a, slot, iq, i, j,
+            const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
                                       (unsigned)(ti * kTileEdge) * (unsigned)a.Ly + liLy, eps,
                                       mu_up, mu_dn, cqx, sqx, cqy, sqy);
             const double w = mirror_weight(kr, i, j, a.Lx, a.Ly);
@@ -985,6 +988,8 @@ void sweep_f64_kernel(const SweepArgs args)
         const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
         const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
         const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+        const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+        const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
 
         // the tile's Delta^2 (the padding repeats the last value) and range
         const double dl = a.d2[dtile * TD + (lane < TD ? lane : TD - 1)];
@@ -1053,7 +1058,7 @@ void sweep_f64_kernel(const SweepArgs args)
             KQ r;
             double w = 0.0, Rc2 = 0.0;
             if ((mk >> lane) & 1ull) {
-                r = kq_setup<B3>(a, slot, iq, i, j,
+                r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
                                  (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
                                      (unsigned)li * (unsigned)a.Ly,
                                  eps, cp[kUcMuUp], cp[kUcMuDn], cqx, sqx, cqy, sqy);
@@ -1274,6 +1279,8 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
 
         const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
         const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+        const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+        const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
 
         if (lane <= TD) {
             const double v = a.d2[dtile * TD + (lane < TD ? lane : TD - 1)];
@@ -1312,7 +1319,7 @@ __global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args
             const float2 *dp = d2s[wave] + zoff;
             n_direct += __popcll(mk);
             if ((mk >> lane) & 1ull) {
-                const KQ q64 = kq_setup<B3>(a, slot, iq, i, j,
+                const KQ q64 = kq_setup<B3>(a, slot, qmx, qmy, i, j,
                                             (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
                                                 (unsigned)li * (unsigned)a.Ly,
                                             eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
@@ -1432,6 +1439,12 @@ __global__ __launch_bounds__(kBlock) void chi_kernel(const ChiArgs a)
     const int ia = pair / a.nb, ib = pair - (pair / a.nb) * a.nb;
     const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+    // three-band: lattice index of q, read once (-1 off the lattice)
+    int qmx = -1, qmy = -1;
+    if constexpr (B3) {
+        qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+        qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
+    }
     const double invT = a.T > 0.0 ? 1.0 / a.T : 0.0;
     const double mu_up = a.mu + a.h, mu_dn = a.mu - a.h;
     const double *cxt = a.trig, *sxt = a.trig + a.Lx;
@@ -1457,11 +1470,10 @@ __global__ __launch_bounds__(kBlock) void chi_kernel(const ChiArgs a)
             const double *Ea = a.etab + (size_t)a.band3[ia] * n;
             const double *Eb = a.etab + (size_t)a.band3[ib] * n;
             E1 = Ea[k];
-            const int mx = a.qlat[2 * iq], my = a.qlat[2 * iq + 1];
-            if (mx >= 0 && my >= 0) {
-                int ii = i + mx;
+            if (qmx >= 0 && qmy >= 0) {
+                int ii = i + qmx;
                 ii -= ii >= a.Lx ? a.Lx : 0;
-                int jj = j + my;
+                int jj = j + qmy;
                 jj -= jj >= a.Ly ? a.Ly : 0;
                 E2 = Eb[(size_t)ii * a.Ly + jj];
             } else {
