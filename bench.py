@@ -41,7 +41,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # (x2.0) and WRITE_SIZE (x1.0) passes, scaled by the same counters on a plain
 # 256 MiB device copy (profiles/sweep_f64_paper_L1024.md).  Valid for the
 # kernel build those counters were taken on; None for other workloads.
-TRAFFIC_BYTES = {("paper", "fp64"): (36140 * 2 + 29790) * 1024}
+TRAFFIC_BYTES = {}
 
 
 def parse():
@@ -156,6 +156,26 @@ def phase_diagram(args):
                      "om": om}
         print(f"bench: {name} {dt:.3f} s, {evals / dt:.3e} evals/s", file=sys.stderr,
               flush=True)
+        if name == "fp64":
+            # the same call captured once into a HIP graph and replayed
+            del idx, omin, rows
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(s):
+                with torch.cuda.graph(g, stream=s):
+                    g_idx, _, _, _ = api.argmin(W.DEFAULT_MODEL, pts, delta, q, 3, prec,
+                                                keep_grid=False, workspace=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.replay()
+            torch.cuda.synchronize()
+            dtg = time.perf_counter() - t0
+            res["graph"] = {"wall_s": dtg, "evals_per_s": evals / dtg,
+                            "argmin_equal": bool(torch.equal(g_idx.cpu(), res[name]["idx"]))}
+            print(f"bench: fp64 graph replay {dtg:.3f} s, argmin equal "
+                  f"{res['graph']['argmin_equal']}", file=sys.stderr, flush=True)
+            del g, g_idx
         del ws
     same = (res["fp64"]["idx"] == res["fp32c"]["idx"]).all(dim=-1)
     rel = ((res["fp32c"]["om"] - res["fp64"]["om"]).abs() / res["fp64"]["om"].abs()).max().item()
@@ -167,6 +187,7 @@ def phase_diagram(args):
                                   f"(SplitMix64), {n_d} Delta x {n_q} Q x 2 bands",
                       "evals": evals},
            "fp64": {"wall_s": res["fp64"]["wall_s"], "evals_per_s": res["fp64"]["evals_per_s"]},
+           "fp64_graph_replay": res["graph"],
            "fp32c": {"wall_s": res["fp32c"]["wall_s"],
                      "evals_per_s": res["fp32c"]["evals_per_s"]},
            "fp32c_vs_fp64": {"max_rel_omega": rel,
@@ -274,17 +295,17 @@ def differentiation(args):
 
 def main():
     args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
+              "supported (the work shards by independent (point, band, Q) units; see "
+              "the design notes)", file=sys.stderr)
+        return 2
     if args.workload == "phase":
         return phase_diagram(args)
     if args.workload == "diff":
         return differentiation(args)
     if args.calibrate_copy:
         return calibrate_copy(args.calibrate_copy)
-    if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
-              "supported (the work shards by independent (point, band, Q) units; see "
-              "the design notes)", file=sys.stderr)
-        return 2
 
     import numpy as np
     import torch
