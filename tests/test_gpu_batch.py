@@ -69,6 +69,29 @@ def test_many_points_beyond_one_fill_launch():
     np.testing.assert_array_equal(idx.cpu().numpy()[sel], ridx)
 
 
+def test_one_point_per_batch_reuses_the_workspace_queues():
+    """16384 Q x 2 bands = 32768 rows allow one point per batch (the grid's
+    z extent is 65535), so these 5 points run as 5 batches, one after the
+    other, through the same workspace and the same work-queue counters."""
+    rng = np.random.default_rng(11)
+    pts = [(float(rng.uniform(-0.2, 0.2)), float(rng.choice([0.0, 0.004, 0.05])), L, L)
+           for L in (8, 6, 8, 4, 8)]
+    delta = np.array([0.0, 0.15, 0.4])
+    q = rng.uniform(-np.pi, np.pi, size=(16384, 2))
+    q[:64, 1] = 0.0
+    q[:16, 0] = 2 * np.pi * np.arange(16) / 8     # some lattice momenta too
+    say(f"{len(pts)} points x {len(q)} Q, one point per batch")
+    idx, omin, rows, om = api.argmin(M, pts, delta, q, 3)
+    torch.cuda.synchronize()
+    om = om.cpu().numpy()
+    ref = oracle.omega_grid(M, pts, delta, q, 3)
+    N = np.array([p[2] * p[3] for p in pts]).reshape(-1, 1, 1, 1)
+    err = np.abs(om - ref)
+    assert (err <= 1e-12 * np.abs(ref) + 1e-13 * N).all(), np.max(err / np.abs(ref))
+    _, ridx, _, _ = oracle.omega_argmin(M, pts, delta, q, 3)
+    np.testing.assert_array_equal(idx.cpu().numpy(), ridx)
+
+
 def test_batched_gradients_against_oracle():
     pts = mixed_points(200, 7)
     rng = np.random.default_rng(8)
