@@ -29,7 +29,7 @@ constexpr int kMaxQ = 16384;
 constexpr long long kMaxCells = 1LL << 30;   // n_q * n_delta of one (point, band)
 constexpr int kMaxPoints = 1 << 24;
 constexpr int kMinWorkgroups = 4096;       // per point, below this chunks split finer
-constexpr int kMinLaunchUnits = 24576;     // per point: 8 sweep units per resident wave
+constexpr int kMinLaunchUnits = 12288;     // per point: 4 sweep units per resident wave
 constexpr size_t kBatchBytes = 512u << 20; // chunk partials of one batch
 constexpr int kMaxGridZ = 65535;
 constexpr int kGradTilesPerChunk = 64;
