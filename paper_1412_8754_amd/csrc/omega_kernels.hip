@@ -1237,9 +1237,12 @@ __device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
 }
 
 // The FP32-compensated per-Delta sweep; persistent like the FP64 sweep, with
-// the same work queue and units, one unit per wave at a time.
+// the same work queue and units, one unit per wave at a time.  Two-band: 5
+// waves/SIMD (a few spills outside the Delta loop beat the 4 waves its
+// registers would otherwise give); three-band: 4.
 template <int TD, bool B3>
-__global__ __launch_bounds__(kBlock) void sweep_f32c_kernel(const SweepArgs args)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B3 ? 4 : 5)))
+void sweep_f32c_kernel(const SweepArgs args)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
