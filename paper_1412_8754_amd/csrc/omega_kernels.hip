@@ -741,11 +741,15 @@ enum {
 
 // Work queues of the persistent sweeps: kQueues 64-bit counters in the
 // workspace, zeroed by fill_points_kernel before every batch.  Units are
-// (chunk, Delta tile, row), numbered chunk fastest, then Delta tile; queue q
-// hands out the units u = q, q + nq, q + 2 nq, ... and is served by the
-// workgroups with blockIdx.x = q mod nq, nq = kQueues (1 for a grid of
-// fewer workgroups), so every unit has a taker whatever the placement of
-// the workgroups.  take_unit returns the next unit of queue q as {chunk,
+// (chunk, Delta tile, row).  The groups g = (row, chunk) are dealt out to
+// the queues, g = q mod nq going to queue q (nq = kQueues, 1 for a grid of
+// fewer workgroups), and a queue hands out the Delta tiles of one group
+// one after the other: the waves that take them run on one XCD at about the
+// same time and share that chunk's tile list and band-table entries in its
+// L2.  Queue q is served by the workgroups with blockIdx.x = q mod nq, so
+// every unit has a taker whatever the placement of the workgroups.  The
+// chunk index is rotated by the row, so that each queue sees chunks from
+// the whole zone.  take_unit returns the next unit of queue q as {chunk,
 // Delta tile, row}, with row -1 once the queue is empty; a wave stops at the
 // first -1, so every wave ends.
 __device__ __forceinline__ int sweep_queues()
@@ -756,18 +760,15 @@ __device__ __forceinline__ int sweep_queues()
 __device__ __forceinline__ int3 take_unit(const SweepArgs &a, int q, int nq)
 {
     const unsigned long long k = atomicAdd(a.queue + (size_t)q * kQueueStride, 1ull);
-    const unsigned long long u = (unsigned long long)q + (unsigned long long)nq * k;
-    const unsigned long long per_row = (unsigned long long)a.n_chunks * a.n_dtiles;
-    if (u >= per_row * (unsigned long long)a.n_rows)
+    const unsigned long long nd = (unsigned long long)a.n_dtiles;
+    const unsigned long long nc = (unsigned long long)a.n_chunks;
+    const unsigned long long m = k / nd;
+    const unsigned long long g = (unsigned long long)q + (unsigned long long)nq * m;
+    if (g >= nc * (unsigned long long)a.n_rows)
         return make_int3(0, 0, -1);
-    const unsigned long long row = u / per_row;
-    const unsigned long long rest = u - row * per_row;
-    const unsigned long long dtile = rest / (unsigned long long)a.n_chunks;
-    // the chunk index rotated by Delta tile and row (a bijection for each of
-    // them), so that every queue sees chunks from the whole zone
-    const unsigned long long chunk =
-        (rest - dtile * (unsigned long long)a.n_chunks + dtile + row) %
-        (unsigned long long)a.n_chunks;
+    const unsigned long long dtile = k - m * nd;
+    const unsigned long long row = g / nc;
+    const unsigned long long chunk = (g - row * nc + row) % nc;
     return make_int3((int)chunk, (int)dtile, (int)row);
 }
 
