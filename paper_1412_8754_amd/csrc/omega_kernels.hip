@@ -631,17 +631,6 @@ __device__ __forceinline__ bool series_term(const KQ &r, double R02, double hw, 
     return (r.as - r.m) >= cutT && hw * r.eta2 <= kSeriesRho * R02;
 }
 
-// Adds a workgroup's count of directly evaluated (k, Delta) terms (optional
-// instrumentation for the benchmark; integer sums are order independent).
-__device__ __forceinline__ void count_direct(unsigned long long *count, int n)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        n += __shfl_xor(n, off, 64);
-    if ((threadIdx.x & 63) == 0 && n)
-        atomicAdd(count, (unsigned long long)n);
-}
-
 // Momentum range of one workgroup.  Both models have E(-kx, ky) =
 // E(kx, -ky) = E(kx, ky), and eta^2 is even in each component, so with
 // qy == 0 the term at ky equals the term at -ky and only ky indices 0..Ly/2
@@ -723,15 +712,6 @@ __device__ __forceinline__ void listed_tile(const TileList &t, int e, int &tile,
 // made opaque once per unit of a persistent kernel, reloads them with scalar
 // loads instead of holding them in registers across the whole unit.
 typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
-
-// A wave-uniform double copied into scalar registers.
-__device__ __forceinline__ double wave_uniform(double v)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
 
 // Per-unit constants of the FP64 sweep, in LDS: the tile's Delta^2 range
 // [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T and the cut 36 T.
