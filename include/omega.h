@@ -34,8 +34,10 @@
  *     enqueued; an invalid call returns a negative OMEGA_E_* code and enqueues
  *     nothing.  A HIP launch failure returns OMEGA_E_HIP.  Device arrays are
  *     not validated: NaN in delta_dev or q_dev propagates into Omega.
- *   - Determinism: for fixed inputs and workspace the results are bitwise
- *     reproducible (fixed-order reductions, no atomics).
+ *   - Determinism: for fixed inputs the results are bitwise reproducible.
+ *     Every sum runs in a fixed order; the only atomics are the integer
+ *     counters (in the workspace) from which the sweep's waves take work
+ *     units, and a unit's result does not depend on which wave computes it.
  */
 #ifndef OMEGA_H
 #define OMEGA_H
