@@ -133,7 +133,7 @@ Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
     r.TX = (Lx + kTileEdge - 1) / kTileEdge;
     r.TY = (Ly + kTileEdge - 1) / kTileEdge;
     r.n_tiles = r.TX * r.TY;
-    int tpw = 256;
+    int tpw = kMaxChunkTiles;
     for (;;) {
         const long long units = (long long)((r.n_tiles + tpw - 1) / tpw) * other_blocks;
         if (!((tpw > 4 && units < kMinWorkgroups) || (tpw > 64 && units < kMinLaunchUnits)))
@@ -231,7 +231,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         const size_t per_point =
             sizeof(double) * rows * (p.n_delta_pad + 1 + kMomentSlots +
                                      (size_t)p.n_dtiles * kTileSlots) +
-            sizeof(unsigned long long) * rows * 4 * lcap * 2 + sizeof(int) * rows * 4;
+            sizeof(unsigned long long) * rows * 4 * lcap * 2 + sizeof(int) * rows;
         const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
         p.tiles.push_back(t);
         p.batch.push_back(G);
@@ -241,7 +241,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         base = std::max(base, sizeof(double) * rows * G);
         mom = std::max(mom, sizeof(double) * rows * kMomentSlots * G);
         tlist = std::max(tlist, sizeof(unsigned long long) * rows * 4 * lcap * 2 * G);
-        tcnt = std::max(tcnt, sizeof(int) * rows * 4 * G);
+        tcnt = std::max(tcnt, sizeof(int) * rows * G);
         tpart = std::max(tpart, sizeof(double) * rows * p.n_dtiles * kTileSlots * G);
     }
     p.off_d2 = 0;
@@ -471,6 +471,8 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         a.n_tiles = t.n_tiles;
         a.n_chunks = t.n_chunks;
         a.lcap = list_cap(t);
+        if (a.lcap > kMaxWaveList)   // the series pass stages a wave's list in LDS
+            return OMEGA_E_INVAL;
         r.n_k = (double)g.Lx * g.Ly;
         r.n_chunks = t.n_chunks;
         const int n = (int)g.idx.size();

@@ -122,6 +122,9 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kQueues = 8;
 constexpr int kQueueStride = 32;   // unsigned long long
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
+constexpr int kMaxChunkTiles = 256;   // k tiles of one sweep chunk, at most
+// entries of one wave's list in the series pass (it visits every 4th tile)
+constexpr int kMaxWaveList = kMaxChunkTiles / 4;
 
 // Per-point record of a batch, written into the workspace by fill_points.
 struct PointRec {
@@ -166,10 +169,10 @@ struct SweepArgs {
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments
-    unsigned long long *tlist;   // [G*nbq][n_chunks][4][lcap][2] (tile, lane mask) of
-                                 // the tiles with lanes evaluated per Delta, listed
-                                 // by the series pass per wave
-    int *tcnt;           // [G*nbq][n_chunks][4] list lengths
+    unsigned long long *tlist;   // [G*nbq][n_chunks][4 lcap][2] ((ti << 32) | tj, lane
+                                 // mask) of the tiles with lanes evaluated per Delta,
+                                 // listed by the series pass, first entries used
+    int *tcnt;           // [G*nbq][n_chunks] list lengths
     double *tpart;       // FP64: [G*nbq][n_chunks][n_dtiles][kTileSlots] tile-series moments
     int n_dtiles;
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)

@@ -668,43 +668,35 @@ __device__ __forceinline__ double mirror_weight(const KRange &k, int i, int j, i
     return wx * wy;
 }
 
-// The listed tiles of one (batch point, band, Q) and chunk: the four wave
-// lists of the series pass, concatenated.  Entries are (tile, lane mask).
-// The lists are written by an earlier kernel and only read here, so they are
-// read through the constant address space (scalar loads of wave-uniform
-// entries).
+// The listed tiles of one (batch point, band, Q) and chunk, as the series
+// pass wrote them: the four wave lists one behind the other, each entry the
+// tile's position (ti << 32) | tj and its lane mask.  The lists are written
+// by an earlier kernel and only read here, so they are read through the
+// constant address space (scalar loads of wave-uniform entries).
 typedef const __attribute__((address_space(4))) unsigned long long *ConstU64Ptr;
 
 struct TileList {
     ConstU64Ptr base;
-    int lcap;
-    int c0, c1, c2, total;   // c0, c0 + c1, c0 + c1 + c2, all four
+    int total;
 };
 
 __device__ __forceinline__ TileList tile_list(const SweepArgs &a, int bz, int chunk)
 {
     TileList t;
     const size_t row = (size_t)bz * a.n_chunks + chunk;
-    const __attribute__((address_space(4))) int *cnt =
-        (const __attribute__((address_space(4))) int *)(a.tcnt + row * 4);
     t.base = (ConstU64Ptr)(a.tlist + row * 4 * a.lcap * 2);
-    t.lcap = a.lcap;
-    t.c0 = cnt[0];
-    t.c1 = t.c0 + cnt[1];
-    t.c2 = t.c1 + cnt[2];
-    t.total = t.c2 + cnt[3];
+    t.total = *(const __attribute__((address_space(4))) int *)(a.tcnt + row);
     return t;
 }
 
-// Entry e (wave-uniform) of the concatenated lists: (tile, lane mask).
-__device__ __forceinline__ void listed_tile(const TileList &t, int e, int &tile,
+// Entry e (wave-uniform) of the list: tile (ti, tj) and lane mask.
+__device__ __forceinline__ void listed_tile(const TileList &t, int e, int &ti, int &tj,
                                             unsigned long long &mask)
 {
-    const int seg = (e >= t.c0) + (e >= t.c1) + (e >= t.c2);
-    const int start = seg == 0 ? 0 : (seg == 1 ? t.c0 : (seg == 2 ? t.c1 : t.c2));
-    const size_t k = 2 * ((size_t)seg * t.lcap + (e - start));
-    tile = (int)t.base[k];
-    mask = t.base[k + 1];
+    const unsigned long long pos = t.base[2 * e];
+    ti = (int)(pos >> 32);
+    tj = (int)(unsigned)pos;
+    mask = t.base[2 * e + 1];
 }
 
 // The argument block of a kernel whose only parameter is a SweepArgs: the
@@ -802,8 +794,10 @@ void series_kernel(const SweepArgs a, int fp64)
     const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
     const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
     const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
-    unsigned long long *tl =
-        a.tlist + (((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave) * a.lcap * 2;
+    // the wave's list, staged here and written out behind the lists of the
+    // lower waves once all four are known
+    __shared__ unsigned long long lst[4][2 * kMaxWaveList];
+    __shared__ int lcnt[4];
     int n_listed = 0;
     double mom[kMomentSlots];
 #pragma unroll
@@ -812,9 +806,10 @@ void series_kernel(const SweepArgs a, int fp64)
     double bs = 0.0, bc = 0.0;
     const int li = lane >> 3, lj = lane & 7;
     const unsigned liLy = (unsigned)li * (unsigned)a.Ly;
+    // tile = ti TYw + tj, advanced by 4 without a division per tile
+    int ti = (kr.begin + wave) / kr.TYw;
+    int tj = kr.begin + wave - ti * kr.TYw;
     for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
-        const int ti = tile / kr.TYw;
-        const int tj = tile - ti * kr.TYw;
         const int i = ti * kTileEdge + li;
         const int j = tj * kTileEdge + lj;
         bool direct = false;
@@ -864,14 +859,20 @@ void series_kernel(const SweepArgs a, int fp64)
         const unsigned long long ballot = __ballot(direct);
         if (ballot != 0ull) {
             if (lane == 0) {
-                tl[2 * n_listed] = (unsigned long long)tile;
-                tl[2 * n_listed + 1] = ballot;
+                lst[wave][2 * n_listed] =
+                    ((unsigned long long)(unsigned)ti << 32) | (unsigned)tj;
+                lst[wave][2 * n_listed + 1] = ballot;
             }
             ++n_listed;
         }
+        tj += 4;
+        while (tj >= kr.TYw) {
+            tj -= kr.TYw;
+            ++ti;
+        }
     }
     if (lane == 0)
-        a.tcnt[((size_t)blockIdx.y * a.n_chunks + chunk) * 4 + wave] = n_listed;
+        lcnt[wave] = n_listed;
     __shared__ double red[4][64];
     __shared__ double bred[4];
     const double bv = wave_sum(bs + bc);
@@ -880,6 +881,16 @@ void series_kernel(const SweepArgs a, int fp64)
     wave_reduce_halving<kMomentSlots>(mom, lane);
     red[wave][lane] = mom[0];
     __syncthreads();
+    {
+        const size_t row = (size_t)blockIdx.y * a.n_chunks + chunk;
+        const int pre = (wave > 0 ? lcnt[0] : 0) + (wave > 1 ? lcnt[1] : 0) +
+                        (wave > 2 ? lcnt[2] : 0);
+        unsigned long long *tl = a.tlist + row * 4 * a.lcap * 2 + 2 * (size_t)pre;
+        for (int x = lane; x < 2 * n_listed; x += 64)
+            tl[x] = lst[wave][x];
+        if (threadIdx.x == 0)
+            a.tcnt[row] = ((lcnt[0] + lcnt[1]) + lcnt[2]) + lcnt[3];
+    }
     constexpr int SHIFT = 6 - Log2<kMomentSlots>::value;
     if (threadIdx.x < kMomentSlots) {
         const int src = threadIdx.x << SHIFT;
@@ -945,7 +956,6 @@ void sweep_f64_kernel(const SweepArgs args)
         gt[n] = a0.gtab[n];
     __syncthreads();
     int n_direct = 0;
-    const int li = lane >> 3, lj = lane & 7;
     const int nq = sweep_queues();
     const int q = (int)(blockIdx.x % (unsigned)nq);
     for (;;) {
@@ -969,8 +979,11 @@ void sweep_f64_kernel(const SweepArgs args)
         const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
         const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
         const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
-        const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
-        const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
+        int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+        int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
+        // held in scalar registers for the unit, so that the tile walk does
+        // not load them again ahead of the E(Q - k) read that needs them
+        asm volatile("" : "+s"(qmx), "+s"(qmy));
 
         // the tile's Delta^2 (the padding repeats the last value) and range
         const double dl = a.d2[dtile * TD + (lane < TD ? lane : TD - 1)];
@@ -1014,19 +1027,20 @@ void sweep_f64_kernel(const SweepArgs args)
         int pending = 0;   // queued terms of this wave
         // the next entry of the walk is fetched one tile ahead
         int e = 0;
-        int nt_tile = 0;
+        int nt_ti = 0, nt_tj = 0;
         unsigned long long nt_mask = 0ull;
         if (e < tl.total)
-            listed_tile(tl, e, nt_tile, nt_mask);
+            listed_tile(tl, e, nt_ti, nt_tj, nt_mask);
         for (; e < tl.total; ++e) {
-            const int tile = nt_tile;
+            const int ti = nt_ti, tj = nt_tj;
             const unsigned long long mk = nt_mask;
             if (e + 1 < tl.total)
-                listed_tile(tl, e + 1, nt_tile, nt_mask);
-            const int ti = tile / kr.TYw;
-            const int tj = tile - ti * kr.TYw;
-            const int i = ti * kTileEdge + li;
-            const int j = tj * kTileEdge + lj;
+                listed_tile(tl, e + 1, nt_ti, nt_tj, nt_mask);
+            // the lane's place in the tile, from its lane id (cheaper than
+            // keeping it in a register across the unit)
+            const int ln = (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+            const int i = ti * kTileEdge + (ln >> 3);
+            const int j = tj * kTileEdge + (ln & 7);
             // an opaque zero offset keeps the Delta^2 and unit-constant reads
             // in LDS, read per tile, instead of hoisting them out of the loop
             // into (scarce) registers
@@ -1040,8 +1054,7 @@ void sweep_f64_kernel(const SweepArgs args)
             double w = 0.0, Rc2 = 0.0;
             if ((mk >> lane) & 1ull) {
                 r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
-                                 (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
-                                     (unsigned)li * (unsigned)a.Ly,
+                                 (unsigned)i * (unsigned)a.Ly,
                                  eps, cp[kUcMuUp], cp[kUcMuDn], cqx, sqx, cqy, sqy);
                 w = mirror_weight(kr, i, j, a.Lx, a.Ly);
                 const double up = r.m + cutT, dn = r.m - cutT;
@@ -1285,17 +1298,15 @@ void sweep_f32c_kernel(const SweepArgs args)
         const TileList tl = tile_list(a, bz, chunk);
         // the next entry of the walk is fetched one tile ahead
         int e = 0;
-        int nt_tile = 0;
+        int nt_ti = 0, nt_tj = 0;
         unsigned long long nt_mask = 0ull;
         if (e < tl.total)
-            listed_tile(tl, e, nt_tile, nt_mask);
+            listed_tile(tl, e, nt_ti, nt_tj, nt_mask);
         for (; e < tl.total; ++e) {
-            const int tile = nt_tile;
+            const int ti = nt_ti, tj = nt_tj;
             const unsigned long long mk = nt_mask;
             if (e + 1 < tl.total)
-                listed_tile(tl, e + 1, nt_tile, nt_mask);
-            const int ti = tile / kr.TYw;
-            const int tj = tile - ti * kr.TYw;
+                listed_tile(tl, e + 1, nt_ti, nt_tj, nt_mask);
             const int i = ti * kTileEdge + li;
             const int j = tj * kTileEdge + lj;
             int zoff = 0;
