@@ -144,7 +144,10 @@ Tiles sweep_tiles(int Lx, int Ly, long long other_blocks)
     return r;
 }
 
-// Per-wave capacity of the series pass's tile lists.
+// Per-wave capacity of the series pass's tile lists.  sweep_tiles makes a
+// chunk at most kMaxChunkTiles tiles, so this is at most kMaxWaveList, the
+// entries the series pass stages per wave in LDS.
+static_assert(4 * kMaxWaveList >= kMaxChunkTiles, "series-pass list staging too small");
 int list_cap(const Tiles &t)
 {
     const int span = (t.n_tiles + t.n_chunks - 1) / t.n_chunks;
@@ -471,8 +474,6 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         a.n_tiles = t.n_tiles;
         a.n_chunks = t.n_chunks;
         a.lcap = list_cap(t);
-        if (a.lcap > kMaxWaveList)   // the series pass stages a wave's list in LDS
-            return OMEGA_E_INVAL;
         r.n_k = (double)g.Lx * g.Ly;
         r.n_chunks = t.n_chunks;
         const int n = (int)g.idx.size();
