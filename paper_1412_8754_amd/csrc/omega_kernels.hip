@@ -632,11 +632,16 @@ __device__ __forceinline__ bool series_term(const KQ &r, double R02, double hw, 
 // Momentum range of one workgroup.  Both models have E(-kx, ky) =
 // E(kx, -ky) = E(kx, ky), and eta^2 is even in each component, so with
 // qy == 0 the term at ky equals the term at -ky and only ky indices 0..Ly/2
-// are visited; likewise kx with qx == 0 (Q = 0: a quarter of the zone).  The
-// tiles of the layout are spread evenly over the same n_chunks workgroups.
+// are visited; likewise kx with qx == 0 (Q = 0: a quarter of the zone).  On a
+// square lattice both models are also symmetric under kx <-> ky (it swaps
+// the two orbitals of App. A, and d_xz with d_yz in App. B), and so is
+// eta^2; with Q = 0, E(Q - k) = E(k) keeps the term symmetric too, so only
+// the triangle j <= i of that quarter is visited (an eighth of the zone).
+// The tiles of the layout, the rectangle TXw x TYw or the triangle tj <= ti,
+// row after row, are spread evenly over the same n_chunks workgroups.
 struct KRange {
-    bool fx, fy;
-    int TYw;        // tiles along ky in this layout
+    bool fx, fy, fd;
+    int TYw;        // tiles along ky in this layout (rectangle)
     int ilim, jlim; // kx / ky index bounds
     int begin, end; // tile range of this workgroup
 };
@@ -646,24 +651,56 @@ __device__ __forceinline__ KRange k_range(const SweepArgs &a, double qx, double 
     KRange k;
     k.fx = (qx == 0.0);
     k.fy = (qy == 0.0);
+    k.fd = k.fx && k.fy && a.Lx == a.Ly;
     k.ilim = k.fx ? a.Lx / 2 + 1 : a.Lx;
     k.jlim = k.fy ? a.Ly / 2 + 1 : a.Ly;
     const int TXw = (k.ilim + kTileEdge - 1) / kTileEdge;
     k.TYw = (k.jlim + kTileEdge - 1) / kTileEdge;
-    const int nt = TXw * k.TYw;
+    const int nt = k.fd ? TXw * (TXw + 1) / 2 : TXw * k.TYw;
     const int span = (nt + a.n_chunks - 1) / a.n_chunks;
     k.begin = chunk * span;
     k.end = min(k.begin + span, nt);
     return k;
 }
 
+// Tiles in row ti of the layout.
+__device__ __forceinline__ int tile_row_len(const KRange &k, int ti)
+{
+    return k.fd ? ti + 1 : k.TYw;
+}
+
+// Position (ti, tj) of tile t of the layout (wave-uniform).
+__device__ __forceinline__ void tile_pos(const KRange &k, int t, int &ti, int &tj)
+{
+    if (!k.fd) {
+        ti = t / k.TYw;
+        tj = t - ti * k.TYw;
+        return;
+    }
+    // row ti holds tiles ti (ti + 1) / 2 .. ti (ti + 1) / 2 + ti
+    int r = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (r > 0 && r * (r + 1) / 2 > t)
+        --r;
+    while ((r + 1) * (r + 2) / 2 <= t)
+        ++r;
+    ti = r;
+    tj = t - r * (r + 1) / 2;
+}
+
+// Whether momentum (i, j) belongs to the layout.
+__device__ __forceinline__ bool in_layout(const KRange &k, int i, int j)
+{
+    return i < k.ilim && j < k.jlim && (!k.fd || j <= i);
+}
+
 // weight of momentum (i, j): 2 per folded axis whose mirror index L - i is
-// a different momentum
+// a different momentum, and 2 more off the diagonal when kx <-> ky is folded
 __device__ __forceinline__ double mirror_weight(const KRange &k, int i, int j, int Lx, int Ly)
 {
     const double wx = (k.fx && i != 0 && 2 * i != Lx) ? 2.0 : 1.0;
     const double wy = (k.fy && j != 0 && 2 * j != Ly) ? 2.0 : 1.0;
-    return wx * wy;
+    const double wd = (k.fd && i != j) ? 2.0 : 1.0;
+    return wx * wy * wd;
 }
 
 // The listed tiles of one (batch point, band, Q) and chunk, as the series
@@ -804,14 +841,14 @@ void series_kernel(const SweepArgs a, int fp64)
     double bs = 0.0, bc = 0.0;
     const int li = lane >> 3, lj = lane & 7;
     const unsigned liLy = (unsigned)li * (unsigned)a.Ly;
-    // tile = ti TYw + tj, advanced by 4 without a division per tile
-    int ti = (kr.begin + wave) / kr.TYw;
-    int tj = kr.begin + wave - ti * kr.TYw;
+    // tile (ti, tj), advanced by 4 without a division per tile
+    int ti = 0, tj = 0;
+    tile_pos(kr, kr.begin + wave, ti, tj);
     for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
         const int i = ti * kTileEdge + li;
         const int j = tj * kTileEdge + lj;
         bool direct = false;
-        if (i < kr.ilim && j < kr.jlim) {
+        if (in_layout(kr, i, j)) {
             const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
                                       (unsigned)(ti * kTileEdge) * (unsigned)a.Ly + liLy, eps,
                                       mu_up, mu_dn, cqx, sqx, cqy, sqy);
@@ -864,8 +901,8 @@ void series_kernel(const SweepArgs a, int fp64)
             ++n_listed;
         }
         tj += 4;
-        while (tj >= kr.TYw) {
-            tj -= kr.TYw;
+        while (tj >= tile_row_len(kr, ti)) {
+            tj -= tile_row_len(kr, ti);
             ++ti;
         }
     }

@@ -126,12 +126,14 @@ def test_random_ragged_cases(seed):
     np.testing.assert_array_equal(rows, rrows)
 
 
-@pytest.mark.parametrize("Lx,Ly", [(17, 9), (24, 30), (13, 2), (40, 3), (2, 15), (8, 8)])
+@pytest.mark.parametrize("Lx,Ly", [(17, 9), (24, 30), (13, 2), (40, 3), (2, 15), (8, 8),
+                                   (2, 2), (3, 3), (17, 17), (66, 66), (131, 131)])
 def test_mirror_folded_rows_match_oracle(Lx, Ly):
     # A zero component of Q folds that momentum axis (odd and even sides, the
     # self-mirrored indices 0 and L/2): Q on the kx axis folds ky, Q on the ky
-    # axis folds kx, Q = 0 folds both; a Q off the axes in the same launch
-    # takes the full sum.
+    # axis folds kx, Q = 0 folds both, and on a square lattice Q = 0 also
+    # folds kx <-> ky (the triangle j <= i, diagonal tiles cut in half); a Q
+    # off the axes in the same launch takes the full sum.
     pts = [(0.07, 0.004, Lx, Ly), (-0.12, 0.0, Lx, Ly)]
     delta = np.linspace(0.0, 0.6, 35)
     q = np.array([[0.0, 0.0], [0.3, 0.0], [-0.7, 0.0], [2 * np.pi * 3 / Lx, 0.0], [0.2, 0.1],

@@ -66,8 +66,11 @@ def test_band_table_matches_eigvalsh(L):
 
 def test_three_band_grid_lattice_and_off_lattice_q():
     # Q = (2 pi/24, 0) lies on the 24 x 20 lattice but not on 16 x 16 or
-    # 33 x 17; (0.1, 0.05) lies on none: both E(Q - k) paths run.
-    pts = [(0.01, 0.0005, 24, 20), (-0.02, 0.0, 16, 16), (0.005, 0.01, 33, 17)]
+    # 33 x 17; (0.1, 0.05) lies on none: both E(Q - k) paths run.  Q = 0 on
+    # the square lattices (16 x 16, 37 x 37) sums the triangle j <= i of a
+    # quarter of the zone.
+    pts = [(0.01, 0.0005, 24, 20), (-0.02, 0.0, 16, 16), (0.005, 0.01, 33, 17),
+           (0.0, 0.003, 37, 37)]
     delta = np.linspace(0.0, 0.1, 40)
     q = np.array([[0.0, 0.0], [2 * np.pi / 24, 0.0], [0.1, 0.05],
                   [2 * np.pi * 3 / 16, 2 * np.pi * 2 / 16], [2 * np.pi / 24, 2 * np.pi / 20]])
