@@ -19,6 +19,7 @@
 // the one summed; half of it is reached through the mirror.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <type_traits>
 
 #include "omega_internal.h"
 
@@ -663,10 +664,11 @@ __device__ __forceinline__ KRange k_range(const SweepArgs &a, double qx, double 
     return k;
 }
 
-// Tiles in row ti of the layout.
+// Tiles in row ti of the layout (FD: the triangle).
+template <bool FD>
 __device__ __forceinline__ int tile_row_len(const KRange &k, int ti)
 {
-    return k.fd ? ti + 1 : k.TYw;
+    return FD ? ti + 1 : k.TYw;
 }
 
 // Position (ti, tj) of tile t of the layout (wave-uniform).
@@ -687,14 +689,27 @@ __device__ __forceinline__ void tile_pos(const KRange &k, int t, int &ti, int &t
     tj = t - r * (r + 1) / 2;
 }
 
-// Whether momentum (i, j) belongs to the layout.
+// Whether momentum (i, j) belongs to the layout (FD: the triangle).
+template <bool FD>
 __device__ __forceinline__ bool in_layout(const KRange &k, int i, int j)
 {
-    return i < k.ilim && j < k.jlim && (!k.fd || j <= i);
+    return i < k.ilim && j < k.jlim && (!FD || j <= i);
 }
 
 // weight of momentum (i, j): 2 per folded axis whose mirror index L - i is
 // a different momentum, and 2 more off the diagonal when kx <-> ky is folded
+// (FD, known at compile time, or k.fd)
+template <bool FD>
+__device__ __forceinline__ double mirror_weight_t(const KRange &k, int i, int j, int Lx, int Ly)
+{
+    const double wx = (k.fx && i != 0 && 2 * i != Lx) ? 2.0 : 1.0;
+    const double wy = (k.fy && j != 0 && 2 * j != Ly) ? 2.0 : 1.0;
+    if constexpr (FD)
+        return (i != j ? 2.0 : 1.0) * (wx * wy);
+    else
+        return wx * wy;
+}
+
 __device__ __forceinline__ double mirror_weight(const KRange &k, int i, int j, int Lx, int Ly)
 {
     const double wx = (k.fx && i != 0 && 2 * i != Lx) ? 2.0 : 1.0;
@@ -841,71 +856,80 @@ void series_kernel(const SweepArgs a, int fp64)
     double bs = 0.0, bc = 0.0;
     const int li = lane >> 3, lj = lane & 7;
     const unsigned liLy = (unsigned)li * (unsigned)a.Ly;
-    // tile (ti, tj), advanced by 4 without a division per tile
-    int ti = 0, tj = 0;
-    tile_pos(kr, kr.begin + wave, ti, tj);
-    for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
-        const int i = ti * kTileEdge + li;
-        const int j = tj * kTileEdge + lj;
-        bool direct = false;
-        if (in_layout(kr, i, j)) {
-            const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
-                                      (unsigned)(ti * kTileEdge) * (unsigned)a.Ly + liLy, eps,
-                                      mu_up, mu_dn, cqx, sqx, cqy, sqy);
-            const double w = mirror_weight(kr, i, j, a.Lx, a.Ly);
-            const double A0 = r.as - r.m;
-            double base = r.base;
-            if (!fp64) {
-                double P0 = fmax(A0, 0.0);
-                if (fabs(A0) < cutT)
-                    P0 = fma(T, thermal_log(fabs(A0), r.as + r.m, invT, cutT), P0);
-                base -= P0;
-            }
-            neumaier(bs, bc, w * base);
-            const double R02 = fma(x0, r.eta2, r.s2);
-            if (series_term(r, R02, hw, cutT)) {
-                const double R0 = sqrt_rn(R02);
-                // R0 - |s| = x0 eta^2 / (R0 + |s|) without cancellation
-                const double c0 = fp64 ? R0 - r.m
-                                       : (R02 > 0.0 ? x0 * r.eta2 * rcp_nr(R0 + r.as) : 0.0);
-                mom[0] = fma(w, c0, mom[0]);
-                // R0 = 0 only with s = 0 and eta^2 x0 = 0: then the powers vanish
-                const double ratio = R02 > 0.0 ? r.eta2 * rcp_nr(R02) : 0.0;
-                // terms this wave needs: the smallest level that covers the
-                // ratio of every series lane (the active lanes here)
-                const double rho = hw * ratio;
-                int nt = kSeriesTerms;
-#pragma unroll
-                for (int k = kSeriesLevels - 2; k >= 0; --k)
-                    if (__ballot(rho > kLevelRho.v[k]) == 0ull)
-                        nt = kSeriesLevel[k];
-                double t = w * R0;
-#pragma unroll
-                for (int n = 1; n <= kSeriesTerms; ++n) {
-                    if (is_series_level(n - 1) && n > nt)
-                        break;
-                    t *= ratio;
-                    mom[n] += t;
+    // the walk, compiled once per layout: the rectangle, and the triangle
+    // of Q = 0 on a square lattice
+    auto walk = [&](auto fd_tag) __attribute__((always_inline)) {
+        constexpr bool FD = decltype(fd_tag)::value;
+        // tile (ti, tj), advanced by 4 without a division per tile
+        int ti = 0, tj = 0;
+        tile_pos(kr, kr.begin + wave, ti, tj);
+        for (int tile = kr.begin + wave; tile < kr.end; tile += 4) {
+            const int i = ti * kTileEdge + li;
+            const int j = tj * kTileEdge + lj;
+            bool direct = false;
+            if (in_layout<FD>(kr, i, j)) {
+                const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
+                                          (unsigned)(ti * kTileEdge) * (unsigned)a.Ly + liLy, eps,
+                                          mu_up, mu_dn, cqx, sqx, cqy, sqy);
+                const double w = mirror_weight_t<FD>(kr, i, j, a.Lx, a.Ly);
+                const double A0 = r.as - r.m;
+                double base = r.base;
+                if (!fp64) {
+                    double P0 = fmax(A0, 0.0);
+                    if (fabs(A0) < cutT)
+                        P0 = fma(T, thermal_log(fabs(A0), r.as + r.m, invT, cutT), P0);
+                    base -= P0;
                 }
-            } else {
-                direct = true;
+                neumaier(bs, bc, w * base);
+                const double R02 = fma(x0, r.eta2, r.s2);
+                if (series_term(r, R02, hw, cutT)) {
+                    const double R0 = sqrt_rn(R02);
+                    // R0 - |s| = x0 eta^2 / (R0 + |s|) without cancellation
+                    const double c0 = fp64 ? R0 - r.m
+                                           : (R02 > 0.0 ? x0 * r.eta2 * rcp_nr(R0 + r.as) : 0.0);
+                    mom[0] = fma(w, c0, mom[0]);
+                    // R0 = 0 only with s = 0 and eta^2 x0 = 0: then the powers vanish
+                    const double ratio = R02 > 0.0 ? r.eta2 * rcp_nr(R02) : 0.0;
+                    // terms this wave needs: the smallest level that covers the
+                    // ratio of every series lane (the active lanes here)
+                    const double rho = hw * ratio;
+                    int nt = kSeriesTerms;
+    #pragma unroll
+                    for (int k = kSeriesLevels - 2; k >= 0; --k)
+                        if (__ballot(rho > kLevelRho.v[k]) == 0ull)
+                            nt = kSeriesLevel[k];
+                    double t = w * R0;
+    #pragma unroll
+                    for (int n = 1; n <= kSeriesTerms; ++n) {
+                        if (is_series_level(n - 1) && n > nt)
+                            break;
+                        t *= ratio;
+                        mom[n] += t;
+                    }
+                } else {
+                    direct = true;
+                }
+            }
+            const unsigned long long ballot = __ballot(direct);
+            if (ballot != 0ull) {
+                if (lane == 0) {
+                    lst[wave][2 * n_listed] =
+                        ((unsigned long long)(unsigned)ti << 32) | (unsigned)tj;
+                    lst[wave][2 * n_listed + 1] = ballot;
+                }
+                ++n_listed;
+            }
+            tj += 4;
+            while (tj >= tile_row_len<FD>(kr, ti)) {
+                tj -= tile_row_len<FD>(kr, ti);
+                ++ti;
             }
         }
-        const unsigned long long ballot = __ballot(direct);
-        if (ballot != 0ull) {
-            if (lane == 0) {
-                lst[wave][2 * n_listed] =
-                    ((unsigned long long)(unsigned)ti << 32) | (unsigned)tj;
-                lst[wave][2 * n_listed + 1] = ballot;
-            }
-            ++n_listed;
-        }
-        tj += 4;
-        while (tj >= tile_row_len(kr, ti)) {
-            tj -= tile_row_len(kr, ti);
-            ++ti;
-        }
-    }
+    };
+    if (kr.fd)
+        walk(std::true_type{});
+    else
+        walk(std::false_type{});
     if (lane == 0)
         lcnt[wave] = n_listed;
     __shared__ double red[4][64];
