@@ -167,21 +167,26 @@ Tiles grad_tiles(int Lx, int Ly)
 // Points of equal (Lx, Ly), in order of first appearance.
 struct Group {
     int Lx, Ly;
+    bool hot;   // FP32-compensated sweep: T >= kF32InPlaceT
     std::vector<int> idx;
 };
 
-std::vector<Group> group_points(const omega_point *pts, int n)
+// Points grouped by lattice size and, for the FP32-compensated sweep
+// (split_hot), by T >= kF32InPlaceT, which picks its kernel: a point's
+// group, and so the arithmetic of its result, depends on the point alone.
+std::vector<Group> group_points(const omega_point *pts, int n, bool split_hot = false)
 {
     std::vector<Group> gs;
     for (int i = 0; i < n; ++i) {
+        const bool hot = split_hot && pts[i].T >= kF32InPlaceT;
         Group *g = nullptr;
         for (Group &x : gs)
-            if (x.Lx == pts[i].Lx && x.Ly == pts[i].Ly) {
+            if (x.Lx == pts[i].Lx && x.Ly == pts[i].Ly && x.hot == hot) {
                 g = &x;
                 break;
             }
         if (!g) {
-            gs.push_back(Group{pts[i].Lx, pts[i].Ly, {}});
+            gs.push_back(Group{pts[i].Lx, pts[i].Ly, hot, {}});
             g = &gs.back();
         }
         g->idx.push_back(i);
@@ -215,7 +220,7 @@ struct GridPlan {
 // for it and 2 for the two-band model; the lattice indices of the pair momenta
 // follow it.
 GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb,
-                   bool b3 = false)
+                   bool b3, int precision)
 {
     GridPlan p;
     p.nb = nb;
@@ -223,7 +228,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.n_dtiles = (n_delta + p.td - 1) / p.td;
     p.n_delta_pad = p.n_dtiles * p.td;
     p.nbq = nb * n_q;
-    p.groups = group_points(pts, n_pts);
+    p.groups = group_points(pts, n_pts, precision == OMEGA_FP32_COMP);
     size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, etab = 0, tlist = 0,
            tcnt = 0, tpart = 0;
     for (const Group &g : p.groups) {
@@ -385,7 +390,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
                  double *grid, int32_t *row_idx, hipStream_t s)
 {
     const int nb = md.nb;
-    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3);
+    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3, precision);
     double *d2 = (double *)(ws + P.off_d2);
     double *qtrig = (double *)(ws + P.off_qtrig);
     double2 *gtab = (double2 *)(ws + P.off_gtab);
@@ -441,7 +446,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     r.base_part = base;
     r.mpart = mom;
     r.d2c = d2 + P.n_delta_pad;
-    r.tpart = precision == OMEGA_FP64 ? tpart : nullptr;
+    r.zero_d0 = precision == OMEGA_FP64 ? 0 : 1;
     r.d2 = d2;
     r.td = P.td;
     r.n_dtiles = P.n_dtiles;
@@ -476,6 +481,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         a.lcap = list_cap(t);
         r.n_k = (double)g.Lx * g.Ly;
         r.n_chunks = t.n_chunks;
+        r.tpart = g.hot ? nullptr : tpart;   // the in-place kernel has no tile series
         const int n = (int)g.idx.size();
         for (int b0 = 0; b0 < n; b0 += P.batch[gi]) {
             const int G = n - b0 < P.batch[gi] ? n - b0 : P.batch[gi];
@@ -488,7 +494,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
                 return OMEGA_E_HIP;
             hipError_t e = precision == OMEGA_FP64
                                ? launch_sweep_f64(a, P.td, P.n_dtiles, G, md.b3, s)
-                               : launch_sweep_f32c(a, P.td, P.n_dtiles, G, md.b3, s);
+                               : launch_sweep_f32c(a, P.td, P.n_dtiles, G, md.b3, g.hot, s);
             if (e != hipSuccess)
                 return OMEGA_E_HIP;
             if (g_sweep_stop && hipEventRecord(g_sweep_stop, s) != hipSuccess)
@@ -508,7 +514,7 @@ int run_grid(const ModelDesc &md, const omega_point *pts, int n_pts, const doubl
 {
     if (!delta_dev || !q_dev || !omega_dev || !ws_dev)
         return OMEGA_E_INVAL;
-    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, md.nb, md.b3).sweep_bytes)
+    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, md.nb, md.b3, precision).sweep_bytes)
         return OMEGA_E_WORKSPACE;
     return enqueue_grid(md, pts, n_pts, delta_dev, n_delta, q_dev, n_q, precision,
                         (char *)ws_dev, 0.0, omega_dev, nullptr, (hipStream_t)stream);
@@ -524,7 +530,7 @@ int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const dou
     if (!(tie_rel >= 0.0) || !isfinite(tie_rel))
         return OMEGA_E_INVAL;
     const int nb = md.nb;
-    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3).sweep_bytes;
+    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3, precision).sweep_bytes;
     const size_t need = sweep + (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
     if (ws_bytes < need)
         return OMEGA_E_WORKSPACE;
@@ -665,7 +671,7 @@ size_t omega_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
         return plan_grad(pts, n_pts, nb).bytes;
     if (!sizes_ok(n_delta, n_q, bands, precision))
         return 0;
-    return plan_grid(pts, n_pts, n_delta, n_q, nb).sweep_bytes +
+    return plan_grid(pts, n_pts, n_delta, n_q, nb, false, precision).sweep_bytes +
            grid_bytes(n_pts, n_delta, n_q, nb);
 }
 
@@ -724,7 +730,7 @@ size_t omega3_workspace_bytes(const omega_point *pts, int n_pts, int n_delta, in
         return 0;
     int list[3];
     const int nb = slot_bands3(bands, list);
-    return plan_grid(pts, n_pts, n_delta, n_q, nb, true).sweep_bytes +
+    return plan_grid(pts, n_pts, n_delta, n_q, nb, true, precision).sweep_bytes +
            grid_bytes(n_pts, n_delta, n_q, nb);
 }
 

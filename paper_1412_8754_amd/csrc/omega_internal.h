@@ -31,6 +31,10 @@ constexpr double kCutFp64 = 36.0;
 // Same for the FP32 sweep: exp(-17) = 4.1e-8 is below the FP32 resolution of
 // the terms it would be added to.
 constexpr float kCutFp32 = 17.0f;
+// FP32-compensated sweep: from this temperature on, a point's marked terms
+// run the per-Delta loop in place rather than being classified per Delta
+// tile and queued (at higher T almost none is zero or on a tile series).
+constexpr double kF32InPlaceT = 0.005;
 
 // Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 36: entry N
 // holds (G(a0), 1/(1 + e^a0)) at a0 = N / kGStep.
@@ -173,7 +177,7 @@ struct SweepArgs {
                                  // mask) of the tiles with lanes evaluated per Delta,
                                  // listed by the series pass, first entries used
     int *tcnt;           // [G*nbq][n_chunks] list lengths
-    double *tpart;       // FP64: [G*nbq][n_chunks][n_dtiles][kTileSlots] tile-series moments
+    double *tpart;       // [G*nbq][n_chunks][n_dtiles][kTileSlots] tile-series moments
     int n_dtiles;
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
@@ -189,7 +193,10 @@ struct RowArgs {
     const double *base_part;
     const double *mpart;   // [G*nbq][n_chunks][kMomentSlots] series moments
     const double *d2c;     // centre of the Delta^2 range (series variable x - x0)
-    const double *tpart;   // tile-series moments (FP64 sweep) or nullptr
+    const double *tpart;   // tile-series moments of the sweep
+    int zero_d0;           // 1: the FP32-compensated sweep, whose Delta-dependent
+                           // part vanishes at Delta = 0: the tile series is not
+                           // added there
     const double *d2;      // [n_delta_pad] Delta^2 (tile centres)
     int td, n_dtiles;
     const PointRec *pts;   // [G]
@@ -278,8 +285,10 @@ hipError_t launch_qlat(const double *q, int n_q, int Lx, int Ly, int *qlat, hipS
 hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStream_t s);
 hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                             hipStream_t s);
+// hot: the batch's points all have T >= kF32InPlaceT (the in-place kernel,
+// which writes no tile-series moments)
 hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
-                             hipStream_t s);
+                             bool hot, hipStream_t s);
 hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s);
 hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s);
 hipError_t launch_grad(const GradArgs &a, int G, hipStream_t s);

@@ -985,16 +985,94 @@ static int persistent_blocks(K kernel, unsigned long long units)
     return (int)(n < units ? n : units);
 }
 
-// Per-Delta FP64 sweep over the lanes series_kernel marked for direct
+// FP32-compensated sweep.  With P(Delta) = max(R - |d|, 0) + T ln((1+u1)(1+u2))
+// the term of Eq. (5) is [2 min(d,0) + E_{k down}] - P(Delta), split as
+//   [2 min(d,0) + E_{k down} - P(0)]          FP64, in series_kernel
+//   - [P(Delta) - P(0)]                       FP32, per Delta
+// With A0 = |s| - |d| and delta = R - |s| = Delta^2 eta^2 / (R + |s|) (no
+// cancellation), the cold part of the difference is delta when A0 >= 0 and
+// max(A0 + delta, 0) otherwise.  The thermal part is T (L(Delta) - L(0)) with
+// both logarithms in FP32.  The difference vanishes at Delta = 0, where the
+// result is exactly the FP64 value (Delta = 0 slots are zeroed), so the
+// Q-degenerate normal-state row keeps its FP64 degeneracy; elsewhere it is
+// small where the term is large.  Terms on the series path contribute
+// delta through the FP64 moments instead, and terms on a Delta tile's series
+// (R - |d|) - P(0) through FP64 tile moments.  Each lane sums the few queued
+// terms it evaluates per unit in FP32 before the FP64 reduction tree.
+struct KQf {
+    float s2, as, m, eta2, A0;
+    float P0;      // T * L(0) in FP32, through the Delta loop's own arithmetic
+};
+
+// FP32 thermal logarithm of the Delta loop, ln((1 + u1)(1 + u2)).
+__device__ __forceinline__ float thermal_log_f32(float ax, float y, float invT,
+                                                 float cutT)
+{
+    float u1 = __expf(-ax * invT);
+    float u2 = (y < cutT) ? __expf(-y * invT) : 0.0f;
+    return __logf(1.0f + (u1 + u2 + u1 * u2));
+}
+
+__device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
+{
+    KQf r;
+    r.s2 = (float)q.s2;
+    // |s| >= 1e-30 keeps R + |s| > 0 at s = Delta = 0 (delta stays 0 there)
+    r.as = (float)fmax(q.as, 1e-30);
+    r.m = (float)q.m;
+    r.eta2 = (float)q.eta2;
+    r.A0 = (float)(q.as - q.m);
+    const float Tf = (float)T, cutTf = kCutFp32 * Tf;
+    const float ax0 = fabsf(r.A0);
+    r.P0 = ax0 < cutTf
+               ? Tf * thermal_log_f32(ax0, __builtin_amdgcn_sqrtf(r.s2) + r.m,
+                                      (float)invT, cutTf)
+               : 0.0f;
+    return r;
+}
+
+// The per-Delta FP32 loop of one term: acc[t] += w (P(Delta_t) - P(0)),
+// Delta^2 from the hi/lo pairs dp[0..TD] (dp[TD] only read ahead).
+template <int TD>
+__device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float wf,
+                                          const float2 *dp, float Tf, float invTf,
+                                          float cutTf)
+{
+    const bool hot0 = f.P0 != 0.0f;
+    const bool pos = f.A0 >= 0.0f;
+    float2 dcur = dp[0];
+#pragma unroll
+    for (int t = 0; t < TD; ++t) {
+        const float2 dnext = dp[t + 1];
+        const float g2 = fmaf(dcur.x, f.eta2, dcur.y * f.eta2);
+        const float R = __builtin_amdgcn_sqrtf(f.s2 + g2);
+        const float del = g2 * __builtin_amdgcn_rcpf(R + f.as);
+        const float x = f.A0 + del;
+        float piece = pos ? del : fmaxf(x, 0.0f);
+        const float ax = fabsf(x);
+        if (ax < cutTf || hot0) {
+            const float L = ax < cutTf ? thermal_log_f32(ax, R + f.m, invTf, cutTf) : 0.0f;
+            piece += fmaf(Tf, L, -f.P0);
+        }
+        acc[t] = fmaf(wf, piece, acc[t]);
+        dcur = dnext;
+    }
+}
+
+// Per-Delta sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.  The kernel is
 // persistent and each wave works on its own: it takes (chunk, Delta tile,
 // row) units from the work queue until it runs dry (see take_unit), walks
 // all listed tiles of the unit's chunk and writes the unit's sums itself, so
-// no wave waits for another.  The workgroup only shares the thermal table,
-// loaded into LDS once.
-template <int TD, bool B3>
+// no wave waits for another.  Per Delta tile a marked term is exactly zero,
+// summed through the tile series, or queued for the per-Delta loop.
+// F32 = false: everything in FP64; the workgroup shares the thermal table,
+// loaded into LDS once.  F32 = true (the FP32-compensated sweep): the
+// classification and the tile series stay FP64, and the loop evaluates
+// P(Delta) - P(0) in FP32 (see KQf).
+template <int TD, bool B3, bool F32>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
-void sweep_f64_kernel(const SweepArgs args)
+void sweep_kernel(const SweepArgs args)
 {
     const SweepArgs &a0 = args;
     const int lane = threadIdx.x & 63;
@@ -1004,15 +1082,23 @@ void sweep_f64_kernel(const SweepArgs args)
     // the unit's constants (kept in LDS rather than in registers across the
     // tile loop); per workgroup: the thermal table
     __shared__ double d2s[4][TD + 1];
+    // FP32 sweep: the same Delta^2 as an unevaluated FP32 pair hi + lo
+    // (rounding Delta^2 to one float would shift every momentum's term at
+    // that Delta the same way, a systematic 6e-8 that the sum would not
+    // average out)
+    __shared__ float2 d2f[4][F32 ? TD + 1 : 1];
     __shared__ double uc[4][kUnitConsts];
-    __shared__ double2 gt[kGTabN];
-    // per wave: queue of the (k, Q) terms that need the per-Delta loop,
-    // s^2 (floored), |d|, eta^2 and the mirror weight; the loop runs on 64
-    // of them at a time, so that every lane of the wave has a term
-    __shared__ double lq[4][3][2 * 64];   // s^2, |d|, eta^2
-    __shared__ float lqw[4][2 * 64];      // weight
-    for (int n = threadIdx.x; n < kGTabN; n += kBlock)
-        gt[n] = a0.gtab[n];
+    __shared__ double2 gt[F32 ? 1 : kGTabN];
+    // per wave: queue of the (k, Q) terms that need the per-Delta loop and
+    // their mirror weights; the loop runs on 64 of them at a time, so that
+    // every lane of the wave has a term.  FP64: s^2 (floored), |d|, eta^2;
+    // FP32: the six floats of KQf in the same bytes.
+    __shared__ double lq[4][3][2 * 64];
+    __shared__ float lqw[4][2 * 64];
+    if constexpr (!F32) {
+        for (int n = threadIdx.x; n < kGTabN; n += kBlock)
+            gt[n] = a0.gtab[n];
+    }
     __syncthreads();
     int n_direct = 0;
     const int nq = sweep_queues();
@@ -1052,8 +1138,13 @@ void sweep_f64_kernel(const SweepArgs args)
             lo = fmin(lo, __shfl_xor(lo, off, 64));
             hi = fmax(hi, __shfl_xor(hi, off, 64));
         }
-        if (lane <= TD)
+        if (lane <= TD) {
             d2s[wave][lane] = dl;
+            if constexpr (F32) {
+                const float dhi = (float)dl;
+                d2f[wave][lane] = make_float2(dhi, (float)(dl - (double)dhi));
+            }
+        }
         if (lane == 0) {
             // centre and half-width of the tile series
             double *u = uc[wave];
@@ -1073,10 +1164,11 @@ void sweep_f64_kernel(const SweepArgs args)
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        double acc[TD];
+        using Acc = std::conditional_t<F32, float, double>;
+        Acc acc[TD];
 #pragma unroll
         for (int t = 0; t < TD; ++t)
-            acc[t] = 0.0;
+            acc[t] = Acc(0);
         double tm[kTileSlots];
 #pragma unroll
         for (int n = 0; n < kTileSlots; ++n)
@@ -1129,7 +1221,17 @@ void sweep_f64_kernel(const SweepArgs args)
                 const double Rc = sqrt_rn(Rc2);
                 // Rc = 0 only with s = 0 and xc eta^2 = 0: the powers vanish
                 const double ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
-                tm[0] = fma(w, Rc - r.m, tm[0]);
+                double c0 = Rc - r.m;
+                if constexpr (F32) {
+                    // minus P(0), as series_kernel takes it off the base term
+                    const double A0 = r.as - r.m;
+                    double P0 = fmax(A0, 0.0);
+                    if (fabs(A0) < cutT)
+                        P0 = fma(cp[kUcT], thermal_log(fabs(A0), r.as + r.m, cp[kUcInvT], cutT),
+                                 P0);
+                    c0 -= P0;
+                }
+                tm[0] = fma(w, c0, tm[0]);
                 double tp = w * Rc;
 #pragma unroll
                 for (int n = 1; n < kTileSlots; ++n) {
@@ -1146,9 +1248,20 @@ void sweep_f64_kernel(const SweepArgs args)
                 const int at = pending + (int)__builtin_amdgcn_mbcnt_hi(
                                              (unsigned)(lb >> 32),
                                              __builtin_amdgcn_mbcnt_lo((unsigned)lb, 0u));
-                lq[wave][0][at] = r.s2 + 1e-300;
-                lq[wave][1][at] = r.m;
-                lq[wave][2][at] = r.eta2;
+                if constexpr (F32) {
+                    const KQf f = kq_setup_f32(r, cp[kUcT], cp[kUcInvT]);
+                    float *lf = reinterpret_cast<float *>(&lq[wave][0][0]);
+                    lf[0 * 128 + at] = f.s2;
+                    lf[1 * 128 + at] = f.as;
+                    lf[2 * 128 + at] = f.m;
+                    lf[3 * 128 + at] = f.eta2;
+                    lf[4 * 128 + at] = f.A0;
+                    lf[5 * 128 + at] = f.P0;
+                } else {
+                    lq[wave][0][at] = r.s2 + 1e-300;
+                    lq[wave][1][at] = r.m;
+                    lq[wave][2][at] = r.eta2;
+                }
                 lqw[wave][at] = (float)w;
             }
             pending += __popcll(lb);
@@ -1161,7 +1274,21 @@ void sweep_f64_kernel(const SweepArgs args)
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
                 const int nb = pending < 64 ? pending : 64;
-                if (lane < nb) {
+                if (F32 && lane < nb) {
+                    // P(Delta) - P(0) in FP32 (see KQf)
+                    const float *lf = reinterpret_cast<const float *>(&lq[wave][0][0]);
+                    KQf f;
+                    f.s2 = lf[0 * 128 + lane];
+                    f.as = lf[1 * 128 + lane];
+                    f.m = lf[2 * 128 + lane];
+                    f.eta2 = lf[3 * 128 + lane];
+                    f.A0 = lf[4 * 128 + lane];
+                    f.P0 = lf[5 * 128 + lane];
+                    const float Tf = (float)cp[kUcT];
+                    if constexpr (F32)
+                        f32_steps<TD>(acc, f, lqw[wave][lane], d2f[wave] + zoff, Tf,
+                                      (float)cp[kUcInvT], kCutFp32 * Tf);
+                } else if (!F32 && lane < nb) {
                     const double s2p = lq[wave][0][lane];
                     const double m = lq[wave][1][lane];
                     const double eta2 = lq[wave][2][lane];
@@ -1190,9 +1317,16 @@ void sweep_f64_kernel(const SweepArgs args)
                 // terms beyond the first 64 move to the front of the queue
                 pending -= nb;
                 if (lane < pending) {
-                    lq[wave][0][lane] = lq[wave][0][64 + lane];
-                    lq[wave][1][lane] = lq[wave][1][64 + lane];
-                    lq[wave][2][lane] = lq[wave][2][64 + lane];
+                    if constexpr (F32) {
+                        float *lf = reinterpret_cast<float *>(&lq[wave][0][0]);
+#pragma unroll
+                        for (int c = 0; c < 6; ++c)
+                            lf[c * 128 + lane] = lf[c * 128 + 64 + lane];
+                    } else {
+                        lq[wave][0][lane] = lq[wave][0][64 + lane];
+                        lq[wave][1][lane] = lq[wave][1][64 + lane];
+                        lq[wave][2][lane] = lq[wave][2][64 + lane];
+                    }
                     lqw[wave][lane] = lqw[wave][64 + lane];
                 }
             }
@@ -1200,11 +1334,19 @@ void sweep_f64_kernel(const SweepArgs args)
 
         // the unit's sums: lane t << SHIFT holds Delta t, lane n << TSHIFT
         // moment n
-        wave_reduce_halving<TD>(acc, lane);
+        double accd[TD];
+#pragma unroll
+        for (int t = 0; t < TD; ++t) {
+            if constexpr (F32)   // the FP32 difference is zero at Delta = 0
+                accd[t] = d2s[wave][t] == 0.0 ? 0.0 : (double)acc[t];
+            else
+                accd[t] = acc[t];
+        }
+        wave_reduce_halving<TD>(accd, lane);
         constexpr int SHIFT = 6 - Log2<TD>::value;
         if ((lane & ((1 << SHIFT) - 1)) == 0)
             a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD +
-                   (lane >> SHIFT)] = acc[0];
+                   (lane >> SHIFT)] = accd[0];
         wave_reduce_halving<kTileSlots>(tm, lane);
         constexpr int TSHIFT = 6 - Log2<kTileSlots>::value;
         if ((lane & ((1 << TSHIFT) - 1)) == 0)
@@ -1215,15 +1357,15 @@ void sweep_f64_kernel(const SweepArgs args)
         atomicAdd(a0.count, (unsigned long long)n_direct * TD);
 }
 
-template <int TD, bool B3>
-static hipError_t launch_persistent_f64(const SweepArgs &a, hipStream_t s)
+template <int TD, bool B3, bool F32>
+static hipError_t launch_persistent(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_f64_kernel<TD, B3>, units);
+    const int blocks = persistent_blocks(sweep_kernel<TD, B3, F32>, units);
     if (blocks <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_f64_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<TD, B3, F32>), dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1234,68 +1376,26 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, boo
     p.n_dtiles = n_dtiles;
     p.n_rows = a.nbq * G;
     if (td == 16 && !b3)
-        return launch_persistent_f64<16, false>(p, s);
+        return launch_persistent<16, false, false>(p, s);
     if (td == 32 && !b3)
-        return launch_persistent_f64<32, false>(p, s);
+        return launch_persistent<32, false, false>(p, s);
     if (td == 16)
-        return launch_persistent_f64<16, true>(p, s);
+        return launch_persistent<16, true, false>(p, s);
     if (td == 32)
-        return launch_persistent_f64<32, true>(p, s);
+        return launch_persistent<32, true, false>(p, s);
     return hipErrorInvalidValue;
 }
 
-// FP32-compensated sweep.  With P(Delta) = max(R - |d|, 0) + T ln((1+u1)(1+u2))
-// the term of Eq. (5) is [2 min(d,0) + E_{k down}] - P(Delta), split as
-//   [2 min(d,0) + E_{k down} - P(0)]          FP64, in series_kernel
-//   - [P(Delta) - P(0)]                       FP32, per Delta
-// With A0 = |s| - |d| and delta = R - |s| = Delta^2 eta^2 / (R + |s|) (no
-// cancellation), the cold part of the difference is delta when A0 >= 0 and
-// max(A0 + delta, 0) otherwise.  The thermal part is T (L(Delta) - L(0)) with
-// both logarithms in FP32.  The difference vanishes at Delta = 0, where the
-// result is exactly the FP64 value (Delta = 0 slots are zeroed), so the
-// Q-degenerate normal-state row keeps its FP64 degeneracy; elsewhere it is
-// small where the term is large.  Terms on the series path contribute
-// delta through the FP64 moments instead.  Each thread sums a few tens of
-// momenta per Delta in FP32 before the FP64 reduction tree.
-struct KQf {
-    float s2, as, m, eta2, A0;
-    float P0;      // T * L(0) in FP32, through the Delta loop's own arithmetic
-};
-
-// FP32 thermal logarithm of the Delta loop, ln((1 + u1)(1 + u2)).
-__device__ __forceinline__ float thermal_log_f32(float ax, float y, float invT,
-                                                 float cutT)
-{
-    float u1 = __expf(-ax * invT);
-    float u2 = (y < cutT) ? __expf(-y * invT) : 0.0f;
-    return __logf(1.0f + (u1 + u2 + u1 * u2));
-}
-
-__device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
-{
-    KQf r;
-    r.s2 = (float)q.s2;
-    // |s| >= 1e-30 keeps R + |s| > 0 at s = Delta = 0 (delta stays 0 there)
-    r.as = (float)fmax(q.as, 1e-30);
-    r.m = (float)q.m;
-    r.eta2 = (float)q.eta2;
-    r.A0 = (float)(q.as - q.m);
-    const float Tf = (float)T, cutTf = kCutFp32 * Tf;
-    const float ax0 = fabsf(r.A0);
-    r.P0 = ax0 < cutTf
-               ? Tf * thermal_log_f32(ax0, __builtin_amdgcn_sqrtf(r.s2) + r.m,
-                                      (float)invT, cutTf)
-               : 0.0f;
-    return r;
-}
-
-// The FP32-compensated per-Delta sweep; persistent like the FP64 sweep, with
-// the same work queue and units, one unit per wave at a time.  Two-band: 5
+// The FP32-compensated per-Delta sweep for points at T >= kF32InPlaceT, where
+// almost no marked term is zero or on a tile series over a Delta tile: every
+// marked lane runs the FP32 loop in place, without classification or queue.
+// Persistent like sweep_kernel, with the same work queues and units, one
+// unit per wave at a time.  Two-band: 5
 // waves/SIMD (a few spills outside the Delta loop beat the 4 waves its
 // registers would otherwise give); three-band: 4.
 template <int TD, bool B3>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B3 ? 4 : 5)))
-void sweep_f32c_kernel(const SweepArgs args)
+void sweep_f32c_hot_kernel(const SweepArgs args)
 {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -1420,31 +1520,42 @@ void sweep_f32c_kernel(const SweepArgs args)
 }
 
 template <int TD, bool B3>
-static hipError_t launch_persistent_f32c(const SweepArgs &a, hipStream_t s)
+static hipError_t launch_persistent_f32c_hot(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_f32c_kernel<TD, B3>, units);
+    const int blocks = persistent_blocks(sweep_f32c_hot_kernel<TD, B3>, units);
     if (blocks <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_f32c_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((sweep_f32c_hot_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
-                             hipStream_t s)
+                             bool hot, hipStream_t s)
 {
     SweepArgs p = a;
     p.n_dtiles = n_dtiles;
     p.n_rows = a.nbq * G;
+    if (hot) {
+        if (td == 16 && !b3)
+            return launch_persistent_f32c_hot<16, false>(p, s);
+        if (td == 32 && !b3)
+            return launch_persistent_f32c_hot<32, false>(p, s);
+        if (td == 16)
+            return launch_persistent_f32c_hot<16, true>(p, s);
+        if (td == 32)
+            return launch_persistent_f32c_hot<32, true>(p, s);
+        return hipErrorInvalidValue;
+    }
     if (td == 16 && !b3)
-        return launch_persistent_f32c<16, false>(p, s);
+        return launch_persistent<16, false, true>(p, s);
     if (td == 32 && !b3)
-        return launch_persistent_f32c<32, false>(p, s);
+        return launch_persistent<32, false, true>(p, s);
     if (td == 16)
-        return launch_persistent_f32c<16, true>(p, s);
+        return launch_persistent<16, true, true>(p, s);
     if (td == 32)
-        return launch_persistent_f32c<32, true>(p, s);
+        return launch_persistent<32, true, true>(p, s);
     return hipErrorInvalidValue;
 }
 
@@ -1714,7 +1825,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
                 ser = fma(ser, x, sh_mom[n]);
             ser = fma(ser, x, sh_mom[0]);
             double sp_t = 0.0;
-            if (r.tpart) {
+            if (r.tpart && !(r.zero_d0 && D * D == 0.0)) {
                 const int u = id / r.td - b0;
                 const double z = D * D - sh_tc[u];
                 double ts = sh_tm[u][kTileSlots - 1];
