@@ -44,6 +44,15 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 TRAFFIC_BYTES = {("paper", "fp64"): (13616 * 2 + 26720) * 1024}
 
 
+def sweep_kernel_name(precision, three, T):
+    """The library's sweep kernel for one workload point (the FP32-compensated
+    path runs points at T >= 0.005 through its in-place kernel)."""
+    b3 = "true" if three else "false"
+    if precision == "fp32c" and T >= 0.005:
+        return f"sweep_f32c_hot_kernel<32, {b3}>"
+    return f"sweep_kernel<32, {b3}, {'true' if precision == 'fp32c' else 'false'}>"
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,8 +425,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
                      "traffic": TRAFFIC_BYTES.get((args.workload, args.precision)),
-                     "kernel": "sweep_%s_kernel<32>" % ("f64" if args.precision == "fp64"
-                                                        else "f32c"),
+                     "kernel": sweep_kernel_name(args.precision, three, pts[0][1]),
                      "kernel_ms": sweep_avg, "ops_per_eval": OPS_PER_EVAL},
     }
     if not args.no_compare and prec == api.OMEGA_FP64:
