@@ -41,7 +41,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # (x2.0) and WRITE_SIZE (x1.0) passes, scaled by the same counters on a plain
 # 256 MiB device copy (profiles/sweep_f64_paper_L1024.md).  Valid for the
 # kernel build those counters were taken on; None for other workloads.
-TRAFFIC_BYTES = {}   # not yet measured on the current sweep build
+TRAFFIC_BYTES = {("paper", "fp64"): (13604 * 2 + 26720) * 1024}
 
 
 def sweep_kernel_name(precision, three, T):
@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--precision", choices=["fp64", "fp32c"], default="fp64")
     ap.add_argument("--workload", default="paper")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-rows", type=int, default=4,
+    ap.add_argument("--cpu-rows", type=int, default=12,
                     help="Q rows per band in the CPU oracle sample")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32-compensated comparison leg")
