@@ -167,18 +167,18 @@ Tiles grad_tiles(int Lx, int Ly)
 // Points of equal (Lx, Ly), in order of first appearance.
 struct Group {
     int Lx, Ly;
-    bool hot;   // FP32-compensated sweep: T >= kF32InPlaceT
+    bool hot;   // grid sweeps: T >= kInPlaceT
     std::vector<int> idx;
 };
 
-// Points grouped by lattice size and, for the FP32-compensated sweep
-// (split_hot), by T >= kF32InPlaceT, which picks its kernel: a point's
-// group, and so the arithmetic of its result, depends on the point alone.
+// Points grouped by lattice size and, for the grid sweeps (split_hot), by
+// T >= kInPlaceT, which picks the sweep kernel: a point's group, and so the
+// arithmetic of its result, depends on the point alone.
 std::vector<Group> group_points(const omega_point *pts, int n, bool split_hot = false)
 {
     std::vector<Group> gs;
     for (int i = 0; i < n; ++i) {
-        const bool hot = split_hot && pts[i].T >= kF32InPlaceT;
+        const bool hot = split_hot && pts[i].T >= kInPlaceT;
         Group *g = nullptr;
         for (Group &x : gs)
             if (x.Lx == pts[i].Lx && x.Ly == pts[i].Ly && x.hot == hot) {
@@ -220,7 +220,7 @@ struct GridPlan {
 // for it and 2 for the two-band model; the lattice indices of the pair momenta
 // follow it.
 GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int nb,
-                   bool b3, int precision)
+                   bool b3)
 {
     GridPlan p;
     p.nb = nb;
@@ -228,7 +228,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.n_dtiles = (n_delta + p.td - 1) / p.td;
     p.n_delta_pad = p.n_dtiles * p.td;
     p.nbq = nb * n_q;
-    p.groups = group_points(pts, n_pts, precision == OMEGA_FP32_COMP);
+    p.groups = group_points(pts, n_pts, true);
     size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, etab = 0, tlist = 0,
            tcnt = 0, tpart = 0;
     for (const Group &g : p.groups) {
@@ -390,7 +390,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
                  double *grid, int32_t *row_idx, hipStream_t s)
 {
     const int nb = md.nb;
-    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3, precision);
+    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3);
     double *d2 = (double *)(ws + P.off_d2);
     double *qtrig = (double *)(ws + P.off_qtrig);
     double2 *gtab = (double2 *)(ws + P.off_gtab);
@@ -493,7 +493,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
             if (g_sweep_start && hipEventRecord(g_sweep_start, s) != hipSuccess)
                 return OMEGA_E_HIP;
             hipError_t e = precision == OMEGA_FP64
-                               ? launch_sweep_f64(a, P.td, P.n_dtiles, G, md.b3, s)
+                               ? launch_sweep_f64(a, P.td, P.n_dtiles, G, md.b3, g.hot, s)
                                : launch_sweep_f32c(a, P.td, P.n_dtiles, G, md.b3, g.hot, s);
             if (e != hipSuccess)
                 return OMEGA_E_HIP;
@@ -514,7 +514,7 @@ int run_grid(const ModelDesc &md, const omega_point *pts, int n_pts, const doubl
 {
     if (!delta_dev || !q_dev || !omega_dev || !ws_dev)
         return OMEGA_E_INVAL;
-    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, md.nb, md.b3, precision).sweep_bytes)
+    if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, md.nb, md.b3).sweep_bytes)
         return OMEGA_E_WORKSPACE;
     return enqueue_grid(md, pts, n_pts, delta_dev, n_delta, q_dev, n_q, precision,
                         (char *)ws_dev, 0.0, omega_dev, nullptr, (hipStream_t)stream);
@@ -530,7 +530,7 @@ int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const dou
     if (!(tie_rel >= 0.0) || !isfinite(tie_rel))
         return OMEGA_E_INVAL;
     const int nb = md.nb;
-    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3, precision).sweep_bytes;
+    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3).sweep_bytes;
     const size_t need = sweep + (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
     if (ws_bytes < need)
         return OMEGA_E_WORKSPACE;
@@ -671,7 +671,7 @@ size_t omega_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
         return plan_grad(pts, n_pts, nb).bytes;
     if (!sizes_ok(n_delta, n_q, bands, precision))
         return 0;
-    return plan_grid(pts, n_pts, n_delta, n_q, nb, false, precision).sweep_bytes +
+    return plan_grid(pts, n_pts, n_delta, n_q, nb, false).sweep_bytes +
            grid_bytes(n_pts, n_delta, n_q, nb);
 }
 
@@ -730,7 +730,7 @@ size_t omega3_workspace_bytes(const omega_point *pts, int n_pts, int n_delta, in
         return 0;
     int list[3];
     const int nb = slot_bands3(bands, list);
-    return plan_grid(pts, n_pts, n_delta, n_q, nb, true, precision).sweep_bytes +
+    return plan_grid(pts, n_pts, n_delta, n_q, nb, true).sweep_bytes +
            grid_bytes(n_pts, n_delta, n_q, nb);
 }
 

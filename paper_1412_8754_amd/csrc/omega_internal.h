@@ -31,10 +31,10 @@ constexpr double kCutFp64 = 36.0;
 // Same for the FP32 sweep: exp(-17) = 4.1e-8 is below the FP32 resolution of
 // the terms it would be added to.
 constexpr float kCutFp32 = 17.0f;
-// FP32-compensated sweep: from this temperature on, a point's marked terms
-// run the per-Delta loop in place rather than being classified per Delta
-// tile and queued (at higher T almost none is zero or on a tile series).
-constexpr double kF32InPlaceT = 0.005;
+// From this temperature on, a point's marked terms run the per-Delta loop in
+// place rather than being classified per Delta tile and queued (at higher T
+// almost none is zero or on a tile series), in both precisions.
+constexpr double kInPlaceT = 0.005;
 
 // Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 36: entry N
 // holds (G(a0), 1/(1 + e^a0)) at a0 = N / kGStep.
@@ -283,10 +283,10 @@ hipError_t launch_etab(const Hop3 &h, const double *trig, int Lx, int Ly, double
                        hipStream_t s);
 hipError_t launch_qlat(const double *q, int n_q, int Lx, int Ly, int *qlat, hipStream_t s);
 hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStream_t s);
+// hot: the batch's points all have T >= kInPlaceT (the in-place kernels,
+// which write no tile-series moments)
 hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
-                            hipStream_t s);
-// hot: the batch's points all have T >= kF32InPlaceT (the in-place kernel,
-// which writes no tile-series moments)
+                            bool hot, hipStream_t s);
 hipError_t launch_sweep_f32c(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
                              bool hot, hipStream_t s);
 hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s);

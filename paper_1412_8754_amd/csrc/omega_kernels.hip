@@ -1059,6 +1059,35 @@ __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float 
     }
 }
 
+// The per-Delta FP64 loop of one term: acc[t] += w P(Delta_t), with
+// P = max(x, 0) + T ln((1 + u1)(1 + u2)), x = R - |d|, u1 = e^-|x|/T,
+// u2 = e^-(R + |d|)/T (each thermal part skipped beyond the cut 36 T);
+// s2p = s^2 (floored), Delta^2 from dp[0..TD] (dp[TD] only read ahead).
+template <int TD>
+__device__ __forceinline__ void f64_steps(double (&acc)[TD], double s2p, double m,
+                                          double eta2, double w, double T, double invT,
+                                          double cutT, const double *dp, const double2 *gt)
+{
+    const double wT = w * T;
+    double dcur = dp[0];
+#pragma unroll
+    for (int t = 0; t < TD; ++t) {
+        const double dnext = dp[t + 1];
+        const double R = sqrt_1s(fma(dcur, eta2, s2p));
+        const double x = R - m;
+        acc[t] = fma(w, fmax(x, 0.0), acc[t]);
+        const double ax = fabs(x);
+        if (ax < cutT) {
+            double L = log1p_exp_tab(ax * invT, gt);
+            const double y = R + m;
+            if (y < cutT)
+                L += log1p_exp_tab(y * invT, gt);
+            acc[t] = fma(wT, L, acc[t]);
+        }
+        dcur = dnext;
+    }
+}
+
 // Per-Delta sweep over the lanes series_kernel marked for direct
 // evaluation; tiles without such lanes are skipped whole.  The kernel is
 // persistent and each wave works on its own: it takes (chunk, Delta tile,
@@ -1289,30 +1318,10 @@ void sweep_kernel(const SweepArgs args)
                         f32_steps<TD>(acc, f, lqw[wave][lane], d2f[wave] + zoff, Tf,
                                       (float)cp[kUcInvT], kCutFp32 * Tf);
                 } else if (!F32 && lane < nb) {
-                    const double s2p = lq[wave][0][lane];
-                    const double m = lq[wave][1][lane];
-                    const double eta2 = lq[wave][2][lane];
-                    const double wq = (double)lqw[wave][lane];
-                    const double wT = wq * cp[kUcT];
-                    const double invT = cp[kUcInvT];
-                    double dcur = dp[0];
-#pragma unroll
-                    for (int t = 0; t < TD; ++t) {
-                        const double dnext = dp[t + 1];
-                        const double R = sqrt_1s(fma(dcur, eta2, s2p));
-                        const double x = R - m;
-                        acc[t] = fma(wq, fmax(x, 0.0), acc[t]);
-                        const double ax = fabs(x);
-                        if (ax < cutT) {
-                            // T ln((1 + u1)(1 + u2)), u1 = e^-|x|/T, u2 = e^-(R + |d|)/T
-                            double L = log1p_exp_tab(ax * invT, gt);
-                            const double y = R + m;
-                            if (y < cutT)
-                                L += log1p_exp_tab(y * invT, gt);
-                            acc[t] = fma(wT, L, acc[t]);
-                        }
-                        dcur = dnext;
-                    }
+                    if constexpr (!F32)
+                        f64_steps<TD>(acc, lq[wave][0][lane], lq[wave][1][lane],
+                                      lq[wave][2][lane], (double)lqw[wave][lane], cp[kUcT],
+                                      cp[kUcInvT], cutT, dp, gt);
                 }
                 // terms beyond the first 64 move to the front of the queue
                 pending -= nb;
@@ -1369,12 +1378,135 @@ static hipError_t launch_persistent(const SweepArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// The FP64 sweep for points at T >= kInPlaceT, where almost no marked term
+// is zero or on a tile series over a Delta tile: every marked lane runs the
+// FP64 loop in place, without classification or queue, and without the
+// tile-series registers the queued kernel holds (two-band: 4 waves/SIMD
+// instead of 3; three-band: 3).
+// Persistent like sweep_kernel, with the same work queues and units, one
+// unit per wave at a time.
+template <int TD, bool B3>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B3 ? 3 : 4)))
+void sweep_f64_hot_kernel(const SweepArgs args)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    __shared__ double d2s[4][TD + 1];
+    __shared__ double2 gt[kGTabN];
+    for (int n = threadIdx.x; n < kGTabN; n += kBlock)
+        gt[n] = args.gtab[n];
+    __syncthreads();
+    int n_direct = 0;
+    const int li = lane >> 3, lj = lane & 7;
+    const int nq = sweep_queues();
+    const int q = (int)(blockIdx.x % (unsigned)nq);
+    for (;;) {
+        ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
+        asm volatile("" : "+s"(ap));
+        const SweepArgs &a = *(const SweepArgs *)ap;   // the argument, reloaded per unit
+        int3 un = make_int3(0, 0, -1);
+        if (lane == 0)
+            un = take_unit(a, q, nq);
+        const int bz = __builtin_amdgcn_readfirstlane(un.z);
+        if (bz < 0)
+            break;
+        const int chunk = __builtin_amdgcn_readfirstlane(un.x);
+        const int dtile = __builtin_amdgcn_readfirstlane(un.y);
+        const int g = bz / a.nbq;                  // point within the batch
+        const int bq = bz - g * a.nbq;
+        const int slot = bq / a.n_q;
+        const int iq = bq - slot * a.n_q;
+        const double eps = slot ? a.eps[1] : a.eps[0];
+        const double qy = a.q[2 * iq + 1];
+        const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
+        const PointRec pt = a.pts[g];
+        const double mu_up = a.mu + pt.h;
+        const double mu_dn = a.mu - pt.h;
+        const double T = pt.T;
+        const double invT = T > 0.0 ? 1.0 / T : 0.0;
+        const double cutT = kCutFp64 * T;
+        const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
+        const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+        const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+        const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
+
+        if (lane <= TD)
+            d2s[wave][lane] = a.d2[dtile * TD + (lane < TD ? lane : TD - 1)];
+        // the wave's LDS writes above are visible to all of its lanes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        double acc[TD];
+#pragma unroll
+        for (int t = 0; t < TD; ++t)
+            acc[t] = 0.0;
+        const TileList tl = tile_list(a, bz, chunk);
+        // the next entry of the walk is fetched one tile ahead
+        int e = 0;
+        int nt_ti = 0, nt_tj = 0;
+        unsigned long long nt_mask = 0ull;
+        if (e < tl.total)
+            listed_tile(tl, e, nt_ti, nt_tj, nt_mask);
+        for (; e < tl.total; ++e) {
+            const int ti = nt_ti, tj = nt_tj;
+            const unsigned long long mk = nt_mask;
+            if (e + 1 < tl.total)
+                listed_tile(tl, e + 1, nt_ti, nt_tj, nt_mask);
+            const int i = ti * kTileEdge + li;
+            const int j = tj * kTileEdge + lj;
+            int zoff = 0;
+            asm volatile("" : "+v"(zoff));
+            n_direct += __popcll(mk);
+            if ((mk >> lane) & 1ull) {
+                const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j, (unsigned)i * (unsigned)a.Ly,
+                                          eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
+                // R^2 >= 1e-300 keeps the reciprocal square root finite
+                f64_steps<TD>(acc, r.s2 + 1e-300, r.m, r.eta2,
+                              mirror_weight(kr, i, j, a.Lx, a.Ly), T, invT, cutT,
+                              d2s[wave] + zoff, gt);
+            }
+        }
+        // lane t << SHIFT holds Delta t
+        wave_reduce_halving<TD>(acc, lane);
+        constexpr int SHIFT = 6 - Log2<TD>::value;
+        if ((lane & ((1 << SHIFT) - 1)) == 0)
+            a.part[((size_t)bz * a.n_chunks + chunk) * a.n_delta_pad + dtile * TD +
+                   (lane >> SHIFT)] = acc[0];
+    }
+    if (args.count && lane == 0 && n_direct)
+        atomicAdd(args.count, (unsigned long long)n_direct * TD);
+}
+
+template <int TD, bool B3>
+static hipError_t launch_persistent_f64_hot(const SweepArgs &a, hipStream_t s)
+{
+    const unsigned long long units =
+        (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
+    const int blocks = persistent_blocks(sweep_f64_hot_kernel<TD, B3>, units);
+    if (blocks <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_f64_hot_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, bool b3,
-                            hipStream_t s)
+                            bool hot, hipStream_t s)
 {
     SweepArgs p = a;
     p.n_dtiles = n_dtiles;
     p.n_rows = a.nbq * G;
+    if (hot) {
+        if (td == 16 && !b3)
+            return launch_persistent_f64_hot<16, false>(p, s);
+        if (td == 32 && !b3)
+            return launch_persistent_f64_hot<32, false>(p, s);
+        if (td == 16)
+            return launch_persistent_f64_hot<16, true>(p, s);
+        if (td == 32)
+            return launch_persistent_f64_hot<32, true>(p, s);
+        return hipErrorInvalidValue;
+    }
     if (td == 16 && !b3)
         return launch_persistent<16, false, false>(p, s);
     if (td == 32 && !b3)
@@ -1386,7 +1518,7 @@ hipError_t launch_sweep_f64(const SweepArgs &a, int td, int n_dtiles, int G, boo
     return hipErrorInvalidValue;
 }
 
-// The FP32-compensated per-Delta sweep for points at T >= kF32InPlaceT, where
+// The FP32-compensated per-Delta sweep for points at T >= kInPlaceT, where
 // almost no marked term is zero or on a tile series over a Delta tile: every
 // marked lane runs the FP32 loop in place, without classification or queue.
 // Persistent like sweep_kernel, with the same work queues and units, one
