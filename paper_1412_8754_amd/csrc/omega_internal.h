@@ -103,8 +103,10 @@ struct SeriesLevelRho {
     }
 };
 
-// Tile series of the FP64 sweep.  Within one Delta tile (the TD Delta of a
-// sweep workgroup; x = Delta^2 in [x_lo, x_hi], centre xc, half-width ht), a
+// Tile series of the queued sweep (both precisions; in the FP32-compensated
+// one the moments are of (R - |d|) - P(0), C0 taking P(0) off).  Within one
+// Delta tile (the TD Delta of a sweep unit; x = Delta^2 in [x_lo, x_hi],
+// centre xc, half-width ht), a
 // direct term that is cold and positive over the whole tile
 // (R(x_lo) >= |d| + 36 T: R - |d| >= 36 T for every Delta of the tile, no
 // thermal part) has R - |d| = (Rc - |d|) + Rc sum_{n>=1} c_n z^n with
@@ -169,7 +171,7 @@ struct SweepArgs {
     const double *q;     // [n_q][2]
     const double *qtrig; // [n_q][4] cos qx, sin qx, cos qy, sin qy
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
-    const double2 *gtab; // [kGTabN] thermal table (FP64 sweep)
+    const double2 *gtab; // [kGTabN] thermal table (FP64 sweeps)
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments

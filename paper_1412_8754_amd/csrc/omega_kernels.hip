@@ -755,8 +755,9 @@ __device__ __forceinline__ void listed_tile(const TileList &t, int e, int &ti, i
 // loads instead of holding them in registers across the whole unit.
 typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
 
-// Per-unit constants of the FP64 sweep, in LDS: the tile's Delta^2 range
-// [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T and the cut 36 T.
+// Per-unit constants of the queued sweep (sweep_kernel), in LDS: the tile's
+// Delta^2 range [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T and
+// the cut 36 T.
 enum {
     kUcXlo, kUcXhi, kUcXc, kUcHt, kUcMuUp, kUcMuDn, kUcT, kUcInvT, kUcCutT, kUnitConsts
 };
@@ -1917,7 +1918,7 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     double *out = r.omega + orow * r.n_delta;
     const double *pp = r.part + row * r.n_chunks * r.n_delta_pad;
 
-    // tile series of the FP64 sweep, per Delta tile: c_n times the
+    // tile series of the queued sweep, per Delta tile: c_n times the
     // fixed-order chunk sums of its moments, and the tile centre, a batch of
     // kTileBatch tiles at a time
     __shared__ double sh_tm[kTileBatch][kTileSlots];

@@ -162,6 +162,27 @@ def test_series_and_direct_split_against_oracle(dmax, T):
         say(f"series split dmax={dmax} T={T} prec={prec}: worst rel {worst:.3e}")
 
 
+@pytest.mark.parametrize("n_delta", [9, 40])
+def test_kernel_choice_at_the_temperature_threshold(n_delta):
+    # Points below T = 0.005 take the classified, queued sweep and points at
+    # or above it the in-place one, in both precisions and with Delta tiles
+    # of 16 (9 Delta) and 32 (40 Delta); one call holds both sides of the
+    # test, T = 0 and a high T, on square and rectangular lattices.
+    pts = [(0.05, 0.004999, 40, 36), (0.05, 0.005, 40, 36), (-0.1, 0.0051, 33, 33),
+           (0.0, 0.0, 24, 24), (0.1, 0.08, 24, 30)]
+    delta = np.linspace(0.0, 0.6, n_delta)
+    q = np.array([[0.0, 0.0], [2 * np.pi / 40, 0.0], [0.1, 0.2]])
+    ref = oracle.omega_grid(M, pts, delta, q, 3)
+    for prec in (OMEGA_FP64, OMEGA_FP32_COMP):
+        idx, omin, rows, om = run_argmin(pts, delta, q, 3, prec)
+        worst = assert_close(om, ref, pts, delta=delta, **TOL[prec])
+        say(f"threshold n_delta={n_delta} prec={prec}: worst rel {worst:.3e}")
+        if prec == OMEGA_FP64:
+            for p in range(len(pts)):
+                for b in range(2):
+                    assert tuple(idx[p, b]) == brute_argmin(ref[p, b], 1e-11), (p, b)
+
+
 @pytest.mark.parametrize("kind", ["offset", "shuffled", "two_values"])
 def test_series_centre_for_offset_and_unsorted_delta(kind):
     # The series centre comes from the min and max of Delta^2, not from the
