@@ -41,7 +41,7 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # (x2.0) and WRITE_SIZE (x1.0) passes, scaled by the same counters on a plain
 # 256 MiB device copy (profiles/sweep_f64_paper_L1024.md).  Valid for the
 # kernel build those counters were taken on; None for other workloads.
-TRAFFIC_BYTES = {("paper", "fp64"): (13604 * 2 + 26720) * 1024}
+TRAFFIC_BYTES = {("paper", "fp64"): (13616 * 2 + 26720) * 1024}
 
 
 def sweep_kernel_name(precision, three, T):

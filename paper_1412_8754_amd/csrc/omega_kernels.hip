@@ -1122,8 +1122,12 @@ void sweep_kernel(const SweepArgs args)
     // per wave: queue of the (k, Q) terms that need the per-Delta loop and
     // their mirror weights; the loop runs on 64 of them at a time, so that
     // every lane of the wave has a term.  FP64: s^2 (floored), |d|, eta^2;
-    // FP32: the six floats of KQf in the same bytes.
-    __shared__ double lq[4][3][2 * 64];
+    // FP32: the six floats of KQf.  Each instance uses its own member only.
+    union Queue {
+        double d[3][2 * 64];
+        float f[6][2 * 64];
+    };
+    __shared__ Queue lq[4];
     __shared__ float lqw[4][2 * 64];
     if constexpr (!F32) {
         for (int n = threadIdx.x; n < kGTabN; n += kBlock)
@@ -1280,17 +1284,17 @@ void sweep_kernel(const SweepArgs args)
                                              __builtin_amdgcn_mbcnt_lo((unsigned)lb, 0u));
                 if constexpr (F32) {
                     const KQf f = kq_setup_f32(r, cp[kUcT], cp[kUcInvT]);
-                    float *lf = reinterpret_cast<float *>(&lq[wave][0][0]);
-                    lf[0 * 128 + at] = f.s2;
-                    lf[1 * 128 + at] = f.as;
-                    lf[2 * 128 + at] = f.m;
-                    lf[3 * 128 + at] = f.eta2;
-                    lf[4 * 128 + at] = f.A0;
-                    lf[5 * 128 + at] = f.P0;
+                    float(*lf)[2 * 64] = lq[wave].f;
+                    lf[0][at] = f.s2;
+                    lf[1][at] = f.as;
+                    lf[2][at] = f.m;
+                    lf[3][at] = f.eta2;
+                    lf[4][at] = f.A0;
+                    lf[5][at] = f.P0;
                 } else {
-                    lq[wave][0][at] = r.s2 + 1e-300;
-                    lq[wave][1][at] = r.m;
-                    lq[wave][2][at] = r.eta2;
+                    lq[wave].d[0][at] = r.s2 + 1e-300;
+                    lq[wave].d[1][at] = r.m;
+                    lq[wave].d[2][at] = r.eta2;
                 }
                 lqw[wave][at] = (float)w;
             }
@@ -1306,36 +1310,35 @@ void sweep_kernel(const SweepArgs args)
                 const int nb = pending < 64 ? pending : 64;
                 if (F32 && lane < nb) {
                     // P(Delta) - P(0) in FP32 (see KQf)
-                    const float *lf = reinterpret_cast<const float *>(&lq[wave][0][0]);
+                    const float(*lf)[2 * 64] = lq[wave].f;
                     KQf f;
-                    f.s2 = lf[0 * 128 + lane];
-                    f.as = lf[1 * 128 + lane];
-                    f.m = lf[2 * 128 + lane];
-                    f.eta2 = lf[3 * 128 + lane];
-                    f.A0 = lf[4 * 128 + lane];
-                    f.P0 = lf[5 * 128 + lane];
+                    f.s2 = lf[0][lane];
+                    f.as = lf[1][lane];
+                    f.m = lf[2][lane];
+                    f.eta2 = lf[3][lane];
+                    f.A0 = lf[4][lane];
+                    f.P0 = lf[5][lane];
                     const float Tf = (float)cp[kUcT];
                     if constexpr (F32)
                         f32_steps<TD>(acc, f, lqw[wave][lane], d2f[wave] + zoff, Tf,
                                       (float)cp[kUcInvT], kCutFp32 * Tf);
                 } else if (!F32 && lane < nb) {
                     if constexpr (!F32)
-                        f64_steps<TD>(acc, lq[wave][0][lane], lq[wave][1][lane],
-                                      lq[wave][2][lane], (double)lqw[wave][lane], cp[kUcT],
+                        f64_steps<TD>(acc, lq[wave].d[0][lane], lq[wave].d[1][lane],
+                                      lq[wave].d[2][lane], (double)lqw[wave][lane], cp[kUcT],
                                       cp[kUcInvT], cutT, dp, gt);
                 }
                 // terms beyond the first 64 move to the front of the queue
                 pending -= nb;
                 if (lane < pending) {
                     if constexpr (F32) {
-                        float *lf = reinterpret_cast<float *>(&lq[wave][0][0]);
 #pragma unroll
                         for (int c = 0; c < 6; ++c)
-                            lf[c * 128 + lane] = lf[c * 128 + 64 + lane];
+                            lq[wave].f[c][lane] = lq[wave].f[c][64 + lane];
                     } else {
-                        lq[wave][0][lane] = lq[wave][0][64 + lane];
-                        lq[wave][1][lane] = lq[wave][1][64 + lane];
-                        lq[wave][2][lane] = lq[wave][2][64 + lane];
+#pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            lq[wave].d[c][lane] = lq[wave].d[c][64 + lane];
                     }
                     lqw[wave][lane] = lqw[wave][64 + lane];
                 }
