@@ -1257,13 +1257,16 @@ void sweep_kernel(const SweepArgs args)
                 const double ratio = Rc2 > 0.0 ? r.eta2 * rcp_nr(Rc2) : 0.0;
                 double c0 = Rc - r.m;
                 if constexpr (F32) {
-                    // minus P(0), as series_kernel takes it off the base term
+                    // minus P(0): its cold part in FP64, its thermal part in
+                    // FP32 as the loop terms take it (kq_setup_f32)
                     const double A0 = r.as - r.m;
-                    double P0 = fmax(A0, 0.0);
-                    if (fabs(A0) < cutT)
-                        P0 = fma(cp[kUcT], thermal_log(fabs(A0), r.as + r.m, cp[kUcInvT], cutT),
-                                 P0);
-                    c0 -= P0;
+                    const float Tf = (float)cp[kUcT], cutTf = kCutFp32 * Tf;
+                    const float ax0 = (float)fabs(A0);
+                    const float P0f =
+                        ax0 < cutTf ? Tf * thermal_log_f32(ax0, (float)(r.as + r.m),
+                                                           (float)cp[kUcInvT], cutTf)
+                                    : 0.0f;
+                    c0 -= fmax(A0, 0.0) + (double)P0f;
                 }
                 tm[0] = fma(w, c0, tm[0]);
                 double tp = w * Rc;
