@@ -409,7 +409,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
         return OMEGA_E_HIP;
     if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
         return OMEGA_E_HIP;
-    if (precision == OMEGA_FP64 && launch_gtable(gtab, s) != hipSuccess)
+    if (launch_gtable(gtab, s) != hipSuccess)
         return OMEGA_E_HIP;
 
     SweepArgs a;

@@ -171,7 +171,7 @@ struct SweepArgs {
     const double *q;     // [n_q][2]
     const double *qtrig; // [n_q][4] cos qx, sin qx, cos qy, sin qy
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
-    const double2 *gtab; // [kGTabN] thermal table (FP64 sweeps)
+    const double2 *gtab; // [kGTabN] thermal table (FP64 sweeps; P(0) of the FP32-compensated series pass)
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments

@@ -118,18 +118,6 @@ __device__ __forceinline__ double log1p_small(double z)
     return fma(de, kLn2Hi, fma(de, kLn2Lo, lf));
 }
 
-// Thermal part of the two quasiparticle branches, ln((1 + u1)(1 + u2)) with
-// u1 = exp(-ax/T), u2 = exp(-y/T) (u2 dropped beyond the cut).  Kept out of
-// line: it runs for few (k, Delta) at low T and would otherwise hold
-// registers and instruction cache in the cold loop.
-__device__ __attribute__((noinline)) double thermal_log(double ax, double y,
-                                                        double invT, double cutT)
-{
-    double u1 = exp_nonpos(-ax * invT);
-    double u2 = (y < cutT) ? exp_nonpos(-y * invT) : 0.0;
-    return log1p_small(u1 + u2 + u1 * u2);
-}
-
 // G(a) = ln(1 + e^-a) for 0 <= a <= 36 (the thermal term over T) from the
 // table at a0 = N / kGStep, |a - a0| <= 1/128.  With sigma = 1/(1 + e^a0),
 // p = sigma (1 - sigma) and b = 1 - 2 sigma, the derivatives of G at a0 are
@@ -155,6 +143,20 @@ __device__ __forceinline__ double log1p_exp_tab(double a, const double2 *gt)
     g = fma(g, r, 0.5 * p);
     g = fma(g, r, -s);
     return fma(g, r, c.x);
+}
+
+// Thermal part of the two quasiparticle branches, ln((1 + u1)(1 + u2)) =
+// G(ax/T) + G(y/T) with u1 = exp(-ax/T), u2 = exp(-y/T), from the thermal
+// table gt (the second term dropped beyond the cut; the caller has
+// ax < cutT).  Kept out of line: series_kernel needs it for few momenta and
+// would otherwise hold its registers across the tile loop.
+__device__ __attribute__((noinline)) double thermal_tab(double ax, double y, double invT,
+                                                        double cutT, const double2 *gt)
+{
+    double L = log1p_exp_tab(ax * invT, gt);
+    if (y < cutT)
+        L += log1p_exp_tab(y * invT, gt);
+    return L;
 }
 
 // Band energy of App. A, (A.4), from cos/sin of the two momentum components.
@@ -876,9 +878,11 @@ void series_kernel(const SweepArgs a, int fp64)
                 const double A0 = r.as - r.m;
                 double base = r.base;
                 if (!fp64) {
+                    // P(0) for the FP32-compensated sweep, its thermal part
+                    // from the thermal table (read through the cache)
                     double P0 = fmax(A0, 0.0);
                     if (fabs(A0) < cutT)
-                        P0 = fma(T, thermal_log(fabs(A0), r.as + r.m, invT, cutT), P0);
+                        P0 = fma(T, thermal_tab(fabs(A0), r.as + r.m, invT, cutT, a.gtab), P0);
                     base -= P0;
                 }
                 neumaier(bs, bc, w * base);
