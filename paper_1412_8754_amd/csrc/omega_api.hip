@@ -405,11 +405,8 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     int *tcnt = (int *)(ws + P.off_tcnt);
     double *tpart = (double *)(ws + P.off_tpart);
     unsigned long long *queue = (unsigned long long *)(ws + P.off_queue);
-    if (launch_delta2(delta, n_delta, P.n_delta_pad, d2, s) != hipSuccess)
-        return OMEGA_E_HIP;
-    if (launch_qtrig(q, n_q, qtrig, s) != hipSuccess)
-        return OMEGA_E_HIP;
-    if (launch_gtable(gtab, s) != hipSuccess)
+    if (launch_call_tables(delta, n_delta, P.n_delta_pad, d2, q, n_q, qtrig, gtab, s) !=
+        hipSuccess)
         return OMEGA_E_HIP;
 
     SweepArgs a;
@@ -466,11 +463,11 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
         const Group &g = P.groups[gi];
         const Tiles &t = P.tiles[gi];
-        if (launch_trig(g.Lx, g.Ly, trig, s) != hipSuccess)
+        if (launch_group_tables(g.Lx, g.Ly, trig, q, n_q, qlat, s) != hipSuccess)
             return OMEGA_E_HIP;
         const hipError_t te = md.b3 ? launch_etab(md.hop3, trig, g.Lx, g.Ly, etab, s)
                                     : launch_etab2(md.hop, trig, g.Lx, g.Ly, etab, s);
-        if (te != hipSuccess || launch_qlat(q, n_q, g.Lx, g.Ly, qlat, s) != hipSuccess)
+        if (te != hipSuccess)
             return OMEGA_E_HIP;
         a.Lx = g.Lx;
         a.Ly = g.Ly;

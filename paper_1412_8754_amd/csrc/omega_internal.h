@@ -277,6 +277,13 @@ hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, unsigned long 
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
 hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
 hipError_t launch_gtable(double2 *gtab, hipStream_t s);
+// delta2 + qtrig + gtable in one launch
+hipError_t launch_call_tables(const double *delta, int n_delta, int n_delta_pad, double *d2,
+                              const double *q, int n_q, double *qtrig, double2 *gt,
+                              hipStream_t s);
+// trig + qlat in one launch
+hipError_t launch_group_tables(int Lx, int Ly, double *trig, const double *q, int n_q,
+                               int *qlat, hipStream_t s);
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s);
 hipError_t launch_etab2(const Hop &h, const double *trig, int Lx, int Ly, double *etab,

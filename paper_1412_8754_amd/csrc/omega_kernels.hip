@@ -270,9 +270,8 @@ hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, unsigned long 
 }
 
 // cos/sin of the lattice momenta 2 pi i / L.
-__global__ void trig_kernel(int Lx, int Ly, double *trig)
+__device__ __forceinline__ void trig_at(int t, int Lx, int Ly, double *trig)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     double s, c;
     if (t < Lx) {
         sincospi(2.0 * t / Lx, &s, &c);
@@ -286,6 +285,11 @@ __global__ void trig_kernel(int Lx, int Ly, double *trig)
     }
 }
 
+__global__ void trig_kernel(int Lx, int Ly, double *trig)
+{
+    trig_at(blockIdx.x * blockDim.x + threadIdx.x, Lx, Ly, trig);
+}
+
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s)
 {
     const int n = Lx > Ly ? Lx : Ly;
@@ -296,15 +300,15 @@ hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s)
 
 // Squared Delta values, padded to a whole Delta tile with the last value;
 // workgroup 0 also writes max Delta^2 (NaN ignored) into d2[n_delta_pad].
-__global__ __launch_bounds__(kBlock) void delta2_kernel(const double *delta, int n_delta,
-                                                        int n_delta_pad, double *d2)
+__device__ __forceinline__ void delta2_block(int blk, const double *delta, int n_delta,
+                                             int n_delta_pad, double *d2)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blk * kBlock + threadIdx.x;
     if (t < n_delta_pad) {
         const double D = delta[t < n_delta ? t : n_delta - 1];
         d2[t] = D * D;
     }
-    if (blockIdx.x == 0) {
+    if (blk == 0) {
         // centre and half-width of [min Delta^2, max Delta^2] (NaN ignored;
         // a NaN Delta still poisons its own output through Delta^2)
         __shared__ double sh[2][kBlock];
@@ -333,6 +337,12 @@ __global__ __launch_bounds__(kBlock) void delta2_kernel(const double *delta, int
     }
 }
 
+__global__ __launch_bounds__(kBlock) void delta2_kernel(const double *delta, int n_delta,
+                                                        int n_delta_pad, double *d2)
+{
+    delta2_block(blockIdx.x, delta, n_delta, n_delta_pad, d2);
+}
+
 hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
                          double *d2, hipStream_t s)
 {
@@ -343,9 +353,8 @@ hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
 
 // cos and sin of both components of n pair momenta, [n][4] =
 // (cos qx, sin qx, cos qy, sin qy), once per call.
-__global__ void qtrig_kernel(const double *q, int n, double *out)
+__device__ __forceinline__ void qtrig_at(int t, const double *q, int n, double *out)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < n) {
         double s, c;
         sincos(q[2 * t], &s, &c);
@@ -355,6 +364,11 @@ __global__ void qtrig_kernel(const double *q, int n, double *out)
         out[4 * t + 2] = c;
         out[4 * t + 3] = s;
     }
+}
+
+__global__ void qtrig_kernel(const double *q, int n, double *out)
+{
+    qtrig_at(blockIdx.x * blockDim.x + threadIdx.x, q, n, out);
 }
 
 hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s)
@@ -367,13 +381,47 @@ hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s)
 
 // Per (k, Q) invariants of one band.
 // Thermal table: entry N = (ln(1 + e^-a0), 1/(1 + e^a0)), a0 = N / kGStep.
-__global__ void gtable_kernel(double2 *gt)
+__device__ __forceinline__ void gtable_at(int n, double2 *gt)
 {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n < kGTabN) {
         const double e = exp(-n * (1.0 / kGStep));
         gt[n] = make_double2(log1p(e), e / (1.0 + e));
     }
+}
+
+__global__ void gtable_kernel(double2 *gt)
+{
+    gtable_at(blockIdx.x * blockDim.x + threadIdx.x, gt);
+}
+
+// The per-call tables of a grid call in one launch: Delta^2 (with its
+// range), cos/sin of Q and the thermal table, in consecutive workgroup
+// ranges.
+__global__ __launch_bounds__(kBlock) void call_tables_kernel(const double *delta, int n_delta,
+                                                             int n_delta_pad, double *d2,
+                                                             const double *q, int n_q,
+                                                             double *qtrig, double2 *gt)
+{
+    const int nd = (n_delta_pad + kBlock - 1) / kBlock;
+    const int nqb = (n_q + kBlock - 1) / kBlock;
+    const int b = blockIdx.x;
+    if (b < nd)
+        delta2_block(b, delta, n_delta, n_delta_pad, d2);
+    else if (b < nd + nqb)
+        qtrig_at((b - nd) * kBlock + threadIdx.x, q, n_q, qtrig);
+    else
+        gtable_at((b - nd - nqb) * kBlock + threadIdx.x, gt);
+}
+
+hipError_t launch_call_tables(const double *delta, int n_delta, int n_delta_pad, double *d2,
+                              const double *q, int n_q, double *qtrig, double2 *gt,
+                              hipStream_t s)
+{
+    const int blocks = (n_delta_pad + kBlock - 1) / kBlock + (n_q + kBlock - 1) / kBlock +
+                       (kGTabN + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(call_tables_kernel, dim3(blocks), dim3(kBlock), 0, s, delta, n_delta,
+                       n_delta_pad, d2, q, n_q, qtrig, gt);
+    return hipGetLastError();
 }
 
 hipError_t launch_gtable(double2 *gtab, hipStream_t s)
@@ -593,9 +641,9 @@ hipError_t launch_etab(const Hop3 &h, const double *trig, int Lx, int Ly, double
 
 // Lattice index of each pair momentum: (m, n) with Q = (2 pi m/Lx, 2 pi n/Ly)
 // to within 1e-13 (m, n reduced into [0, L)), else (-1, -1).
-__global__ void qlat_kernel(const double *q, int n_q, int Lx, int Ly, int *qlat)
+__device__ __forceinline__ void qlat_at(int t, const double *q, int n_q, int Lx, int Ly,
+                                        int *qlat)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_q)
         return;
     int idx[2] = {-1, -1};
@@ -614,6 +662,35 @@ __global__ void qlat_kernel(const double *q, int n_q, int Lx, int Ly, int *qlat)
     }
     qlat[2 * t] = ok ? idx[0] : -1;
     qlat[2 * t + 1] = ok ? idx[1] : -1;
+}
+
+__global__ void qlat_kernel(const double *q, int n_q, int Lx, int Ly, int *qlat)
+{
+    qlat_at(blockIdx.x * blockDim.x + threadIdx.x, q, n_q, Lx, Ly, qlat);
+}
+
+// The per-lattice tables of a grid call in one launch: cos/sin of the
+// lattice momenta and the lattice index of each Q.
+__global__ __launch_bounds__(kBlock) void group_tables_kernel(int Lx, int Ly, double *trig,
+                                                              const double *q, int n_q,
+                                                              int *qlat)
+{
+    const int nl = Lx > Ly ? Lx : Ly;
+    const int nt = (nl + kBlock - 1) / kBlock;
+    if ((int)blockIdx.x < nt)
+        trig_at(blockIdx.x * kBlock + threadIdx.x, Lx, Ly, trig);
+    else
+        qlat_at((blockIdx.x - nt) * kBlock + threadIdx.x, q, n_q, Lx, Ly, qlat);
+}
+
+hipError_t launch_group_tables(int Lx, int Ly, double *trig, const double *q, int n_q,
+                               int *qlat, hipStream_t s)
+{
+    const int nl = Lx > Ly ? Lx : Ly;
+    const int blocks = (nl + kBlock - 1) / kBlock + (n_q + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(group_tables_kernel, dim3(blocks), dim3(kBlock), 0, s, Lx, Ly, trig, q,
+                       n_q, qlat);
+    return hipGetLastError();
 }
 
 hipError_t launch_qlat(const double *q, int n_q, int Lx, int Ly, int *qlat, hipStream_t s)
