@@ -213,7 +213,7 @@ struct GridPlan {
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, off_queue, sweep_bytes;
+        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, off_queue, off_rowmin, sweep_bytes;
 };
 
 // b3: three-band model.  The band table of the largest lattice holds 3 bands
@@ -266,7 +266,9 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_etab = p.off_tpart + align_up(tpart);
     p.off_qlat = p.off_etab + align_up(etab);
     p.off_queue = p.off_qlat + align_up(sizeof(int) * 2 * (size_t)n_q);
-    p.sweep_bytes = p.off_queue + align_up(sizeof(unsigned long long) * kQueues * kQueueStride);
+    p.off_rowmin = p.off_queue + align_up(sizeof(unsigned long long) * kQueues * kQueueStride);
+    // the minimum of every output row, for the global search
+    p.sweep_bytes = p.off_rowmin + align_up(sizeof(double) * (size_t)n_pts * p.nbq);
     return p;
 }
 
@@ -444,6 +446,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     r.mpart = mom;
     r.d2c = d2 + P.n_delta_pad;
     r.zero_d0 = precision == OMEGA_FP64 ? 0 : 1;
+    r.rowmin = (double *)(ws + P.off_rowmin);
     r.d2 = d2;
     r.td = P.td;
     r.n_dtiles = P.n_dtiles;
@@ -527,7 +530,8 @@ int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const dou
     if (!(tie_rel >= 0.0) || !isfinite(tie_rel))
         return OMEGA_E_INVAL;
     const int nb = md.nb;
-    const size_t sweep = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3).sweep_bytes;
+    const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3);
+    const size_t sweep = P.sweep_bytes;
     const size_t need = sweep + (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
     if (ws_bytes < need)
         return OMEGA_E_WORKSPACE;
@@ -539,6 +543,7 @@ int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const dou
         return rc;
     ArgminArgs a;
     a.omega = grid;
+    a.rowmin = (const double *)((const char *)ws_dev + P.off_rowmin);
     a.n_q = n_q;
     a.n_delta = n_delta;
     a.tie_rel = tie_rel;

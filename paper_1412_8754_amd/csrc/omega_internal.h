@@ -210,10 +210,12 @@ struct RowArgs {
     int n_chunks, n_delta, n_delta_pad, n_q, nbq;
     double *omega;         // [n_pts][nbq][n_delta] (all points of the call)
     int32_t *row_idx;      // [n_pts][nbq], or nullptr
+    double *rowmin;        // [n_pts][nbq] minimum of each row (NaN ignored)
 };
 
 struct ArgminArgs {
     const double *omega;   // [n_set][n_q][n_delta]
+    const double *rowmin;  // [n_set][n_q] minimum of each row (rows_kernel)
     int n_q, n_delta;
     double tie_rel;
     int32_t *idx;          // [n_set][2]

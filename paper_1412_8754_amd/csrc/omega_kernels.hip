@@ -2058,9 +2058,11 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
             best = nan_min(best, om);
         }
     }
+    best = block_nan_min(best, shd);
+    if (threadIdx.x == 0)
+        r.rowmin[orow] = best;
     if (!r.row_idx)
         return;
-    best = block_nan_min(best, shd);
     int pick = 0x7fffffff;
     if (best == best) {
         const double thr = tie_threshold(best, r.tie_rel);
@@ -2087,52 +2089,61 @@ hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s)
 
 // One workgroup per (point, band) set: global search of Algorithm 1 with the
 // tie rule (lexicographically smallest (iDelta, iq) within the tie band).
+// The global minimum is the minimum of the row minima rows_kernel stored;
+// only rows whose minimum lies within the tie band can hold the pick.  The
+// first 256 keys (key = iDelta n_q + iq) are checked at once, which settles
+// the common tie of the Delta = 0 row over lattice Q; otherwise each wave
+// scans its rows within the tie band 64 Delta at a time from the start, the
+// first Delta at or below the threshold giving the row's smallest key.
 __global__ __launch_bounds__(kBlock) void argmin_kernel(const ArgminArgs a)
 {
     const size_t set = blockIdx.x;
     const int n = a.n_q * a.n_delta;
     const double *g = a.omega + set * (size_t)n;
+    const double *rm = a.rowmin + set * (size_t)a.n_q;
     __shared__ double shd[4];
     __shared__ int shi[4];
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
-    // both passes load kAhead values per thread before using them
     double best = nan;
-    for (int t0 = threadIdx.x; t0 < n; t0 += kBlock * kAhead) {
-        double v[kAhead];
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u)
-            v[u] = t0 + u * kBlock < n ? g[t0 + u * kBlock] : nan;
-#pragma unroll
-        for (int u = 0; u < kAhead; ++u)
-            best = nan_min(best, v[u]);
-    }
+    for (int iq = threadIdx.x; iq < a.n_q; iq += kBlock)
+        best = nan_min(best, rm[iq]);
     best = block_nan_min(best, shd);
     int key = 0x7fffffff;
     if (best == best) {
         const double thr = tie_threshold(best, a.tie_rel);
-        for (int t0 = threadIdx.x; t0 < n; t0 += kBlock * kAhead) {
-            double v[kAhead];
-#pragma unroll
-            for (int u = 0; u < kAhead; ++u)
-                v[u] = t0 + u * kBlock < n ? g[t0 + u * kBlock] : nan;
-#pragma unroll
-            for (int u = 0; u < kAhead; ++u) {
-                if (v[u] <= thr) {
-                    const int t = t0 + u * kBlock;
-                    const int iq = t / a.n_delta;
-                    const int id = t - iq * a.n_delta;
-                    const int k = id * a.n_q + iq;
-                    key = k < key ? k : key;
+        const int k = (int)threadIdx.x;
+        bool hit = false;
+        if (k < n) {
+            const int id = k / a.n_q;
+            const int iq = k - id * a.n_q;
+            hit = rm[iq] <= thr && g[(size_t)iq * a.n_delta + id] <= thr;
+        }
+        key = block_int_min(hit ? k : 0x7fffffff, shi);
+        if (key == 0x7fffffff) {
+            const int lane = threadIdx.x & 63;
+            const int wave = threadIdx.x >> 6;
+            for (int iq = wave; iq < a.n_q; iq += kBlock / 64) {
+                if (!(rm[iq] <= thr))
+                    continue;
+                for (int d0 = 0; d0 < a.n_delta; d0 += 64) {
+                    const int id = d0 + lane;
+                    const bool h = id < a.n_delta && g[(size_t)iq * a.n_delta + id] <= thr;
+                    const unsigned long long b = __ballot(h);
+                    if (b != 0ull) {
+                        const int kk = (d0 + __builtin_ctzll(b)) * a.n_q + iq;
+                        key = kk < key ? kk : key;
+                        break;
+                    }
                 }
             }
+            key = block_int_min(key, shi);
         }
     }
-    key = block_int_min(key, shi);
     if (threadIdx.x == 0) {
         if (key == 0x7fffffff) {
             a.idx[2 * set] = -1;
             a.idx[2 * set + 1] = -1;
-            a.omin[set] = __longlong_as_double(0x7ff8000000000000LL);
+            a.omin[set] = nan;
         } else {
             const int id = key / a.n_q;
             const int iq = key - id * a.n_q;
