@@ -305,9 +305,9 @@ def differentiation(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
-              "supported (the work shards by independent (point, band, Q) units; see "
-              "the design notes)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the work would shard by independent (point, band, Q) units)",
+              file=sys.stderr)
         return 2
     if args.workload == "phase":
         return phase_diagram(args)

@@ -82,7 +82,7 @@ enum {
     OMEGA_E_INVAL = -1,       /* an argument is out of range or NULL        */
     OMEGA_E_WORKSPACE = -2,   /* ws_bytes smaller than required             */
     OMEGA_E_HIP = -3,         /* a HIP runtime call or launch failed        */
-    OMEGA_E_UNSUPPORTED = -4  /* valid request this build does not provide  */
+    OMEGA_E_UNSUPPORTED = -4  /* valid request the library does not provide */
 };
 
 /* Bytes of device workspace that omega_grid / omega_argmin (grad = 0) or
