@@ -201,6 +201,36 @@ __device__ __forceinline__ double ordered_sum(const double *p, size_t stride, in
     return s + c;
 }
 
+// Two chains of ordered_sum in one loop, each with exactly its arithmetic,
+// so that the loads of both are in flight together; a null p1 or p2 leaves
+// its sum at 0.
+__device__ __forceinline__ void ordered_sum2(const double *p1, size_t stride1,
+                                             const double *p2, size_t stride2, int n,
+                                             double &sum1, double &sum2)
+{
+    double s1 = 0.0, c1 = 0.0, s2 = 0.0, c2 = 0.0;
+    int k = 0;
+    for (; k + kAhead <= n; k += kAhead) {
+        double v1[kAhead], v2[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            v1[u] = p1 ? p1[(size_t)(k + u) * stride1] : 0.0;
+            v2[u] = p2 ? p2[(size_t)(k + u) * stride2] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            neumaier(s1, c1, v1[u]);
+            neumaier(s2, c2, v2[u]);
+        }
+    }
+    for (; k < n; ++k) {
+        neumaier(s1, c1, p1 ? p1[(size_t)k * stride1] : 0.0);
+        neumaier(s2, c2, p2 ? p2[(size_t)k * stride2] : 0.0);
+    }
+    sum1 = s1 + c1;
+    sum2 = s2 + c2;
+}
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -1983,60 +2013,81 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
     const int iq = bq - slot * r.n_q;
     const size_t row = (size_t)g * r.nbq + bq;       // partial row of the batch
     const size_t orow = (size_t)r.pts[g].out * r.nbq + bq;  // output row
+    const int t = threadIdx.x;
     __shared__ double sh_base;
     __shared__ double shd[4];
     __shared__ int shi[4];
     __shared__ double sh_mom[kMomentSlots];   // C0, c_n M_n
-    if (threadIdx.x == kMomentSlots)
-        sh_base = ordered_sum(r.base_part + row * r.n_chunks, 1, r.n_chunks);
-    if (threadIdx.x < kMomentSlots) {
-        // fixed-order chunk sum of one moment (positive terms)
-        const double m = ordered_sum(r.mpart + row * r.n_chunks * kMomentSlots + threadIdx.x,
-                                     kMomentSlots, r.n_chunks);
-        // times binomial(1/2, n) (c_0 = 1: C0 as it is)
-        sh_mom[threadIdx.x] = threadIdx.x == 0 ? m : kHalfBinomial.c[threadIdx.x] * m;
-    }
-    __syncthreads();
-    const double base = sh_base;
+    // tile series of the queued sweep, per Delta tile: c_n times the
+    // fixed-order chunk sums of its moments, and the tile centre, a batch of
+    // kTileBatch tiles at a time
+    __shared__ double sh_tm[kTileBatch][kTileSlots];
+    __shared__ double sh_tc[kTileBatch];
     const double x0 = *r.d2c;
     // 0 * q is 0 for finite q and NaN for NaN q: a NaN momentum poisons the row
     const double qpoison = 0.0 * r.q[2 * iq] + 0.0 * r.q[2 * iq + 1];
     const double V = r.Vs[slot];
     double *out = r.omega + orow * r.n_delta;
     const double *pp = r.part + row * r.n_chunks * r.n_delta_pad;
-
-    // tile series of the queued sweep, per Delta tile: c_n times the
-    // fixed-order chunk sums of its moments, and the tile centre, a batch of
-    // kTileBatch tiles at a time
-    __shared__ double sh_tm[kTileBatch][kTileSlots];
-    __shared__ double sh_tc[kTileBatch];
+    const double *mp = r.mpart + row * r.n_chunks * kMomentSlots;
     double best = __longlong_as_double(0x7ff8000000000000LL);
     for (int b0 = 0; b0 < r.n_dtiles; b0 += kTileBatch) {
         const int nbt = min(kTileBatch, r.n_dtiles - b0);
+        const int id_end = min(r.n_delta, (b0 + nbt) * r.td);
+        const int id0 = b0 * r.td + t;   // this thread's first Delta of the batch
+        // Every thread sums the chunks of its first Delta together with one
+        // other fixed-order chunk sum: in the first batch the series moments
+        // and the base term, then the tile moments of the batch.
+        const int nfix = b0 == 0 ? kMomentSlots + 1 : 0;
+        const int ntm = r.tpart ? nbt * kTileSlots : 0;
+        const double *p2 = nullptr;
+        size_t s2 = 0;
+        if (t < nfix) {
+            p2 = t < kMomentSlots ? mp + t : r.base_part + row * r.n_chunks;
+            s2 = t < kMomentSlots ? kMomentSlots : 1;
+        } else if (t - nfix < ntm) {
+            const int u = t - nfix;
+            p2 = r.tpart + (row * r.n_chunks * r.n_dtiles + b0 + u / kTileSlots) * kTileSlots +
+                 u % kTileSlots;
+            s2 = (size_t)r.n_dtiles * kTileSlots;
+        }
+        double sp0 = 0.0, v2 = 0.0;
+        ordered_sum2(id0 < id_end ? pp + id0 : nullptr, r.n_delta_pad, p2, s2, r.n_chunks, sp0,
+                     v2);
+        if (t < nfix) {
+            // moments are positive terms; times binomial(1/2, n) (c_0 = 1: C0 as it is)
+            if (t < kMomentSlots)
+                sh_mom[t] = t == 0 ? v2 : kHalfBinomial.c[t] * v2;
+            else
+                sh_base = v2;
+        } else if (t - nfix < ntm) {
+            const int u = t - nfix;
+            sh_tm[u / kTileSlots][u % kTileSlots] = kHalfBinomial.c[u % kTileSlots] * v2;
+        }
+        // tile moments beyond one per thread
+        for (int u = kBlock - nfix + t; u < ntm; u += kBlock) {
+            const double m =
+                ordered_sum(r.tpart + (row * r.n_chunks * r.n_dtiles + b0 + u / kTileSlots) *
+                                          kTileSlots + u % kTileSlots,
+                            (size_t)r.n_dtiles * kTileSlots, r.n_chunks);
+            sh_tm[u / kTileSlots][u % kTileSlots] = kHalfBinomial.c[u % kTileSlots] * m;
+        }
         if (r.tpart) {
-            __syncthreads();
-            for (int u = threadIdx.x; u < nbt * kTileSlots; u += kBlock) {
-                const int dt = b0 + u / kTileSlots, n = u % kTileSlots;
-                const double m =
-                    ordered_sum(r.tpart + (row * r.n_chunks * r.n_dtiles + dt) * kTileSlots + n,
-                                (size_t)r.n_dtiles * kTileSlots, r.n_chunks);
-                sh_tm[u / kTileSlots][n] = kHalfBinomial.c[n] * m;
-            }
-            for (int u = threadIdx.x; u < nbt; u += kBlock) {
+            for (int u = t; u < nbt; u += kBlock) {
                 // same arithmetic as the sweep's tile range
                 const double *dt2 = r.d2 + (size_t)(b0 + u) * r.td;
                 double lo = dt2[0], hi = dt2[0];
-                for (int t = 1; t < r.td; ++t) {
-                    lo = fmin(lo, dt2[t]);
-                    hi = fmax(hi, dt2[t]);
+                for (int k = 1; k < r.td; ++k) {
+                    lo = fmin(lo, dt2[k]);
+                    hi = fmax(hi, dt2[k]);
                 }
                 sh_tc[u] = 0.5 * (lo + hi);
             }
-            __syncthreads();
         }
-        const int id_end = min(r.n_delta, (b0 + nbt) * r.td);
-        for (int id = b0 * r.td + threadIdx.x; id < id_end; id += kBlock) {
-            const double sp = ordered_sum(pp + id, r.n_delta_pad, r.n_chunks);
+        __syncthreads();
+        const double base = sh_base;
+        for (int id = id0; id < id_end; id += kBlock) {
+            const double sp = id == id0 ? sp0 : ordered_sum(pp + id, r.n_delta_pad, r.n_chunks);
             const double D = r.delta[id];
             // series part: C0 + sum_n c_n M_n (Delta^2 - x0)^n by Horner
             const double x = D * D - x0;
@@ -2057,9 +2108,11 @@ __global__ __launch_bounds__(kBlock) void rows_kernel(const RowArgs r)
             out[id] = om;
             best = nan_min(best, om);
         }
+        // the next batch rewrites the shared tables
+        __syncthreads();
     }
     best = block_nan_min(best, shd);
-    if (threadIdx.x == 0)
+    if (t == 0)
         r.rowmin[orow] = best;
     if (!r.row_idx)
         return;
