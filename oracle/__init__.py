@@ -31,7 +31,13 @@ BAND_BOTH = 3
 class Model(ctypes.Structure):
     _fields_ = [("t1", ctypes.c_double), ("t2", ctypes.c_double),
                 ("t3", ctypes.c_double), ("t4", ctypes.c_double),
-                ("mu", ctypes.c_double), ("V", ctypes.c_double * 2)]
+                ("mu", ctypes.c_double), ("V", ctypes.c_double * 2),
+                ("form", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+# form factor of the pair (k up, -k+q down): eta(k) on the spin-up momentum
+# (Sec. 2, Eq. (3)) or eta(k - q/2) at the pair's relative momentum
+ETA_K, ETA_REL = 0, 1
 
 
 class Point(ctypes.Structure):
@@ -87,6 +93,7 @@ def lib():
         L.oracle_omega_row_tab.restype = ctypes.c_int
         L.oracle_omega_row_tab.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                            dp, ctypes.c_int, dp]
         L.oracle_pair_chi_tab.restype = ctypes.c_int
         L.oracle_pair_chi_tab.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -106,7 +113,7 @@ def _model(m) -> Model:
     if isinstance(m, Model):
         return m
     return Model(m["t1"], m["t2"], m["t3"], m["t4"], m["mu"],
-                 (ctypes.c_double * 2)(*m["V"]))
+                 (ctypes.c_double * 2)(*m["V"]), int(m.get("form", ETA_K)), 0)
 
 
 def _points(pts):

@@ -16,7 +16,11 @@
  *     sigma = +1 for spin up: Sec. 2, Eq. (1) and the text under it;
  *   - quasiparticle energies: Sec. 2, Eq. (4), pairing (k up, -k+q down) with
  *     Delta_k = Delta * eta(k), eta(k) = cos kx cos ky (s+- form factor of the
- *     introduction);
+ *     introduction; Sec. 2, Eq. (3) attaches it to the spin-up momentum k).
+ *     As a model option the form factor is taken at the pair's relative
+ *     momentum instead, eta(k - q/2) = cos(kx - qx/2) cos(ky - qy/2), the
+ *     momentum of each partner measured from the pair's centre of mass;
+ *     at q = 0 the two coincide;
  *   - free energy per band: Sec. 2, Eq. (5);
  *   - search: Sec. 3.2, Algorithm 1 (for each q: build the two band-energy
  *     arrays over the Brillouin zone, then for each Delta evaluate Eq. (4) and
@@ -54,7 +58,12 @@ typedef struct {
     double t1, t2, t3, t4; /* hoppings of App. A, energy unit |t1| */
     double mu;             /* chemical potential */
     double V[2];           /* pairing strength for band 0 (E_-) and band 1 (E_+) */
+    int32_t form;          /* OR_ETA_K: eta(k); OR_ETA_REL: eta(k - q/2) */
+    int32_t pad;
 } or_model;
+
+#define OR_ETA_K 0
+#define OR_ETA_REL 1
 
 typedef struct {
     double h, T;      /* Zeeman field, temperature (k_B = 1) */
@@ -89,6 +98,15 @@ static double softplus_term(double E, double T)
     if (T == 0.0)
         return lo;
     return lo - T * log1p(exp(-fabs(E) / T));
+}
+
+/* s+- form factor of the pair (k up, -k+q down): eta(k) = cos kx cos ky on
+ * the spin-up momentum, or eta(k - q/2) at the relative momentum. */
+static double form_factor(int form, double kx, double ky, double qx, double qy)
+{
+    if (form == OR_ETA_REL)
+        return cos(kx - 0.5 * qx) * cos(ky - 0.5 * qy);
+    return cos(kx) * cos(ky);
 }
 
 /* Fermi function f(E) = 1 / (1 + exp(E/T)); T = 0 gives the step (1/2 at 0). */
@@ -153,7 +171,7 @@ void oracle_band_grad(const or_model *m, int band, double kx, double ky,
 
 static int check_model(const or_model *m)
 {
-    if (!m)
+    if (!m || (m->form != OR_ETA_K && m->form != OR_ETA_REL))
         return OR_EINVAL;
     const double *v = &m->t1;
     for (int i = 0; i < 7; ++i)
@@ -239,7 +257,7 @@ static void omega_row(const or_model *m, const or_point *p, int band,
             e_up[k] = Ek - (mu + h);   /* sigma = +1 */
             e_dn[k] = Eqk - (mu - h);  /* sigma = -1 at -k+q */
             e_kd[k] = Ek - (mu - h);   /* sigma = -1 at k */
-            eta[k] = cos(kx) * cos(ky);
+            eta[k] = form_factor(m->form, kx, ky, qx, qy);
         }
     }
 
@@ -278,13 +296,16 @@ int oracle_omega_grid(const or_model *m, const or_point *pts, int n_pts,
 /* Eq. (4)-(5) for one band, one q and one point from tabulated band
  * energies (the paper's recipe for models whose bands are found numerically,
  * Sec. 3.2, e.g. the three-band model of App. B): ek[i*Ly + j] = E_eps(k) and
- * eqk[i*Ly + j] = E_eps(q - k) at kx = 2 pi i / Lx, ky = 2 pi j / Ly.
+ * eqk[i*Ly + j] = E_eps(q - k) at kx = 2 pi i / Lx, ky = 2 pi j / Ly;
+ * (qx, qy) = q and form (OR_ETA_K or OR_ETA_REL) fix the form factor.
  * out[id] = Omega_eps(delta[id], q).  T >= 0, V != 0. */
 int oracle_omega_row_tab(const double *ek, const double *eqk, int Lx, int Ly,
-                         double mu, double h, double T, double V,
-                         const double *delta, int n_delta, double *out)
+                         double mu, double h, double T, double V, double qx, double qy,
+                         int form, const double *delta, int n_delta, double *out)
 {
     if (!ek || !eqk || !delta || !out || Lx < 2 || Ly < 2 || n_delta <= 0)
+        return OR_EINVAL;
+    if (form != OR_ETA_K && form != OR_ETA_REL)
         return OR_EINVAL;
     if (!isfinite(mu) || !isfinite(h) || !isfinite(T) || T < 0.0 || V == 0.0 ||
         !isfinite(V))
@@ -302,7 +323,7 @@ int oracle_omega_row_tab(const double *ek, const double *eqk, int Lx, int Ly,
             e_up[k] = ek[k] - (mu + h);
             e_dn[k] = eqk[k] - (mu - h);
             e_kd[k] = ek[k] - (mu - h);
-            eta[k] = cos(kx) * cos(ky);
+            eta[k] = form_factor(form, kx, ky, qx, qy);
         }
     }
     eq5_sum(N, e_up, e_dn, e_kd, eta, V, T, delta, n_delta, out);
@@ -497,7 +518,9 @@ int oracle_omega_argmin(const or_model *m, const or_point *pts, int n_pts,
  *   dE+-/dDelta = +- Delta eta^2 / R;
  *   dE+-/dq     = (dE_{q-k}/dq) (-1 +- s/R) / 2;
  *   dE+-/dmu    = -+ s / R, and the literal Sum_k E_{k down} adds -N;
- *   d(-2 N Delta^2 / V)/dDelta = -4 N Delta / V.
+ *   d(-2 N Delta^2 / V)/dDelta = -4 N Delta / V;
+ *   with eta(k - q/2), also dE+-/dq = +- (Delta^2 eta / R) deta/dq, with
+ *   deta/dqx = sin(kx - qx/2) cos(ky - qy/2) / 2 (likewise qy).
  * R = 0 is given s/R = 0 and Delta eta^2 / R = 0. */
 static void grad_one(const or_model *m, const or_point *p, int band, double D,
                      double qx, double qy, double *om, double *gD, double *gqx,
@@ -516,7 +539,7 @@ static void grad_one(const or_model *m, const or_point *p, int band, double D,
             double bx, by;
             oracle_band_grad(m, band, qx - kx, qy - ky, &bx, &by);
             double a = Ek - (mu + h), b = Eqk - (mu - h);
-            double eta = cos(kx) * cos(ky);
+            double eta = form_factor(m->form, kx, ky, qx, qy);
             double gap = D * eta;
             double s = 0.5 * (a + b), d = 0.5 * (a - b);
             double R = sqrt(s * s + gap * gap);
@@ -529,8 +552,14 @@ static void grad_one(const or_model *m, const or_point *p, int band, double D,
             nadd(&so, Ek - (mu - h));
             nadd(&sd, dr * (fp - fm));
             double w = 0.5 * fp * (sr - 1.0) - 0.5 * fm * (sr + 1.0);
-            nadd(&sx, bx * w);
-            nadd(&sy, by * w);
+            double ex = 0.0, ey = 0.0;   /* form-factor part of dOmega/dq */
+            if (m->form == OR_ETA_REL && R > 0.0) {
+                double ge = D * gap / R * (fp - fm);    /* dOmega_k / d eta */
+                ex = ge * 0.5 * sin(kx - 0.5 * qx) * cos(ky - 0.5 * qy);
+                ey = ge * 0.5 * cos(kx - 0.5 * qx) * sin(ky - 0.5 * qy);
+            }
+            nadd(&sx, bx * w + ex);
+            nadd(&sy, by * w + ey);
             nadd(&sm, sr * (fm - fp));
         }
     }

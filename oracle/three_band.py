@@ -9,7 +9,8 @@ the table-driven C routine ``oracle_omega_row_tab``; E_eps(q - k) is
 diagonalised at q - k itself (no lattice shift).
 
 Model: dict with "t" (t1..t12, eV), "eps0" (on-site energy of d_xy), "mu",
-"V" (three couplings, one per band; V < 0 attractive).
+"V" (three couplings, one per band; V < 0 attractive), and optionally "form"
+(the form factor: 0 = eta(k), 1 = eta(k - q/2); see the two-band oracle).
 """
 from __future__ import annotations
 
@@ -95,8 +96,9 @@ def omega_grid(model, pts, delta, q, bands_mask: int = BAND_ALL) -> np.ndarray:
                 row = np.empty(d.size, np.float64)
                 _check(L.oracle_omega_row_tab(_dp(a), _dp(c), int(Lx), int(Ly),
                                               float(model["mu"]), float(h), float(T),
-                                              float(model["V"][b]), _dp(d), d.size,
-                                              _dp(row)))
+                                              float(model["V"][b]), float(qq[iq, 0]),
+                                              float(qq[iq, 1]), int(model.get("form", 0)),
+                                              _dp(d), d.size, _dp(row)))
                 out[p, ib, iq] = row
     return out
 

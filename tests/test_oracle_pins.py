@@ -43,13 +43,15 @@ def kgrid(Lx, Ly):
     return np.meshgrid(kx, ky, indexing="ij")
 
 
-def fock_free_energy(band, h, T, Lx, Ly, D, qx, qy, mu=M["mu"], V=M["V"]):
+def fock_free_energy(band, h, T, Lx, Ly, D, qx, qy, mu=M["mu"], V=M["V"], relative=False):
     """-T ln Tr exp(-H/T) summed over pair sectors (k up, -k+q down).
 
     Per sector the pair Hamiltonian of Eq. (3) plus the kinetic terms acts on
     {|0>, |up>, |down>, |up down>} as
         [[0, 0, 0, g], [0, a, 0, 0], [0, 0, b, 0], [g, 0, 0, a + b]]
-    with a = E(k) - mu - h, b = E(q - k) - mu + h and g = Delta cos kx cos ky.
+    with a = E(k) - mu - h, b = E(q - k) - mu + h and g = Delta cos kx cos ky
+    (relative: g = Delta eta at the pair's relative momentum (k - (q - k))/2 =
+    k - q/2, i.e. Delta cos(kx - qx/2) cos(ky - qy/2)).
     It is diagonalised numerically, not by Eq. (4).  The constant
     -2 Delta^2 / V per momentum of Eq. (5) is added at the end."""
     KX, KY = kgrid(Lx, Ly)
@@ -57,7 +59,12 @@ def fock_free_energy(band, h, T, Lx, Ly, D, qx, qy, mu=M["mu"], V=M["V"]):
     Eq = bands_eigh(qx - KX, qy - KY)[..., band]
     a = Ek - mu - h
     b = Eq - mu + h
-    g = D * np.cos(KX) * np.cos(KY)
+    if relative:
+        # relative momentum of the partners k and q - k
+        rx, ry = (KX - (qx - KX)) / 2, (KY - (qy - KY)) / 2
+        g = D * np.cos(rx) * np.cos(ry)
+    else:
+        g = D * np.cos(KX) * np.cos(KY)
     H = np.zeros(KX.shape + (4, 4))
     H[..., 0, 3] = H[..., 3, 0] = g
     H[..., 1, 1] = a
@@ -121,6 +128,55 @@ def test_whole_free_energy_equals_fock_space_brute_force(seed):
             ref = fock_free_energy(band, h, T, Lx, Ly, D, qx, qy)
             got = grid[0, bi, 0, di]
             assert got == pytest.approx(ref, rel=1e-12, abs=1e-12 * Lx * Ly)
+
+
+MR = dict(M, form=oracle.ETA_REL)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_relative_form_factor_equals_fock_space_brute_force(seed):
+    # The model option eta(k - q/2): the same four-state brute force with the
+    # gap taken at the relative momentum of the pair, lattice q off the axes.
+    rng = np.random.default_rng(150 + seed)
+    Lx, Ly = [(6, 8), (10, 10), (8, 12), (12, 6)][seed]
+    h = rng.uniform(-0.3, 0.3)
+    T = [0.0, 0.01, 0.1, 0.003][seed]
+    mq, nq = rng.integers(1, Lx), rng.integers(1, Ly)
+    qx, qy = 2 * np.pi * mq / Lx, 2 * np.pi * nq / Ly
+    delta = np.array([0.0, 0.2, 0.6, 1.0])
+    grid = oracle.omega_grid(MR, [(h, T, Lx, Ly)], delta, [[qx, qy]], W.BAND_BOTH)
+    for bi, band in enumerate((0, 1)):
+        for di, D in enumerate(delta):
+            ref = fock_free_energy(band, h, T, Lx, Ly, D, qx, qy, relative=True)
+            got = grid[0, bi, 0, di]
+            assert got == pytest.approx(ref, rel=1e-12, abs=1e-12 * Lx * Ly)
+            if D > 0:
+                # and it differs from the spin-up form factor's value
+                other = fock_free_energy(band, h, T, Lx, Ly, D, qx, qy, relative=False)
+                assert abs(got - other) > 1e-6 * abs(other)
+
+
+def test_relative_form_factor_reduces_to_spin_up_one_at_zero_q():
+    pts = [(0.05, 0.01, 10, 8), (-0.1, 0.0, 9, 9)]
+    delta = np.linspace(0.0, 0.6, 7)
+    a = oracle.omega_grid(M, pts, delta, [[0.0, 0.0]], 3)
+    b = oracle.omega_grid(MR, pts, delta, [[0.0, 0.0]], 3)
+    assert np.array_equal(a, b)
+
+
+def test_relative_form_factor_zeeman_sign_symmetric_on_lattice_q():
+    # With the gap at the relative momentum the pair (k up, q - k down) maps
+    # onto (q - k up, k down) under k -> q - k, so flipping h leaves Omega
+    # unchanged for every lattice q; the spin-up form factor breaks this.
+    L, T = 12, 0.01
+    delta = np.array([0.1, 0.3])
+    q = [[2 * np.pi * 3 / L, 0.0], [2 * np.pi * 2 / L, 2 * np.pi * 5 / L]]
+    gp = oracle.omega_grid(MR, [(0.1, T, L, L)], delta, q, 3)
+    gm = oracle.omega_grid(MR, [(-0.1, T, L, L)], delta, q, 3)
+    np.testing.assert_allclose(gp, gm, rtol=1e-13)
+    hp = oracle.omega_grid(M, [(0.1, T, L, L)], delta, q, 3)
+    hm = oracle.omega_grid(M, [(-0.1, T, L, L)], delta, q, 3)
+    assert np.max(np.abs(hp - hm)) > 1e-6
 
 
 def test_normal_state_is_free_fermion_grand_potential():
@@ -211,8 +267,10 @@ def test_filling_two_electrons_per_site_at_printed_mu():
 
 # ------------------------------------------------------------- derivatives
 
+@pytest.mark.parametrize("form", [oracle.ETA_K, oracle.ETA_REL])
 @pytest.mark.parametrize("seed", range(4))
-def test_gradients_match_central_differences(seed):
+def test_gradients_match_central_differences(seed, form):
+    M = dict(globals()["M"], form=form)
     rng = np.random.default_rng(300 + seed)
     L = [10, 16, 12, 9][seed]
     h = rng.uniform(-0.2, 0.2)

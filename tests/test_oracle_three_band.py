@@ -74,13 +74,17 @@ def test_band_symmetries():
         np.testing.assert_allclose(other, E, rtol=0, atol=1e-13)
 
 
-def fock_free_energy3(band, h, T, Lx, Ly, D, qx, qy):
+def fock_free_energy3(band, h, T, Lx, Ly, D, qx, qy, relative=False):
     """-T ln Tr exp(-H/T) over pair sectors (k up, -k+q down), four-state
-    Fock space per sector, with App. B band energies; plus -2 Delta^2 / V."""
+    Fock space per sector, with App. B band energies; plus -2 Delta^2 / V.
+    relative: the gap at the pair's relative momentum (k - (q - k))/2."""
     KX, KY = kgrid(Lx, Ly)
     a = tb.bands(M3, KX, KY)[..., band] - M3["mu"] - h
     b = tb.bands(M3, qx - KX, qy - KY)[..., band] - M3["mu"] + h
-    g = D * np.cos(KX) * np.cos(KY)
+    if relative:
+        g = D * np.cos((2 * KX - qx) / 2) * np.cos((2 * KY - qy) / 2)
+    else:
+        g = D * np.cos(KX) * np.cos(KY)
     H = np.zeros(KX.shape + (4, 4))
     H[..., 0, 3] = H[..., 3, 0] = g
     H[..., 1, 1] = a
@@ -105,6 +109,22 @@ def test_three_band_free_energy_equals_fock_space_brute_force(seed):
     for band in range(3):
         for di, D in enumerate(delta):
             ref = fock_free_energy3(band, h, T, Lx, Ly, D, qx, qy)
+            assert grid[0, band, 0, di] == pytest.approx(ref, rel=1e-12, abs=1e-13 * Lx * Ly)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_three_band_relative_form_factor_equals_fock_space_brute_force(seed):
+    rng = np.random.default_rng(310 + seed)
+    Lx, Ly = [(8, 6), (10, 10)][seed]
+    h = rng.uniform(-0.03, 0.03)
+    T = [0.001, 0.02][seed]
+    qx, qy = 2 * np.pi * rng.integers(1, Lx) / Lx, 2 * np.pi * rng.integers(1, Ly) / Ly
+    delta = np.array([0.0, 0.03, 0.1])
+    grid = tb.omega_grid(dict(M3, form=oracle.ETA_REL), [(h, T, Lx, Ly)], delta, [[qx, qy]],
+                         tb.BAND_ALL)
+    for band in range(3):
+        for di, D in enumerate(delta):
+            ref = fock_free_energy3(band, h, T, Lx, Ly, D, qx, qy, relative=True)
             assert grid[0, band, 0, di] == pytest.approx(ref, rel=1e-12, abs=1e-13 * Lx * Ly)
 
 
@@ -150,6 +170,11 @@ def test_row_tab_rejects_bad_inputs():
     d = np.zeros(1)
     out = np.zeros(1)
     assert L.oracle_omega_row_tab(oracle._dp(a), oracle._dp(a), 4, 4, 0.0, 0.0, -1.0, -1.0,
-                                  oracle._dp(d), 1, oracle._dp(out)) != 0
+                                  0.0, 0.0, 0, oracle._dp(d), 1, oracle._dp(out)) != 0
     assert L.oracle_omega_row_tab(oracle._dp(a), oracle._dp(a), 4, 4, 0.0, 0.0, 0.1, 0.0,
-                                  oracle._dp(d), 1, oracle._dp(out)) != 0
+                                  0.0, 0.0, 0, oracle._dp(d), 1, oracle._dp(out)) != 0
+    # no such form factor
+    assert L.oracle_omega_row_tab(oracle._dp(a), oracle._dp(a), 4, 4, 0.0, 0.0, 0.1, -1.0,
+                                  0.0, 0.0, 2, oracle._dp(d), 1, oracle._dp(out)) != 0
+    assert L.oracle_omega_row_tab(oracle._dp(a), oracle._dp(a), 4, 4, 0.0, 0.0, 0.1, -1.0,
+                                  0.0, 0.0, 1, oracle._dp(d), 1, oracle._dp(out)) == 0
