@@ -26,22 +26,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic operations of one evaluation of Eq. (4)-(5), with the (k, Q)
-# quantities hoisted as Algorithm 1 does (band energies generated per q):
-#   |Delta_k|^2 = Delta^2 eta^2 (1), s^2 + |Delta_k|^2 (1), sqrt (1),
-#   E+- = d +- R (2), -E/T (2), exp (2), 1 + exp (2), ln (2),
-#   sum of the two logs and the factor -T (2), accumulation over k (1).
-# Elementary functions count as one operation each.  The roofline counts the
-# terms the per-Delta sweep kernel evaluates directly (mirror-folded, and
-# without the terms whose Delta dependence is summed through the Delta^2
-# series), measured by the library's work counter.
-OPS_PER_EVAL = 16
+# quantities hoisted as Algorithm 1 does (band energies generated per q),
+# elementary functions one operation each: 1 square root, 2 exponentials,
+# 1 logarithm of the product (1 + u1)(1 + u2), and 10 arithmetic operations
+# (Delta^2 eta^2, + s^2, d + R, d - R, the two scalings by -1/T, forming
+# u1 + u2 + u1 u2 (2), the factor T, the accumulation over k).  The roofline
+# counts the terms the per-Delta sweep kernel evaluates directly
+# (mirror-folded, and without the terms whose Delta dependence is summed
+# through the Delta^2 series), measured by the library's work counter.
+OPS_PER_EVAL = 14
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 
-# HBM bytes per launch of the timed sweep kernel, from rocprofv3 FETCH_SIZE
-# (x2.0) and WRITE_SIZE (x1.0) passes, scaled by the same counters on a plain
-# 256 MiB device copy (profiles/sweep_f64_paper_L1024.md).  Valid for the
-# kernel build those counters were taken on; None for other workloads.
-TRAFFIC_BYTES = {("paper", "fp64"): (13616 * 2 + 26720) * 1024}
+# Hardware counters of the timed sweep kernel at the paper-scale workload,
+# from rocprofv3 runs of this script (the profile file named in "source"),
+# valid for the kernel build named there.  %VALU = (2 FMA + ADD + MUL +
+# TRANS) FP64 VALU instructions x 64 lanes / kernel time / FP64 peak.
+# traffic: HBM bytes per launch from FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0),
+# each scaled by the same counter on a plain 256 MiB device copy.
+COUNTERS = {("paper", "fp64"): {
+    "source": "profiles/sweep_f64_paper_L1024.md",
+    "kernel_us": 1275.9, "valu_busy": [0.672, 0.700], "valu_utilization": 0.8487,
+    "fma_f64": 1.498e8, "add_f64": 3.248e7, "mul_f64": 9.436e7, "trans_f64": 1.454e7,
+    "wait_frac": 4.42e8 / 1.75e9, "traffic": (13616 * 2 + 26720) * 1024}}
+
+
+def counter_valu_frac(c):
+    """%VALU of the survey's definition from one counter record."""
+    ops = (2 * c["fma_f64"] + c["add_f64"] + c["mul_f64"] + c["trans_f64"]) * 64
+    return ops / (c["kernel_us"] * 1e-6) / (PEAK_TFLOPS["f64"] * 1e12)
 
 
 def sweep_kernel_name(precision, three, T):
@@ -51,6 +63,24 @@ def sweep_kernel_name(precision, three, T):
     if precision == "fp32c" and T >= 0.005:
         return f"sweep_f32c_hot_kernel<32, {b3}>"
     return f"sweep_kernel<32, {b3}, {'true' if precision == 'fp32c' else 'false'}>"
+
+
+def roofline_record(workload, precision, achieved, peak, three, T, sweep_ms, direct):
+    """Roofline of the dominant kernel: algorithmic operations of the terms it
+    evaluated (library counter) over its HIP-event time, plus the counter
+    figures of the same kernel from its profile."""
+    rec = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+           "frac": achieved / peak, "traffic": None,
+           "kernel": sweep_kernel_name(precision, three, T), "kernel_ms": sweep_ms,
+           "ops_per_eval": OPS_PER_EVAL, "units": direct}
+    c = COUNTERS.get((workload, precision))
+    if c is not None:
+        rec["traffic"] = c["traffic"]
+        rec["counters"] = {"source": c["source"], "valu_frac": counter_valu_frac(c),
+                           "valu_busy": c["valu_busy"],
+                           "valu_utilization": c["valu_utilization"],
+                           "wait_frac": c["wait_frac"], "kernel_us": c["kernel_us"]}
+    return rec
 
 
 def parse():
@@ -65,6 +95,14 @@ def parse():
                     help="Q rows per band in the CPU oracle sample")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP32-compensated comparison leg")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the default launch options (no autotuner)")
+    ap.add_argument("--no-lo", action="store_true",
+                    help="skip the LO-pairing record of the default line")
+    ap.add_argument("--no-phase", action="store_true",
+                    help="skip the phase-diagram record of the default line")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the L = 2048 precision record of the default line")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (HBM counter calibration)")
     return ap.parse_args()
@@ -85,10 +123,10 @@ def cpu_baseline(cfg, rows_per_band):
     t0 = time.perf_counter()
     if "model" in cfg:       # three-band model (App. B)
         from oracle import three_band
-        three_band.omega_grid(cfg["model"], pts, cfg["delta"], q[sel], cfg["bands"])
+        ref = three_band.omega_grid(cfg["model"], pts, cfg["delta"], q[sel], cfg["bands"])
         nb = len(three_band.band_list(cfg["bands"]))
     else:
-        oracle.omega_grid(W.DEFAULT_MODEL, pts, cfg["delta"], q[sel], cfg["bands"])
+        ref = oracle.omega_grid(W.DEFAULT_MODEL, pts, cfg["delta"], q[sel], cfg["bands"])
         nb = 2 if cfg["bands"] == 3 else 1
     dt = time.perf_counter() - t0
     n_k = pts[0][2] * pts[0][3]
@@ -107,13 +145,33 @@ def cpu_baseline(cfg, rows_per_band):
         oracle.set_threads(threads)
     evals1 = n_k * len(d1)
     evals = n_k * len(cfg["delta"]) * len(sel) * nb
-    return {"value": evals / dt, "unit": "evals/s", "cores": threads,
-            "kind": "oracle",
+    rec = {"value": evals / dt, "unit": "evals/s", "cores": threads,
+           "kind": "oracle",
             "sample": f"{nb} bands x {len(sel)} of {len(q)} Q rows x {len(cfg['delta'])} Delta "
                       f"at L={pts[0][2]} ({evals:.3e} evals, {dt:.1f} s)",
-            "single_thread": {"value": evals1 / dt1, "unit": "evals/s", "cores": 1,
-                              "sample": f"1 band x 1 Q row x {len(d1)} Delta at "
-                                        f"L={pts[0][2]} ({evals1:.3e} evals, {dt1:.1f} s)"}}
+           "single_thread": {"value": evals1 / dt1, "unit": "evals/s", "cores": 1,
+                             "sample": f"1 band x 1 Q row x {len(d1)} Delta at "
+                                       f"L={pts[0][2]} ({evals1:.3e} evals, {dt1:.1f} s)"}}
+    return rec, sel, ref
+
+
+def oracle_parity(om_gpu, rows_gpu, sel, ref, rel_bar):
+    """Element-by-element comparison of the GPU grid's Q rows `sel` with the
+    oracle's rows of the same workload, and of Algorithm 1's per-row minima
+    (tie rule of the oracle) on those rows."""
+    import numpy as np
+
+    import oracle
+
+    got = om_gpu[:, :, sel]
+    rel = np.abs(got - ref) / np.abs(ref)
+    rec = {"rows_compared": int(ref.shape[0] * ref.shape[1] * ref.shape[2]),
+           "cells_compared": int(ref.size), "max_rel": float(rel.max()),
+           "bar": rel_bar, "within_bar": bool(rel.max() <= rel_bar)}
+    if rows_gpu is not None:
+        rr = oracle.argmin_grid(ref)[2]
+        rec["row_argmin_equal"] = bool(np.array_equal(rows_gpu[:, :, sel], rr))
+    return rec
 
 
 def calibrate_copy(mib):
@@ -130,13 +188,14 @@ def calibrate_copy(mib):
     return 0
 
 
-def phase_diagram(args):
+def phase_record():
     """Phase-diagram workload: every (h, T) point of a 64 x 64 grid, lattice
     sizes drawn per point, full Omega grid + argmin in one library call, FP64
-    then FP32-compensated.  Prints one JSON line with both wall times."""
+    then FP32-compensated, plus the FP64 call captured once in a HIP graph
+    and replayed.  Wall times cover the whole call (every launch of it)."""
     import torch
 
-    from paper_1412_8754_amd import _abi, api
+    from paper_1412_8754_amd import api
     from paper_1412_8754_amd import workloads as W
 
     cfg = W.phase_config()
@@ -162,12 +221,12 @@ def phase_diagram(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         res[name] = {"wall_s": dt, "evals_per_s": evals / dt, "idx": idx.cpu(),
-                     "om": om}
+                     "omin": omin, "om": om}
         print(f"bench: {name} {dt:.3f} s, {evals / dt:.3e} evals/s", file=sys.stderr,
               flush=True)
         if name == "fp64":
             # the same call captured once into a HIP graph and replayed
-            del idx, omin, rows
+            del idx, rows
             s = torch.cuda.Stream()
             s.wait_stream(torch.cuda.current_stream())
             g = torch.cuda.CUDAGraph()
@@ -188,22 +247,109 @@ def phase_diagram(args):
         del ws
     same = (res["fp64"]["idx"] == res["fp32c"]["idx"]).all(dim=-1)
     rel = ((res["fp32c"]["om"] - res["fp64"]["om"]).abs() / res["fp64"]["om"].abs()).max().item()
+    orel = ((res["fp32c"]["omin"] - res["fp64"]["omin"]).abs() /
+            res["fp64"]["omin"].abs()).max().item()
+    return {"workload": f"phase: {len(pts)} (h,T) points, h in [0,0.4], T in [1e-3,0.05], "
+                        f"L per point from {{256,512,1024,2048}} (SplitMix64), "
+                        f"{n_d} Delta x {n_q} Q x 2 bands, full grid + argmin, one call",
+            "evals": evals,
+            "fp64": {"wall_s": res["fp64"]["wall_s"], "evals_per_s": res["fp64"]["evals_per_s"]},
+            "fp64_graph_replay": res["graph"],
+            "fp32c": {"wall_s": res["fp32c"]["wall_s"],
+                      "evals_per_s": res["fp32c"]["evals_per_s"]},
+            "fp32c_speedup": res["fp64"]["wall_s"] / res["fp32c"]["wall_s"],
+            "fp32c_vs_fp64": {"max_rel_omega": rel, "max_rel_omin": orel,
+                              "argmin_equal_fraction": same.float().mean().item(),
+                              "argmin_differs": int((~same).sum().item())}}
+
+
+def lo_record():
+    """LO pairing (pair momenta q and -q of equal amplitude) of the two-band
+    model on a 64 x 64 lattice: 32 Delta in [0, 0.6] x 8 q = (2 pi m/64, 0),
+    m = 1..8, both bands, at the paper's (h, T).  Each (sector, cycle) is one
+    periodic tridiagonal matrix of 2 * 64 / gcd(2m, 64) modes, diagonalised
+    on the GPU.  Wall time of the call (its parity with the oracle is a GPU
+    test)."""
+    import torch
+
+    from paper_1412_8754_amd import api
+    from paper_1412_8754_amd import workloads as W
+
+    pts = [(0.1, 0.002, 64, 64)]
+    delta = W.delta_grid(32)
+    qi = [[m, 0] for m in range(1, 9)]
+    d = torch.as_tensor(delta, dtype=torch.float64, device="cuda")
+    api.lo_grid(W.DEFAULT_MODEL, pts, d, qi, 3)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om = api.lo_grid(W.DEFAULT_MODEL, pts, d, qi, 3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rec = {"workload": "LO: L=64x64, 32 Delta in [0,0.6], 8 q=(2 pi m/64, 0) m=1..8, "
+                       "2 bands, h=0.1, T=0.002",
+           "wall_ms": dt * 1e3, "min_omega_per_band": om.amin(dim=(0, 2, 3)).cpu().tolist()}
+    print(f"bench: LO {rec['wall_ms']:.2f} ms", file=sys.stderr, flush=True)
+    return rec
+
+
+def phase_diagram(args):
+    """The phase-diagram workload alone, as one JSON line."""
+    rec = phase_record()
     out = {"metric": "phase-diagram wall time (Omega grid + argmin over all points)",
-           "value": res["fp64"]["wall_s"], "unit": "s", "higher_is_better": False,
-           "n_gpus": 1, "data": "synthetic",
-           "config": {"workload": f"phase: {len(pts)} (h,T) points, h in [0,0.4], T in "
-                                  f"[1e-3,0.05], L per point from {{256,512,1024,2048}} "
-                                  f"(SplitMix64), {n_d} Delta x {n_q} Q x 2 bands",
-                      "evals": evals},
-           "fp64": {"wall_s": res["fp64"]["wall_s"], "evals_per_s": res["fp64"]["evals_per_s"]},
-           "fp64_graph_replay": res["graph"],
-           "fp32c": {"wall_s": res["fp32c"]["wall_s"],
-                     "evals_per_s": res["fp32c"]["evals_per_s"]},
-           "fp32c_vs_fp64": {"max_rel_omega": rel,
-                             "argmin_equal_fraction": same.float().mean().item(),
-                             "argmin_differs": int((~same).sum().item())}}
+           "value": rec["fp64"]["wall_s"], "unit": "s", "higher_is_better": False,
+           "n_gpus": 1, "data": "synthetic", "config": {"workload": rec["workload"],
+                                                        "evals": rec["evals"]}}
+    out.update({k: v for k, v in rec.items() if k not in ("workload", "evals")})
     print(json.dumps(out), flush=True)
     return 0
+
+
+def precision_record(steps):
+    """The L = 2048 precision workload (512 Delta x 128 Q x 2 bands, h = 0.1,
+    T = 0.002): ms per step of omega_argmin in both precisions, and how far
+    the FP32-compensated grid and minima are from the FP64 ones."""
+    import torch
+
+    from paper_1412_8754_amd import api
+    from paper_1412_8754_amd import workloads as W
+
+    cfg = W.config("precision")
+    pts = cfg["pts"]
+    dev = torch.device("cuda:0")
+    delta = torch.as_tensor(cfg["delta"], dtype=torch.float64, device=dev)
+    q = torch.as_tensor(cfg["q"], dtype=torch.float64, device=dev).contiguous()
+    n_d, n_q = delta.numel(), q.shape[0]
+    evals = sum(p[2] * p[3] for p in pts) * n_d * n_q * 2
+    res = {}
+    for name, prec in (("fp64", api.OMEGA_FP64), ("fp32c", api.OMEGA_FP32_COMP)):
+        ws = torch.empty(api.workspace_bytes(pts, n_d, n_q, 3, prec), dtype=torch.uint8,
+                         device=dev)
+        r = api.argmin(W.DEFAULT_MODEL, pts, delta, q, 3, prec, workspace=ws)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = api.argmin(W.DEFAULT_MODEL, pts, delta, q, 3, prec, workspace=ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        res[name] = {"ms": ms, "r": r}
+        print(f"bench: precision workload {name} {ms:.3f} ms/step", file=sys.stderr,
+              flush=True)
+        del ws
+    i64, o64, r64, g64 = res["fp64"]["r"]
+    i32, o32, r32, g32 = res["fp32c"]["r"]
+    return {"workload": f"precision: L={pts[0][2]}x{pts[0][3]}, {n_d} Delta in [0,0.6], "
+                        f"{n_q} Q=(j*pi/1024,0), 2 bands, h={pts[0][0]}, T={pts[0][1]}",
+            "steps": steps, "evals_per_step": evals,
+            "fp64": {"ms_per_step": res["fp64"]["ms"],
+                     "evals_per_s": evals / (res["fp64"]["ms"] * 1e-3)},
+            "fp32c": {"ms_per_step": res["fp32c"]["ms"],
+                      "evals_per_s": evals / (res["fp32c"]["ms"] * 1e-3)},
+            "fp32c_speedup": res["fp64"]["ms"] / res["fp32c"]["ms"],
+            "fp32c_vs_fp64": {"max_rel_omega": ((g32 - g64).abs() / g64.abs()).max().item(),
+                              "argmin_equal": bool(torch.equal(i32, i64)),
+                              "row_argmin_equal": bool(torch.equal(r32, r64)),
+                              "argmin_fp64": i64.cpu().tolist(),
+                              "argmin_fp32c": i32.cpu().tolist()}}
 
 
 def differentiation(args):
@@ -334,7 +480,7 @@ def main():
     bands = cfg["bands"]
     nb = _abi.n_bands3(bands) if three else _abi.n_bands(bands)
     wsb = api.workspace_bytes3 if three else api.workspace_bytes
-    argmin_fn = L.omega3_argmin if three else L.omega_argmin
+    argmin_fn = L.omega3_argmin_ex if three else L.omega_argmin_ex
     delta = torch.as_tensor(cfg["delta"], dtype=torch.float64, device=dev)
     q = torch.as_tensor(cfg["q"], dtype=torch.float64, device=dev).contiguous()
     n_d, n_q = delta.numel(), q.shape[0]
@@ -349,12 +495,26 @@ def main():
     p = _abi.make_points(pts)
     stream = torch.cuda.current_stream()
 
-    def step():
+    # launch options from the autotuner (they change no result), tuned on this
+    # very call outside the timed region
+    tune = None
+    if not args.no_tune and not three:
+        from paper_1412_8754_amd import autotune
+        tune = autotune.tune(W.DEFAULT_MODEL, pts, delta, q, bands, prec, reps=3, save=False)
+        print(f"bench: autotune picked blocks/CU {tune['sweep_blocks_per_cu']}, queues "
+              f"{tune['sweep_queues']} ({tune['ms']:.3f} ms vs default {tune['default_ms']:.3f})",
+              file=sys.stderr, flush=True)
+    base_launch = (tune["sweep_blocks_per_cu"], tune["sweep_queues"]) if tune else (0, 0)
+
+    def step(start=None, stop=None, count=None, launch=base_launch, prc=prec, wsp=ws,
+             wsz=ws_bytes):
+        lo = _abi.Launch(launch[0], launch[1], start, stop, count)
         rc = argmin_fn(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d, q.data_ptr(),
-                            n_q, bands, prec, 1e-11, ws.data_ptr(), ws_bytes, idx.data_ptr(),
-                            omin.data_ptr(), rows.data_ptr(), om.data_ptr(), stream.cuda_stream)
+                       n_q, bands, prc, 1e-11, wsp.data_ptr(), wsz, idx.data_ptr(),
+                       omin.data_ptr(), rows.data_ptr(), om.data_ptr(), ctypes.byref(lo),
+                       stream.cuda_stream)
         if rc != 0:
-            raise _abi.OmegaError(rc, "omega_argmin")
+            raise _abi.OmegaError(rc, "omega_argmin_ex")
 
     print(f"bench: workload={args.workload} precision={args.precision} steps={args.steps} "
           f"warmup={args.warmup}", file=sys.stderr, flush=True)
@@ -372,18 +532,14 @@ def main():
 
     t0 = time.perf_counter()
     for i in range(args.steps):
-        L.omega_set_sweep_events(ev[i][0].cuda_event, ev[i][1].cuda_event)
-        step()
+        step(ev[i][0].cuda_event, ev[i][1].cuda_event)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    L.omega_set_sweep_events(None, None)
     # one more (untimed) step with the work counter: (k, Delta) terms the
     # per-Delta sweep evaluated directly; the rest went through the series
     counter = torch.zeros(1, dtype=torch.int64, device=dev)
-    L.omega_set_sweep_counter(counter.data_ptr())
-    step()
+    step(count=counter.data_ptr())
     torch.cuda.synchronize()
-    L.omega_set_sweep_counter(None)
     direct = int(counter.item())
 
     ms_step = (t1 - t0) * 1e3 / args.steps
@@ -422,12 +578,17 @@ def main():
                                f"{nb} bands, h={pts[0][0]}, T={pts[0][1]}, full grid + argmin",
                    "precision": args.precision, "evals_per_step": evals_step,
                    "folded_terms_per_step": evaluated, "direct_terms_per_step": direct},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": TRAFFIC_BYTES.get((args.workload, args.precision)),
-                     "kernel": sweep_kernel_name(args.precision, three, pts[0][1]),
-                     "kernel_ms": sweep_avg, "ops_per_eval": OPS_PER_EVAL},
+        "roofline": roofline_record(args.workload, args.precision, achieved, peak, three,
+                                    pts[0][1], sweep_avg, direct),
     }
+    if tune is not None:
+        out["autotune"] = {"sweep_blocks_per_cu": tune["sweep_blocks_per_cu"],
+                           "sweep_queues": tune["sweep_queues"], "tuned_call_ms": tune["ms"],
+                           "default_call_ms": tune["default_ms"],
+                           "note": "launch options only; results are bitwise those of the "
+                                   "default options"}
+    om_first = om.cpu().numpy()
+    rows_first = rows.cpu().numpy()
     if not args.no_compare and prec == api.OMEGA_FP64:
         # same workload through the FP32-compensated sweep: time, Omega error
         # against the FP64 grid just computed, and whether the argmin moved
@@ -437,13 +598,15 @@ def main():
         ws32_bytes = wsb(pts, n_d, n_q, bands, prec32)
         ws32 = torch.empty(ws32_bytes, dtype=torch.uint8, device=dev)
 
+        tune32 = None
+        if tune is not None:
+            tune32 = autotune.tune(W.DEFAULT_MODEL, pts, delta, q, bands, prec32, reps=3,
+                                   save=False)
+        launch32 = ((tune32["sweep_blocks_per_cu"], tune32["sweep_queues"]) if tune32
+                    else (0, 0))
+
         def step32():
-            rc = argmin_fn(ctypes.byref(m), p, n_pts, delta.data_ptr(), n_d,
-                                q.data_ptr(), n_q, bands, prec32, 1e-11, ws32.data_ptr(),
-                                ws32_bytes, idx.data_ptr(), omin.data_ptr(), rows.data_ptr(),
-                                om.data_ptr(), stream.cuda_stream)
-            if rc != 0:
-                raise _abi.OmegaError(rc, "omega_argmin")
+            step(launch=launch32, prc=prec32, wsp=ws32, wsz=ws32_bytes)
 
         step32()
         torch.cuda.synchronize()
@@ -453,17 +616,32 @@ def main():
         torch.cuda.synchronize()
         ms32 = (time.perf_counter() - t0) * 1e3 / args.steps
         rel = ((om - om64).abs() / om64.abs()).max().item()
+        om32_host = om.cpu().numpy()
         out["fp32c_compare"] = {"ms_per_step": ms32, "value": evals_step / (ms32 * 1e-3),
+                                "speedup_vs_fp64": ms_step / ms32,
                                 "max_rel_omega_vs_fp64": rel,
                                 "argmin_equal": bool(torch.equal(idx, idx64))}
         print(f"bench: fp32c {ms32:.3f} ms/step, max rel vs fp64 {rel:.2e}, argmin equal "
               f"{out['fp32c_compare']['argmin_equal']}", file=sys.stderr, flush=True)
     if not args.no_cpu:
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cb = cpu_baseline(cfg, args.cpu_rows)
+        cb, sel, ref = cpu_baseline(cfg, args.cpu_rows)
+        # the oracle rows just timed, against the GPU grid of the timed step
+        fp32c = prec == api.OMEGA_FP32_COMP
+        cb["parity"] = {args.precision: oracle_parity(om_first, rows_first, sel, ref,
+                                                      1e-7 if fp32c else 1e-12)}
+        if "fp32c_compare" in out:
+            cb["parity"]["fp32c"] = oracle_parity(om32_host, None, sel, ref, 1e-7)
         out["cpu_baseline"] = cb
         print(f"bench: cpu {cb['value']:.3e} evals/s on {cb['cores']} threads; "
-              f"GPU/CPU = {value / cb['value']:.1f}x", file=sys.stderr, flush=True)
+              f"GPU/CPU = {value / cb['value']:.1f}x; oracle rows vs GPU {cb['parity']}",
+              file=sys.stderr, flush=True)
+    if args.workload == "paper" and not args.no_lo:
+        out["lo"] = lo_record()
+    if args.workload == "paper" and not args.no_precision:
+        out["precision"] = precision_record(max(1, min(args.steps, 5)))
+    if args.workload == "paper" and not args.no_phase:
+        out["phase"] = phase_record()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -49,14 +49,24 @@
 extern "C" {
 #endif
 
+/* Form factor of the pair (k up, -k+Q down).  OMEGA_ETA_K: Delta_k = Delta
+ * eta(k) on the spin-up momentum, as Sec. 2, Eq. (3) writes it (the default;
+ * a zero-initialised model gets it).  OMEGA_ETA_REL: Delta eta(k - Q/2), the
+ * form factor at the pair's relative momentum (k - (Q - k))/2; the two agree
+ * at Q = 0. */
+enum { OMEGA_ETA_K = 0, OMEGA_ETA_REL = 1 };
+
 /* Model constants.  t1..t4: hoppings of App. A, Eqs. (A.1)-(A.3) (the paper's
  * values are t1=-1, t2=1.3, t3=t4=-0.85); mu: chemical potential (1.54 gives
  * two electrons per site); V[0], V[1]: pairing strength V_eps of Eq. (5) for
- * the E_- and E_+ band.  All finite, V[i] != 0. */
+ * the E_- and E_+ band; form: OMEGA_ETA_K or OMEGA_ETA_REL; pad: 0.  All
+ * finite, V[i] != 0. */
 typedef struct {
     double t1, t2, t3, t4;
     double mu;
     double V[2];
+    int32_t form;
+    int32_t pad;
 } omega_model;
 
 /* One (h, T) point of a phase diagram on an Lx x Ly lattice.
@@ -105,6 +115,32 @@ int omega_grid(const omega_model *model, const omega_point *pts, int n_pts,
                int n_q, int bands, int precision, void *ws_dev,
                size_t ws_bytes, double *omega_dev, void *stream);
 
+/* Launch options of the _ex entry points; NULL, or a zero-initialised
+ * struct, gives the defaults of the plain entry points.  None of them changes
+ * any result: each unit of work of the persistent sweeps is computed by one
+ * wave in a fixed order, whichever wave takes it.
+ *   sweep_blocks_per_cu  workgroups per CU of the persistent per-Delta
+ *                        sweeps (>= 0; 0: as many as stay resident)
+ *   sweep_queues         work queues they take units from (0..16; 0: 8)
+ *   sweep_start_event,   hipEvent_t handles (caller-owned, both or neither)
+ *   sweep_stop_event     recorded on the call's stream right before the
+ *                        call's first per-Delta sweep launch and right after
+ *                        its last (with one batch of points: around that
+ *                        sweep alone; the paper times the computation part
+ *                        only, Sec. 3.3)
+ *   count_dev            NULL, or a device pointer to an unsigned 64-bit
+ *                        counter to which the sweeps add the number of
+ *                        (k, Delta) terms they evaluated directly (terms
+ *                        summed through a series in Delta^2 are not counted)
+ * The options belong to the call: the library keeps none of them. */
+typedef struct {
+    int32_t sweep_blocks_per_cu;
+    int32_t sweep_queues;
+    void *sweep_start_event;
+    void *sweep_stop_event;
+    unsigned long long *count_dev;
+} omega_launch;
+
 /* Omega grid plus the searches of Algorithm 1 (per-Q Delta minimum, then the
  * global minimum), with a tie rule: among grid points with
  * Omega <= Omega_min + tie_rel*|Omega_min| the lexicographically smallest
@@ -123,6 +159,14 @@ int omega_argmin(const omega_model *model, const omega_point *pts, int n_pts,
                  void *ws_dev, size_t ws_bytes, int32_t *idx_dev,
                  double *omin_dev, int32_t *row_idx_dev, double *omega_dev,
                  void *stream);
+
+/* omega_argmin with launch options (NULL: the defaults); OMEGA_E_INVAL for
+ * options out of range. */
+int omega_argmin_ex(const omega_model *model, const omega_point *pts, int n_pts,
+                    const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                    int bands, int precision, double tie_rel, void *ws_dev, size_t ws_bytes,
+                    int32_t *idx_dev, double *omin_dev, int32_t *row_idx_dev,
+                    double *omega_dev, const omega_launch *launch, void *stream);
 
 /* Omega and its first derivatives at one (Delta, Q) per point and band,
  * obtained by differentiating Eqs. (4)-(5) by hand (dOmega/dE = Fermi
@@ -153,12 +197,15 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
  * t2 = 0.1825, t3 = 0.08375, t4 = -0.03, t5 = t6 = 0.15, t7 = -0.12,
  * t8 = 0.06, t9 = 0, t10 = -0.024, t11 = -0.01, t12 = 0.0275,
  * eps0 = 0.75; mu = 0.4748 gives four electrons per site); V[b]: pairing
- * strength of band b in Eq. (5).  All finite; V[b] != 0 for selected bands. */
+ * strength of band b in Eq. (5); form: OMEGA_ETA_K or OMEGA_ETA_REL; pad: 0.
+ * All finite; V[b] != 0 for selected bands. */
 typedef struct {
     double t[12];
     double eps0;
     double mu;
     double V[3];
+    int32_t form;
+    int32_t pad;
 } omega3_model;
 
 /* Band selection of the three-band model; outputs hold the selected bands in
@@ -189,6 +236,14 @@ int omega3_argmin(const omega3_model *model, const omega_point *pts, int n_pts,
                   int bands, int precision, double tie_rel, void *ws_dev,
                   size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
                   int32_t *row_idx_dev, double *omega_dev, void *stream);
+
+/* omega3_argmin with launch options, as omega_argmin_ex. */
+int omega3_argmin_ex(const omega3_model *model, const omega_point *pts, int n_pts,
+                     const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                     int bands, int precision, double tie_rel, void *ws_dev,
+                     size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
+                     int32_t *row_idx_dev, double *omega_dev, const omega_launch *launch,
+                     void *stream);
 
 /* ------------------------------------------------------------------------
  * Static Cooper-pair susceptibility, App. C, at omega -> 0:
@@ -235,28 +290,45 @@ int omega3_pair_chi(const omega3_model *model, const omega_point *pts, int n_pts
  * OMEGA_E_WORKSPACE if capacity is too small. */
 int omega_q_wedge(int Lx, int Ly, double *q_host, int32_t *orbit_host, int capacity);
 
+/* ------------------------------------------------------------------------
+ * Larkin-Ovchinnikov (LO) pairing of the two-band model: the M = 2 case of
+ * the plane-wave sum of Sec. 2, Eq. (6), pairs of momentum q and -q with
+ * equal amplitude, Delta(R_j) = Delta (e^{i q.R_j} + e^{-i q.R_j}), gap
+ * Delta eta(k) on the spin-up momentum (OMEGA_ETA_K only).  As the
+ * historical and technical note of Sec. 2 describes, with q on a lattice
+ * axis the Nambu problem splits into one 2 L x 2 L problem per momentum
+ * across q (L the lattice side along q); each of those splits further into
+ * cycles of 2 L / gcd(2 s, L) modes (q = 2 pi s / L), which the library
+ * diagonalises numerically (cyclic Jacobi, FP64).  Per band:
+ *   Omega_LO = -T sum_n ln(1 + e^{-E_n/T}) + sum_k E_{k down}
+ *              - (2 / V_eps) sum_j |Delta(R_j)|^2
+ * over the 2N Nambu eigenvalues E_n; the last two terms are those of
+ * Eq. (5), with sum_j |Delta(R_j)|^2 = 2 N Delta^2 (4 N Delta^2 where 2q is
+ * a reciprocal lattice vector: then the two waves coincide and the state
+ * is the FF state of gap 2 Delta).  One wave alone reproduces Eq. (5).
+ *   q_host   host [n_q][2] lattice indices (m, n) of q = (2 pi m/Lx,
+ *            2 pi n/Ly) with m == 0 or n == 0; a cycle may hold at most 128
+ *            modes (2 L / gcd(2 s, L) <= 128), else OMEGA_E_UNSUPPORTED
+ *   omega_dev device output [n_pts][nb][n_q][n_delta] (total, not per site)
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes of omega_lo_grid; 0 if the arguments are invalid or a
+ * (point, q) is outside what omega_lo_grid takes. */
+size_t omega_lo_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
+                                const int32_t *q_host, int n_q, int bands);
+
+int omega_lo_grid(const omega_model *model, const omega_point *pts, int n_pts,
+                  const double *delta_dev, int n_delta, const int32_t *q_host, int n_q,
+                  int bands, void *ws_dev, size_t ws_bytes, double *omega_dev, void *stream);
+
 /* Static description of an OMEGA_* code (never NULL). */
 const char *omega_strerror(int code);
 
-/* Library interface version, currently 3 (2 added the three-band model, 3 the
- * pair susceptibility). */
+/* Library interface version, currently 4 (2 added the three-band model, 3 the
+ * pair susceptibility, 4 the form factor field of the model structs, the LO
+ * pairing, and the launch options of the _ex calls in place of process-wide
+ * benchmark hooks). */
 int omega_version(void);
-
-/* Timing hook for benchmarks (the paper times the computation part only,
- * Sec. 3.3).  While set, the per-Delta sweep kernel of every batch the
- * process enqueues is bracketed by hipEventRecord(start_event) and
- * hipEventRecord(stop_event) on the call's stream; start_event and stop_event are hipEvent_t handles owned by the
- * caller.  Passing NULL for both clears the hook.  Process-wide, not
- * thread-safe: set it only while a single thread drives the library.
- * Returns OMEGA_E_INVAL if exactly one of the two is NULL. */
-int omega_set_sweep_events(void *start_event, void *stop_event);
-
-/* Work counter for benchmarks.  While set (count_dev a device pointer to one
- * zeroed unsigned 64-bit integer), the per-Delta sweep adds the number of
- * (k, Delta) terms it evaluated directly; terms whose Delta dependence is
- * summed through moments of a series in Delta^2 (where |s| - |d| >= 36 T
- * and the series converges fast) are not counted.  NULL clears it.  Process-wide, not thread-safe.  Always OMEGA_OK. */
-int omega_set_sweep_counter(unsigned long long *count_dev);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ The computation lives in libomega.so (HIP kernels behind the C interface of
 include/omega.h); `api` marshals torch tensors into it.
 """
 from ._abi import (OMEGA_BAND_BOTH, OMEGA_BAND_MINUS, OMEGA_BAND_PLUS,  # noqa: F401
-                   OMEGA_FP32_COMP, OMEGA_FP64, OmegaError)
+                   OMEGA_ETA_K, OMEGA_ETA_REL, OMEGA_FP32_COMP, OMEGA_FP64, OmegaError)
 
-__all__ = ["OMEGA_BAND_BOTH", "OMEGA_BAND_MINUS", "OMEGA_BAND_PLUS", "OMEGA_FP32_COMP",
-           "OMEGA_FP64", "OmegaError"]
+__all__ = ["OMEGA_BAND_BOTH", "OMEGA_BAND_MINUS", "OMEGA_BAND_PLUS", "OMEGA_ETA_K",
+           "OMEGA_ETA_REL", "OMEGA_FP32_COMP", "OMEGA_FP64", "OmegaError"]

@@ -14,26 +14,40 @@ OMEGA_OK, OMEGA_E_INVAL, OMEGA_E_WORKSPACE, OMEGA_E_HIP, OMEGA_E_UNSUPPORTED = 0
 OMEGA3_BAND_0, OMEGA3_BAND_1, OMEGA3_BAND_2, OMEGA3_BAND_ALL = 1, 2, 4, 7
 
 EXPORTS = ("omega_workspace_bytes", "omega_grid", "omega_argmin", "omega_grad",
-           "omega_strerror", "omega_version", "omega_set_sweep_events",
-           "omega_set_sweep_counter", "omega3_bands", "omega3_workspace_bytes",
+           "omega_strerror", "omega_version", "omega_argmin_ex", "omega3_argmin_ex",
+           "omega3_bands", "omega3_workspace_bytes",
            "omega3_grid", "omega3_argmin", "omega_chi_workspace_bytes", "omega_pair_chi",
-           "omega3_chi_workspace_bytes", "omega3_pair_chi", "omega_q_wedge")
+           "omega3_chi_workspace_bytes", "omega3_pair_chi", "omega_q_wedge",
+           "omega_lo_workspace_bytes", "omega_lo_grid")
+
+
+OMEGA_ETA_K, OMEGA_ETA_REL = 0, 1
 
 
 class Model(ctypes.Structure):
     _fields_ = [("t1", ctypes.c_double), ("t2", ctypes.c_double),
                 ("t3", ctypes.c_double), ("t4", ctypes.c_double),
-                ("mu", ctypes.c_double), ("V", ctypes.c_double * 2)]
+                ("mu", ctypes.c_double), ("V", ctypes.c_double * 2),
+                ("form", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Model3(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double * 12), ("eps0", ctypes.c_double),
-                ("mu", ctypes.c_double), ("V", ctypes.c_double * 3)]
+                ("mu", ctypes.c_double), ("V", ctypes.c_double * 3),
+                ("form", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Point(ctypes.Structure):
     _fields_ = [("h", ctypes.c_double), ("T", ctypes.c_double),
                 ("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32)]
+
+
+class Launch(ctypes.Structure):
+    """omega_launch: launch options of the _ex calls (results do not depend
+    on them)."""
+    _fields_ = [("sweep_blocks_per_cu", ctypes.c_int32), ("sweep_queues", ctypes.c_int32),
+                ("sweep_start_event", ctypes.c_void_p), ("sweep_stop_event", ctypes.c_void_p),
+                ("count_dev", ctypes.c_void_p)]
 
 
 class OmegaError(RuntimeError):
@@ -76,10 +90,10 @@ def load() -> ctypes.CDLL:
     L.omega_strerror.argtypes = [i32]
     L.omega_version.restype = i32
     L.omega_version.argtypes = []
-    L.omega_set_sweep_events.restype = i32
-    L.omega_set_sweep_events.argtypes = [vp, vp]
-    L.omega_set_sweep_counter.restype = i32
-    L.omega_set_sweep_counter.argtypes = [vp]
+    lp = ctypes.POINTER(Launch)
+    L.omega_argmin_ex.restype = i32
+    L.omega_argmin_ex.argtypes = [mp, pp, i32, vp, i32, vp, i32, i32, i32, ctypes.c_double,
+                                  vp, sz, vp, vp, vp, vp, lp, vp]
     m3 = ctypes.POINTER(Model3)
     L.omega3_bands.restype = i32
     L.omega3_bands.argtypes = [m3, i32, i32, vp, sz, vp, vp]
@@ -97,9 +111,16 @@ def load() -> ctypes.CDLL:
     L.omega3_pair_chi.argtypes = [m3, pp, i32, vp, i32, i32, vp, sz, vp, vp]
     L.omega_q_wedge.restype = i32
     L.omega_q_wedge.argtypes = [i32, i32, vp, vp, i32]
+    L.omega_lo_workspace_bytes.restype = sz
+    L.omega_lo_workspace_bytes.argtypes = [pp, i32, i32, vp, i32, i32]
+    L.omega_lo_grid.restype = i32
+    L.omega_lo_grid.argtypes = [mp, pp, i32, vp, i32, vp, i32, i32, vp, sz, vp, vp]
     L.omega3_argmin.restype = i32
     L.omega3_argmin.argtypes = [m3, pp, i32, vp, i32, vp, i32, i32, i32, ctypes.c_double,
                                 vp, sz, vp, vp, vp, vp, vp]
+    L.omega3_argmin_ex.restype = i32
+    L.omega3_argmin_ex.argtypes = [m3, pp, i32, vp, i32, vp, i32, i32, i32, ctypes.c_double,
+                                   vp, sz, vp, vp, vp, vp, lp, vp]
     _lib = L
     return L
 
@@ -112,14 +133,16 @@ def make_model(m) -> Model:
     if isinstance(m, Model):
         return m
     return Model(float(m["t1"]), float(m["t2"]), float(m["t3"]), float(m["t4"]),
-                 float(m["mu"]), (ctypes.c_double * 2)(*[float(v) for v in m["V"]]))
+                 float(m["mu"]), (ctypes.c_double * 2)(*[float(v) for v in m["V"]]),
+                 int(m.get("form", OMEGA_ETA_K)), 0)
 
 
 def make_model3(m) -> Model3:
     if isinstance(m, Model3):
         return m
     return Model3((ctypes.c_double * 12)(*[float(v) for v in m["t"]]), float(m["eps0"]),
-                  float(m["mu"]), (ctypes.c_double * 3)(*[float(v) for v in m["V"]]))
+                  float(m["mu"]), (ctypes.c_double * 3)(*[float(v) for v in m["V"]]),
+                  int(m.get("form", OMEGA_ETA_K)), 0)
 
 
 def make_points(pts):

@@ -75,14 +75,28 @@ def grid(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = OM
     return out
 
 
+def make_launch(launch) -> "_abi.Launch | None":
+    """omega_launch from None, an _abi.Launch, or a dict with any of the keys
+    sweep_blocks_per_cu, sweep_queues (launch options that change no result)."""
+    if launch is None or isinstance(launch, _abi.Launch):
+        return launch
+    return _abi.Launch(int(launch.get("sweep_blocks_per_cu", 0)),
+                       int(launch.get("sweep_queues", 0)), None, None, None)
+
+
 def argmin(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = OMEGA_FP64,
            tie_rel: float = 1e-11, keep_grid: bool = True, rows: bool = True, device="cuda",
-           workspace=None, stream=None):
+           workspace=None, stream=None, launch=None, tuned: bool = False):
     """Grid plus the searches of Algorithm 1.
 
+    launch: launch options (see make_launch); tuned: take them from the
+    autotuner's cache for this call's shape, if it holds an entry.
     Returns (idx [n_pts][nb][2] int32 (iDelta, iq), omin [n_pts][nb],
     row_idx [n_pts][nb][n_q] or None, omega grid or None)."""
     L = _abi.load()
+    if tuned and launch is None:
+        from . import autotune
+        launch = autotune.lookup(pts, len(delta), len(q), bands, precision)
     d = _dev_f64(delta, device, (-1,))
     qq = _dev_f64(q, device, (-1, 2))
     nb = n_bands(bands)
@@ -94,12 +108,14 @@ def argmin(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = 
     ws = _workspace(workspace_bytes(pts, n_d, n_q, bands, precision), device, workspace)
     m = make_model(model)
     p = make_points(pts)
-    rc = L.omega_argmin(ctypes.byref(m), p, n_pts, d.data_ptr(), n_d, qq.data_ptr(), n_q,
-                        int(bands), int(precision), float(tie_rel), ws.data_ptr(),
-                        ws.numel() * ws.element_size(), idx.data_ptr(), omin.data_ptr(),
-                        row_idx.data_ptr() if row_idx is not None else None,
-                        om.data_ptr() if om is not None else None, _stream_ptr(stream))
-    _check(rc, "omega_argmin")
+    lo = make_launch(launch)
+    rc = L.omega_argmin_ex(ctypes.byref(m), p, n_pts, d.data_ptr(), n_d, qq.data_ptr(), n_q,
+                           int(bands), int(precision), float(tie_rel), ws.data_ptr(),
+                           ws.numel() * ws.element_size(), idx.data_ptr(), omin.data_ptr(),
+                           row_idx.data_ptr() if row_idx is not None else None,
+                           om.data_ptr() if om is not None else None,
+                           ctypes.byref(lo) if lo is not None else None, _stream_ptr(stream))
+    _check(rc, "omega_argmin_ex")
     return idx, omin, row_idx, om
 
 
@@ -125,6 +141,34 @@ def grad(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, device="cuda", work
                       gd.data_ptr(), gq.data_ptr(), gm.data_ptr(), _stream_ptr(stream))
     _check(rc, "omega_grad")
     return om, gd, gq, gm
+
+
+# ------------------------------------------------------------- LO pairing
+
+def lo_grid(model, pts, delta, q_index, bands: int = OMEGA_BAND_BOTH, device="cuda",
+            workspace=None, stream=None) -> torch.Tensor:
+    """Omega of the LO state (pair momenta q and -q, equal amplitude) of the
+    two-band model, [n_pts][nb][n_q][n_delta]; q_index: [n_q][2] lattice
+    indices (m, n) of q = (2 pi m/Lx, 2 pi n/Ly), one of them 0."""
+    import numpy as np
+    L = _abi.load()
+    d = _dev_f64(delta, device, (-1,))
+    qi = np.ascontiguousarray(np.asarray(q_index, dtype=np.int32).reshape(-1, 2))
+    nb = n_bands(bands)
+    p = make_points(pts)
+    n = L.omega_lo_workspace_bytes(p, len(pts), d.numel(), qi.ctypes.data, qi.shape[0],
+                                   int(bands))
+    if n == 0:
+        raise OmegaError(_abi.OMEGA_E_UNSUPPORTED, "omega_lo_workspace_bytes")
+    ws = _workspace(int(n), device, workspace)
+    out = torch.empty((len(pts), nb, qi.shape[0], d.numel()), dtype=torch.float64,
+                      device=device)
+    m = make_model(model)
+    rc = L.omega_lo_grid(ctypes.byref(m), p, len(pts), d.data_ptr(), d.numel(),
+                         qi.ctypes.data, qi.shape[0], int(bands), ws.data_ptr(),
+                         ws.numel() * ws.element_size(), out.data_ptr(), _stream_ptr(stream))
+    _check(rc, "omega_lo_grid")
+    return out
 
 
 # ------------------------------------------------------------- three-band model

@@ -1,0 +1,119 @@
+"""Autotuner of the launch options of omega_argmin.
+
+The knobs are the work-queue count and the persistent grid size (workgroups
+per CU) of the per-Delta sweeps.  Neither changes a result: every sweep unit
+is computed by one wave in a fixed order, whichever wave takes it, so a
+tuned call returns the default call's output bitwise.  The tuner times each
+candidate on the caller's own shape with HIP events around the whole call
+and keeps the fastest in a JSON cache keyed by the GPU architecture and the
+call's shape (lattice sizes and temperature class of its points, Delta and
+Q counts, bands, precision).  The cache file is $OMEGA_TUNE_CACHE, else
+~/.cache/paper_1412_8754_amd/autotune.json.
+"""
+from __future__ import annotations
+
+import json
+import os
+import pathlib
+
+# the in-place sweep kernels take the points at or above this temperature
+# (the library groups points by it)
+HOT_T = 0.005
+
+# (workgroups per CU, queues); (0, 0) is the library's default (all resident
+# workgroups, eight queues)
+CANDIDATES = [(0, 0), (0, 4), (0, 16), (0, 2), (0, 1), (2, 0), (2, 16), (1, 0), (1, 16)]
+
+
+def cache_path() -> pathlib.Path:
+    p = os.environ.get("OMEGA_TUNE_CACHE")
+    if p:
+        return pathlib.Path(p)
+    return pathlib.Path.home() / ".cache" / "paper_1412_8754_amd" / "autotune.json"
+
+
+def device_arch() -> str:
+    import torch
+    return str(torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName)
+
+
+def shape_key(pts, n_delta: int, n_q: int, bands: int, precision: int, arch: str) -> str:
+    """Cache key: architecture, then (Lx, Ly, temperature class, count) of the
+    call's point groups, the Delta and Q counts, bands and precision."""
+    groups = {}
+    for (_, T, Lx, Ly) in pts:
+        k = (int(Lx), int(Ly), int(float(T) >= HOT_T))
+        groups[k] = groups.get(k, 0) + 1
+    g = ";".join(f"{a}x{b}:{'hot' if h else 'cold'}:{n}" for (a, b, h), n in sorted(groups.items()))
+    return f"{arch}|{g}|nd={int(n_delta)}|nq={int(n_q)}|bands={int(bands)}|prec={int(precision)}"
+
+
+def load_cache() -> dict:
+    p = cache_path()
+    if not p.exists():
+        return {}
+    with open(p) as f:
+        return json.load(f)
+
+
+def save_entry(key: str, entry: dict) -> None:
+    p = cache_path()
+    p.parent.mkdir(parents=True, exist_ok=True)
+    data = load_cache()
+    data[key] = entry
+    tmp = p.with_suffix(".tmp%d" % os.getpid())
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def lookup(pts, n_delta: int, n_q: int, bands: int, precision: int, arch: str | None = None):
+    """The cached launch options of this shape (a dict for api.argmin's
+    launch argument), or None."""
+    key = shape_key(pts, n_delta, n_q, bands, precision, arch or device_arch())
+    e = load_cache().get(key)
+    if e is None:
+        return None
+    return {"sweep_blocks_per_cu": int(e["sweep_blocks_per_cu"]),
+            "sweep_queues": int(e["sweep_queues"])}
+
+
+def tune(model, pts, delta, q, bands: int = 3, precision: int = 0, reps: int = 3,
+         candidates=None, save: bool = True) -> dict:
+    """Time every candidate on this call (after one untimed call each) and
+    keep the fastest; returns its options with the per-candidate times."""
+    import torch
+
+    from . import api
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    d = torch.as_tensor(delta, dtype=torch.float64, device=dev)
+    qq = torch.as_tensor(q, dtype=torch.float64, device=dev).reshape(-1, 2).contiguous()
+    ws = torch.empty(api.workspace_bytes(pts, d.numel(), qq.shape[0], bands, precision),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    times = {}
+    for (b, nq) in (candidates or CANDIDATES):
+        launch = {"sweep_blocks_per_cu": b, "sweep_queues": nq}
+        api.argmin(model, pts, d, qq, bands, precision, workspace=ws, launch=launch,
+                   keep_grid=False)
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            api.argmin(model, pts, d, qq, bands, precision, workspace=ws, launch=launch,
+                       keep_grid=False)
+            e1.record(stream)
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        times[f"{b},{nq}"] = best
+    (b, nq) = min((tuple(int(x) for x in k.split(",")) for k in times),
+                  key=lambda k: times[f"{k[0]},{k[1]}"])
+    entry = {"sweep_blocks_per_cu": b, "sweep_queues": nq, "ms": times[f"{b},{nq}"],
+             "default_ms": times.get("0,0"), "times_ms": times}
+    if save:
+        save_entry(shape_key(pts, d.numel(), qq.shape[0], bands, precision, device_arch()),
+                   entry)
+    return entry

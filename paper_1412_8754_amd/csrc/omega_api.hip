@@ -34,9 +34,33 @@ constexpr size_t kBatchBytes = 512u << 20; // chunk partials of one batch
 constexpr int kMaxGridZ = 65535;
 constexpr int kGradTilesPerChunk = 64;
 
-hipEvent_t g_sweep_start = nullptr;   // benchmark hooks, see omega_set_sweep_events
-hipEvent_t g_sweep_stop = nullptr;    // and omega_set_sweep_counter
-unsigned long long *g_sweep_count = nullptr;
+// Launch options of one call (omega_launch, resolved): none changes a result.
+struct Launch {
+    int blocks_per_cu = 0;        // persistent sweeps: 0 = all that fit
+    int n_queues = kQueues;       // work queues of the persistent sweeps
+    hipEvent_t start = nullptr;   // recorded before the call's first per-Delta sweep
+    hipEvent_t stop = nullptr;    // and after its last one
+    unsigned long long *count = nullptr;   // direct (k, Delta) terms, added on the device
+};
+
+bool resolve_launch(const omega_launch *in, Launch *out)
+{
+    Launch l;
+    if (in) {
+        if (in->sweep_blocks_per_cu < 0 || in->sweep_queues < 0 ||
+            in->sweep_queues > kMaxQueues ||
+            (in->sweep_start_event == nullptr) != (in->sweep_stop_event == nullptr))
+            return false;
+        l.blocks_per_cu = in->sweep_blocks_per_cu;
+        if (in->sweep_queues > 0)
+            l.n_queues = in->sweep_queues;
+        l.start = (hipEvent_t)in->sweep_start_event;
+        l.stop = (hipEvent_t)in->sweep_stop_event;
+        l.count = in->count_dev;
+    }
+    *out = l;
+    return true;
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -70,6 +94,8 @@ bool model3_ok(const omega3_model *m, int bands)
             return false;
     if (!isfinite(m->eps0) || !isfinite(m->mu))
         return false;
+    if (m->form != OMEGA_ETA_K && m->form != OMEGA_ETA_REL)
+        return false;
     for (int b = 0; b < 3; ++b)
         if ((bands & (1 << b)) && (!isfinite(m->V[b]) || m->V[b] == 0.0))
             return false;
@@ -84,6 +110,8 @@ bool model_ok(const omega_model *m)
     for (double x : v)
         if (!isfinite(x))
             return false;
+    if (m->form != OMEGA_ETA_K && m->form != OMEGA_ETA_REL)
+        return false;
     return m->V[0] != 0.0 && m->V[1] != 0.0;
 }
 
@@ -212,9 +240,22 @@ struct GridPlan {
     std::vector<Group> groups;
     std::vector<Tiles> tiles;   // per group
     std::vector<int> batch;     // points per batch, per group
+    std::vector<int> vchunks;   // momentum chunks of the FP64 check, per group
     size_t off_d2, off_qtrig, off_gtab, off_trig, off_table, off_part, off_base, off_mom,
-        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, off_queue, off_rowmin, sweep_bytes;
+        off_tlist, off_tcnt, off_tpart, off_etab, off_qlat, off_queue, off_rowmin, off_vcand,
+        off_vcnt, off_vthr, off_vpart, sweep_bytes;
 };
+
+// Momentum chunks of one candidate's FP64 sum in the check of the
+// FP32-compensated search: about 4096 busy units at two candidates per set,
+// at least 4096 momenta per chunk.
+int verify_chunks(long long n_k, int sets)
+{
+    long long c = (4096 + 2LL * sets - 1) / (2LL * sets);
+    const long long cap = (n_k + 4095) / 4096;
+    c = c < cap ? c : cap;
+    return c < 1 ? 1 : (int)c;
+}
 
 // b3: three-band model.  The band table of the largest lattice holds 3 bands
 // for it and 2 for the two-band model; the lattice indices of the pair momenta
@@ -230,7 +271,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.nbq = nb * n_q;
     p.groups = group_points(pts, n_pts, true);
     size_t trig = 0, table = 0, part = 0, base = 0, mom = 0, etab = 0, tlist = 0,
-           tcnt = 0, tpart = 0;
+           tcnt = 0, tpart = 0, vsets = 0, vpart = 0;
     for (const Group &g : p.groups) {
         const Tiles t = sweep_tiles(g.Lx, g.Ly, (long long)p.n_dtiles * p.nbq);
         etab = std::max(etab, sizeof(double) * (b3 ? 3 : 2) * (size_t)g.Lx * g.Ly);
@@ -243,6 +284,10 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
         const int G = batch_points(per_point, (int)g.idx.size(), kMaxGridZ / p.nbq);
         p.tiles.push_back(t);
         p.batch.push_back(G);
+        const int vc = verify_chunks((long long)g.Lx * g.Ly, G * nb);
+        p.vchunks.push_back(vc);
+        vsets = std::max(vsets, (size_t)G * nb);
+        vpart = std::max(vpart, sizeof(double) * (size_t)G * nb * kVerifyMax * vc);
         trig = std::max(trig, sizeof(double) * 2 * ((size_t)g.Lx + g.Ly));
         table = std::max(table, sizeof(PointRec) * (size_t)G);
         part = std::max(part, sizeof(double) * rows * p.n_delta_pad * G);
@@ -254,7 +299,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     }
     p.off_d2 = 0;
     p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 2));
-    p.off_gtab = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
+    p.off_gtab = p.off_qtrig + align_up(sizeof(double) * kQTrig * (size_t)n_q);
     p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabN);
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
@@ -266,9 +311,13 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_etab = p.off_tpart + align_up(tpart);
     p.off_qlat = p.off_etab + align_up(etab);
     p.off_queue = p.off_qlat + align_up(sizeof(int) * 2 * (size_t)n_q);
-    p.off_rowmin = p.off_queue + align_up(sizeof(unsigned long long) * kQueues * kQueueStride);
+    p.off_rowmin = p.off_queue + align_up(sizeof(unsigned long long) * kMaxQueues * kQueueStride);
     // the minimum of every output row, for the global search
-    p.sweep_bytes = p.off_rowmin + align_up(sizeof(double) * (size_t)n_pts * p.nbq);
+    p.off_vcand = p.off_rowmin + align_up(sizeof(double) * (size_t)n_pts * p.nbq);
+    p.off_vcnt = p.off_vcand + align_up(sizeof(int) * vsets * kVerifyMax);
+    p.off_vthr = p.off_vcnt + align_up(sizeof(int) * vsets);
+    p.off_vpart = p.off_vthr + align_up(sizeof(double) * vsets);
+    p.sweep_bytes = p.off_vpart + align_up(vpart);
     return p;
 }
 
@@ -301,7 +350,7 @@ GradPlan plan_grad(const omega_point *pts, int n_pts, int nb)
         part = std::max(part, per_point * G);
     }
     p.off_qtrig = 0;
-    p.off_trig = align_up(sizeof(double) * 4 * (size_t)n_pts * nb);
+    p.off_trig = align_up(sizeof(double) * kQTrig * (size_t)n_pts * nb);
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.bytes = p.off_part + align_up(part);
@@ -350,6 +399,7 @@ int upload_points(const omega_point *pts, const int *idx, int G, PointRec *table
 // couplings and hoppings.
 struct ModelDesc {
     bool b3;
+    int eta_rel;     // form factor at the pair's relative momentum
     int nb;
     int list[3];
     double mu;
@@ -362,6 +412,7 @@ ModelDesc describe(const omega_model *m, int bands)
 {
     ModelDesc d{};
     d.b3 = false;
+    d.eta_rel = m->form == OMEGA_ETA_REL;
     d.nb = slot_bands(bands, d.list);
     d.mu = m->mu;
     for (int k = 0; k < 3; ++k)
@@ -374,6 +425,7 @@ ModelDesc describe3(const omega3_model *m, int bands)
 {
     ModelDesc d{};
     d.b3 = true;
+    d.eta_rel = m->form == OMEGA_ETA_REL;
     d.nb = slot_bands3(bands, d.list);
     d.mu = m->mu;
     for (int k = 0; k < 3; ++k)
@@ -386,10 +438,13 @@ ModelDesc describe3(const omega3_model *m, int bands)
 
 // Enqueue the sweep and row reduction of every point.  Omega goes to `grid`,
 // row minima to row_idx (optional).
+// With idx (the FP32-compensated argmin), every batch's minima are checked
+// in FP64 and written to idx / omin (see VerifyArgs).
 int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
                  const double *delta, int n_delta, const double *q, int n_q,
                  int precision, char *ws, double tie_rel,
-                 double *grid, int32_t *row_idx, hipStream_t s)
+                 double *grid, int32_t *row_idx, int32_t *idx, double *omin, const Launch &lo,
+                 hipStream_t s)
 {
     const int nb = md.nb;
     const GridPlan P = plan_grid(pts, n_pts, n_delta, n_q, nb, md.b3);
@@ -425,6 +480,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.nbq = P.nbq;
     a.n_delta_pad = P.n_delta_pad;
     a.d2 = d2;
+    a.eta_rel = md.eta_rel;
     a.q = q;
     a.qtrig = qtrig;
     a.trig = trig;
@@ -436,8 +492,10 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.tcnt = tcnt;
     a.tpart = tpart;
     a.n_dtiles = P.n_dtiles;
-    a.count = g_sweep_count;
+    a.count = lo.count;
     a.queue = queue;
+    a.n_queues = lo.n_queues;
+    a.blocks_per_cu = lo.blocks_per_cu;
     a.n_rows = 0;
 
     RowArgs r;
@@ -462,6 +520,24 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     r.nbq = P.nbq;
     r.omega = grid;
     r.row_idx = row_idx;
+
+    VerifyArgs v;
+    v.nb = nb;
+    v.n_q = n_q;
+    v.n_delta = n_delta;
+    v.delta = delta;
+    v.grid = grid;
+    v.rowmin = r.rowmin;
+    v.tie_rel = tie_rel;
+    v.d2c = d2 + P.n_delta_pad;
+    for (int k = 0; k < 3; ++k)
+        v.Vs[k] = md.V[k];
+    v.cand = (int *)(ws + P.off_vcand);
+    v.cnt = (int *)(ws + P.off_vcnt);
+    v.thr = (double *)(ws + P.off_vthr);
+    v.vpart = (double *)(ws + P.off_vpart);
+    v.idx = idx;
+    v.omin = omin;
 
     for (size_t gi = 0; gi < P.groups.size(); ++gi) {
         const Group &g = P.groups[gi];
@@ -490,17 +566,26 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
                 return rc;
             if (launch_series(a, G, precision == OMEGA_FP64, md.b3, s) != hipSuccess)
                 return OMEGA_E_HIP;
-            if (g_sweep_start && hipEventRecord(g_sweep_start, s) != hipSuccess)
+            const bool first = gi == 0 && b0 == 0;
+            const bool last = gi + 1 == P.groups.size() && b0 + G >= n;
+            if (first && lo.start && hipEventRecord(lo.start, s) != hipSuccess)
                 return OMEGA_E_HIP;
             hipError_t e = precision == OMEGA_FP64
                                ? launch_sweep_f64(a, P.td, P.n_dtiles, G, md.b3, g.hot, s)
                                : launch_sweep_f32c(a, P.td, P.n_dtiles, G, md.b3, g.hot, s);
             if (e != hipSuccess)
                 return OMEGA_E_HIP;
-            if (g_sweep_stop && hipEventRecord(g_sweep_stop, s) != hipSuccess)
+            if (last && lo.stop && hipEventRecord(lo.stop, s) != hipSuccess)
                 return OMEGA_E_HIP;
             if (launch_rows(r, G, s) != hipSuccess)
                 return OMEGA_E_HIP;
+            if (idx) {
+                v.sw = a;
+                v.n_k = r.n_k;
+                v.n_vchunks = P.vchunks[gi];
+                if (launch_verify(v, G, md.b3, s) != hipSuccess)
+                    return OMEGA_E_HIP;
+            }
         }
     }
     return OMEGA_OK;
@@ -517,13 +602,14 @@ int run_grid(const ModelDesc &md, const omega_point *pts, int n_pts, const doubl
     if (ws_bytes < plan_grid(pts, n_pts, n_delta, n_q, md.nb, md.b3).sweep_bytes)
         return OMEGA_E_WORKSPACE;
     return enqueue_grid(md, pts, n_pts, delta_dev, n_delta, q_dev, n_q, precision,
-                        (char *)ws_dev, 0.0, omega_dev, nullptr, (hipStream_t)stream);
+                        (char *)ws_dev, 0.0, omega_dev, nullptr, nullptr, nullptr, Launch(),
+                        (hipStream_t)stream);
 }
 
 int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const double *delta_dev,
                int n_delta, const double *q_dev, int n_q, int precision, double tie_rel,
                void *ws_dev, size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
-               int32_t *row_idx_dev, double *omega_dev, void *stream)
+               int32_t *row_idx_dev, double *omega_dev, const Launch &lo, void *stream)
 {
     if (!delta_dev || !q_dev || !idx_dev || !omin_dev || !ws_dev)
         return OMEGA_E_INVAL;
@@ -537,9 +623,12 @@ int run_argmin(const ModelDesc &md, const omega_point *pts, int n_pts, const dou
         return OMEGA_E_WORKSPACE;
     double *grid = omega_dev ? omega_dev : (double *)((char *)ws_dev + sweep);
     hipStream_t s = (hipStream_t)stream;
+    // FP32-compensated: each batch's minima are checked in FP64 on the way
+    const bool fp32c = precision == OMEGA_FP32_COMP;
     int rc = enqueue_grid(md, pts, n_pts, delta_dev, n_delta, q_dev, n_q, precision,
-                          (char *)ws_dev, tie_rel, grid, row_idx_dev, s);
-    if (rc != OMEGA_OK)
+                          (char *)ws_dev, tie_rel, grid, row_idx_dev, fp32c ? idx_dev : nullptr,
+                          fp32c ? omin_dev : nullptr, lo, s);
+    if (rc != OMEGA_OK || fp32c)
         return rc;
     ArgminArgs a;
     a.omega = grid;
@@ -583,7 +672,7 @@ ChiPlan plan_chi(const omega_point *pts, int n_pts, int n_q, int nb, bool b3)
     }
     p.off_trig = 0;
     p.off_qtrig = align_up(trig);
-    p.off_etab = p.off_qtrig + align_up(sizeof(double) * 4 * (size_t)n_q);
+    p.off_etab = p.off_qtrig + align_up(sizeof(double) * kQTrig * (size_t)n_q);
     p.off_qlat = p.off_etab + align_up(etab);
     p.off_part = p.off_qlat + (b3 ? align_up(sizeof(int) * 2 * (size_t)n_q) : 0);
     p.bytes = p.off_part + align_up(part);
@@ -659,6 +748,59 @@ int run_chi(const ModelDesc &md, const omega_point *pts, int n_pts, const double
     return OMEGA_OK;
 }
 
+// Sector and cycle structure of the LO problem of one point and one pair
+// momentum (m, n) on a lattice axis (see LoArgs); false if q is off the axes
+// or a cycle exceeds kLoMaxCycle modes.
+struct LoShape {
+    int along_y, Lc, Ls, s, g, n;
+    double w;   // sum_j |e^{iqR_j} + e^{-iqR_j}|^2 / N
+};
+
+int gcd_int(int a, int b)
+{
+    while (b) {
+        const int t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+bool lo_shape(const omega_point &pt, int m, int n, LoShape *o)
+{
+    if (m != 0 && n != 0)
+        return false;
+    LoShape r;
+    r.along_y = m == 0;
+    r.Lc = r.along_y ? pt.Ly : pt.Lx;
+    r.Ls = r.along_y ? pt.Lx : pt.Ly;
+    const long long idx = r.along_y ? n : m;
+    r.s = (int)(((idx % r.Lc) + r.Lc) % r.Lc);
+    const int two_s = (int)((2LL * r.s) % r.Lc);
+    r.g = two_s == 0 ? r.Lc : gcd_int(two_s, r.Lc);
+    r.n = 2 * r.Lc / r.g;
+    // the two waves coincide where 2q is a reciprocal lattice vector
+    r.w = two_s == 0 ? 4.0 : 2.0;
+    if (r.n > kLoMaxCycle || (long long)r.Ls * r.g > 0x7fffffffLL)
+        return false;
+    *o = r;
+    return true;
+}
+
+size_t lo_bytes(const omega_point *pts, int n_pts, int n_delta, const int32_t *q, int n_q,
+                int nb)
+{
+    size_t part = 0;
+    for (int p = 0; p < n_pts; ++p)
+        for (int iq = 0; iq < n_q; ++iq) {
+            LoShape sh;
+            if (!lo_shape(pts[p], q[2 * iq], q[2 * iq + 1], &sh))
+                return 0;
+            part = std::max(part, sizeof(double) * (size_t)nb * n_delta * sh.Ls * sh.g);
+        }
+    return align_up(part);
+}
+
 }  // namespace
 
 extern "C" {
@@ -696,12 +838,93 @@ int omega_argmin(const omega_model *model, const omega_point *pts, int n_pts,
                  double *omin_dev, int32_t *row_idx_dev, double *omega_dev,
                  void *stream)
 {
+    return omega_argmin_ex(model, pts, n_pts, delta_dev, n_delta, q_dev, n_q, bands, precision,
+                           tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev, row_idx_dev, omega_dev,
+                           nullptr, stream);
+}
+
+int omega_argmin_ex(const omega_model *model, const omega_point *pts, int n_pts,
+                    const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                    int bands, int precision, double tie_rel, void *ws_dev, size_t ws_bytes,
+                    int32_t *idx_dev, double *omin_dev, int32_t *row_idx_dev,
+                    double *omega_dev, const omega_launch *launch, void *stream)
+{
+    Launch lo;
     if (!model_ok(model) || !points_ok(pts, n_pts) ||
-        !sizes_ok(n_delta, n_q, bands, precision))
+        !sizes_ok(n_delta, n_q, bands, precision) || !resolve_launch(launch, &lo))
         return OMEGA_E_INVAL;
     return run_argmin(describe(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
                       precision, tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev, row_idx_dev,
-                      omega_dev, stream);
+                      omega_dev, lo, stream);
+}
+
+size_t omega_lo_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
+                                const int32_t *q_host, int n_q, int bands)
+{
+    if (!points_ok(pts, n_pts) || !q_host || n_q <= 0 || n_q > kMaxQ || n_delta <= 0 ||
+        n_delta > kMaxDelta || bands < 1 || bands > 3)
+        return 0;
+    return lo_bytes(pts, n_pts, n_delta, q_host, n_q, n_bands(bands));
+}
+
+int omega_lo_grid(const omega_model *model, const omega_point *pts, int n_pts,
+                  const double *delta_dev, int n_delta, const int32_t *q_host, int n_q,
+                  int bands, void *ws_dev, size_t ws_bytes, double *omega_dev, void *stream)
+{
+    if (!model_ok(model) || !points_ok(pts, n_pts) || !q_host || n_q <= 0 || n_q > kMaxQ ||
+        n_delta <= 0 || n_delta > kMaxDelta || bands < 1 || bands > 3 || !delta_dev ||
+        !omega_dev || !ws_dev)
+        return OMEGA_E_INVAL;
+    if (model->form != OMEGA_ETA_K)
+        return OMEGA_E_UNSUPPORTED;
+    int list[2];
+    const int nb = slot_bands(bands, list);
+    const size_t need = lo_bytes(pts, n_pts, n_delta, q_host, n_q, nb);
+    if (need == 0)
+        return OMEGA_E_UNSUPPORTED;   // q off the axes, or a cycle above kLoMaxCycle
+    if (ws_bytes < need)
+        return OMEGA_E_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    LoArgs a;
+    a.hop = make_hop(model);
+    band_signs(nb, list, a.eps);
+    a.mu = model->mu;
+    a.n_delta = n_delta;
+    a.delta = delta_dev;
+    a.part = (double *)ws_dev;
+    LoFinishArgs f;
+    f.part = a.part;
+    f.delta = delta_dev;
+    f.n_delta = n_delta;
+    f.nb = nb;
+    f.Vs[0] = model->V[list[0]];
+    f.Vs[1] = model->V[nb > 1 ? list[1] : list[0]];
+    f.slot_stride = (size_t)n_q * n_delta;
+    for (int p = 0; p < n_pts; ++p) {
+        a.h = pts[p].h;
+        a.T = pts[p].T;
+        a.Lx = pts[p].Lx;
+        a.Ly = pts[p].Ly;
+        for (int iq = 0; iq < n_q; ++iq) {
+            LoShape sh;
+            lo_shape(pts[p], q_host[2 * iq], q_host[2 * iq + 1], &sh);
+            a.along_y = sh.along_y;
+            a.Lc = sh.Lc;
+            a.Ls = sh.Ls;
+            a.s = sh.s;
+            a.g = sh.g;
+            a.n = sh.n;
+            if (launch_lo(a, nb, st) != hipSuccess)
+                return OMEGA_E_HIP;
+            f.n_parts = sh.Ls * sh.g;
+            f.n_k = (double)pts[p].Lx * pts[p].Ly;
+            f.w = sh.w;
+            f.omega = omega_dev + ((size_t)p * nb * n_q + iq) * n_delta;
+            if (launch_lo_finish(f, st) != hipSuccess)
+                return OMEGA_E_HIP;
+        }
+    }
+    return OMEGA_OK;
 }
 
 int omega3_bands(const omega3_model *model, int Lx, int Ly, void *ws_dev, size_t ws_bytes,
@@ -754,12 +977,25 @@ int omega3_argmin(const omega3_model *model, const omega_point *pts, int n_pts,
                   size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
                   int32_t *row_idx_dev, double *omega_dev, void *stream)
 {
+    return omega3_argmin_ex(model, pts, n_pts, delta_dev, n_delta, q_dev, n_q, bands,
+                            precision, tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev,
+                            row_idx_dev, omega_dev, nullptr, stream);
+}
+
+int omega3_argmin_ex(const omega3_model *model, const omega_point *pts, int n_pts,
+                     const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                     int bands, int precision, double tie_rel, void *ws_dev,
+                     size_t ws_bytes, int32_t *idx_dev, double *omin_dev,
+                     int32_t *row_idx_dev, double *omega_dev, const omega_launch *launch,
+                     void *stream)
+{
+    Launch lo;
     if (bands < 1 || bands > 7 || !model3_ok(model, bands) || !points_ok(pts, n_pts) ||
-        !sizes_ok(n_delta, n_q, 1, precision))
+        !sizes_ok(n_delta, n_q, 1, precision) || !resolve_launch(launch, &lo))
         return OMEGA_E_INVAL;
     return run_argmin(describe3(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
                       precision, tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev, row_idx_dev,
-                      omega_dev, stream);
+                      omega_dev, lo, stream);
 }
 
 int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
@@ -796,6 +1032,7 @@ int omega_grad(const omega_model *model, const omega_point *pts, int n_pts,
     a.delta = delta_dev;
     a.q = q_dev;
     a.qtrig = qtrig;
+    a.eta_rel = model->form == OMEGA_ETA_REL;
     a.trig = trig;
     a.part = part;
     GradFinishArgs f;
@@ -944,21 +1181,6 @@ const char *omega_strerror(int code)
     }
 }
 
-int omega_version(void) { return 3; }
-
-int omega_set_sweep_counter(unsigned long long *count_dev)
-{
-    g_sweep_count = count_dev;
-    return OMEGA_OK;
-}
-
-int omega_set_sweep_events(void *start_event, void *stop_event)
-{
-    if ((start_event == nullptr) != (stop_event == nullptr))
-        return OMEGA_E_INVAL;
-    g_sweep_start = (hipEvent_t)start_event;
-    g_sweep_stop = (hipEvent_t)stop_event;
-    return OMEGA_OK;
-}
+int omega_version(void) { return 4; }
 
 }  // extern "C"

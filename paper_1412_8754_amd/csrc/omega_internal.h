@@ -25,9 +25,16 @@ struct Hop3 {
     double eps0;
 };
 
-// Skip threshold of the thermal term: where |E|/T exceeds this,
-// T ln(1 + exp(-|E|/T)) < T * 2.4e-16 and the term is dropped.
-constexpr double kCutFp64 = 36.0;
+// Skip threshold of the thermal term of the grid sweeps: where |E|/T exceeds
+// this, T ln(1 + exp(-|E|/T)) < T e^-30 = 9.4e-14 T and the term is dropped.
+// Both branches of a momentum together move Omega by less than 1.9e-13 T
+// per momentum, i.e. by 1.9e-13 T N at most, one-signed: below 3e-13 of the
+// scale |Omega| >= 0.03 N of the E_+ band's rows (the smaller band) up to
+// T = 0.05, inside the 1e-12 parity bar.
+constexpr double kCutFp64 = 30.0;
+// The gradient sweep keeps the Fermi function to 2.3e-16: it drops the
+// thermal parts beyond 36 T.
+constexpr double kCutGrad = 36.0;
 // Same for the FP32 sweep: exp(-17) = 4.1e-8 is below the FP32 resolution of
 // the terms it would be added to.
 constexpr float kCutFp32 = 17.0f;
@@ -36,17 +43,17 @@ constexpr float kCutFp32 = 17.0f;
 // almost none is zero or on a tile series), in both precisions.
 constexpr double kInPlaceT = 0.005;
 
-// Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 36: entry N
+// Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 30: entry N
 // holds (G(a0), 1/(1 + e^a0)) at a0 = N / kGStep.
 constexpr int kGStep = 64;
-constexpr int kGTabN = 36 * kGStep + 1;
-static_assert(kCutFp64 == 36.0, "the thermal table ends at the FP64 cut");
+constexpr int kGTabN = 30 * kGStep + 1;
+static_assert(kCutFp64 == 30.0, "the thermal table ends at the FP64 cut");
 
 // Series path of the sweep.  With x = Delta^2, the centre x0 and half-width
 // hw of the call's Delta^2 range, R0 = sqrt(s^2 + x0 eta^2) and
 // z = (x - x0) eta^2 / R0^2, the Delta-dependent term is
 //   R - |d| = (R0 - |d|) + R0 sum_{n>=1} c_n z^n,  c_n = binomial(1/2, n).
-// Where A0 = |s| - |d| >= 36 T (R - |d| >= 36 T for every Delta: cold,
+// Where A0 = |s| - |d| >= 30 T (R - |d| >= 30 T for every Delta: cold,
 // positive, no thermal part) and hw eta^2 <= kSeriesRho R0^2 (so |z| <= 1/3),
 // it is summed over k through the moments C0 = sum (R0 - |d|) and
 // M_n = sum R0 (eta^2/R0^2)^n, n = 1..kSeriesTerms.  Since |c_n| decreases,
@@ -108,13 +115,13 @@ struct SeriesLevelRho {
 // Delta tile (the TD Delta of a sweep unit; x = Delta^2 in [x_lo, x_hi],
 // centre xc, half-width ht), a
 // direct term that is cold and positive over the whole tile
-// (R(x_lo) >= |d| + 36 T: R - |d| >= 36 T for every Delta of the tile, no
+// (R(x_lo) >= |d| + 30 T: R - |d| >= 30 T for every Delta of the tile, no
 // thermal part) has R - |d| = (Rc - |d|) + Rc sum_{n>=1} c_n z^n with
 // Rc^2 = s^2 + xc eta^2 and z = (x - xc) eta^2 / Rc^2.  Where
 // ht eta^2 <= kTileRho Rc^2 it is summed through kTileSlots moments per tile
 // (C0 = sum w (Rc - |d|), M_n = sum w Rc (eta^2/Rc^2)^n, n <= kTileTerms);
 // the truncation is below |c_16| 0.15^16 / 0.85 = 3.5e-16 of Rc.  Terms with
-// R(x_hi) <= |d| - 36 T are exactly zero over the tile.
+// R(x_hi) <= |d| - 30 T are exactly zero over the tile.
 constexpr double kTileRho = 0.15;
 constexpr int kTileTerms = 15;
 constexpr int kTileSlots = 16;
@@ -122,10 +129,12 @@ constexpr int kTileBatch = 64;   // Delta tiles per LDS batch of the rows kernel
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 
-// Work queues of the persistent sweeps: kQueues counters, each on its own
-// 256-byte line (one counter sustains about 80 device-scope atomics per
-// microsecond, eight on separate lines about 500).
+// Work queues of the persistent sweeps: kQueues counters by default (at most
+// kMaxQueues, a launch option), each on its own 256-byte line (one counter
+// sustains about 80 device-scope atomics per microsecond, eight on separate
+// lines about 500).
 constexpr int kQueues = 8;
+constexpr int kMaxQueues = 16;
 constexpr int kQueueStride = 32;   // unsigned long long
 constexpr int kTileEdge = 8;     // k tile of one wavefront: 8 x 8 momenta
 constexpr int kMaxChunkTiles = 256;   // k tiles of one sweep chunk, at most
@@ -150,6 +159,9 @@ struct PointPack {
 // Arguments of one Delta-sweep launch: a batch of G points of one lattice
 // size.  series_kernel runs on the grid (chunk, band*Q + nbq*g); the sweeps
 // take (chunk, Delta tile, band*Q + nbq*g) units from a work queue.
+// Doubles per pair momentum in the Q trig table (see qtrig_at).
+constexpr int kQTrig = 8;
+
 struct SweepArgs {
     Hop hop;
     double eps[2];       // two-band: band sign per output slot (-1: E_-, +1: E_+)
@@ -168,8 +180,9 @@ struct SweepArgs {
     int n_delta_pad;     // n_delta rounded up to the Delta tile
     const double *d2;    // [n_delta_pad + 2] Delta^2 (padding repeats the last),
                          // then centre and half-width of the Delta^2 range
+    int eta_rel;         // 1: form factor at the pair's relative momentum, eta(k - Q/2)
     const double *q;     // [n_q][2]
-    const double *qtrig; // [n_q][4] cos qx, sin qx, cos qy, sin qy
+    const double *qtrig; // [n_q][kQTrig] cos/sin of qx, qy, qx/2, qy/2
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
     const double2 *gtab; // [kGTabN] thermal table (FP64 sweeps; P(0) of the FP32-compensated series pass)
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
@@ -184,8 +197,10 @@ struct SweepArgs {
     int lcap;            // list capacity per wave: ceil(ceil(n_tiles/n_chunks)/4)
     unsigned long long *count;   // optional: per-Delta terms evaluated directly
     unsigned long long *queue;   // work-queue counters of the persistent sweeps,
-                                 // kQueues of them kQueueStride apart
+                                 // kMaxQueues of them kQueueStride apart
+    int n_queues;        // queues in use (1 for a grid of fewer workgroups)
     int n_rows;          // G * nbq rows of this launch
+    int blocks_per_cu;   // persistent grid: workgroups per CU (0: all that fit)
 };
 
 // Arguments of the per-row reduction / epilogue / row search: grid
@@ -222,6 +237,40 @@ struct ArgminArgs {
     double *omin;          // [n_set]
 };
 
+// FP64 check of the FP32-compensated search ("scan in low precision, verify
+// in double precision", Sec. 3.3).  Per (point, band) set of a batch, the
+// cells whose FP32-compensated Omega lies within twice the stated FP32 error
+// bound plus the tie band of the set's FP32 minimum are candidates for the
+// FP64 minimum: kVerifyMax of them with Delta != 0 (the lowest-valued ones
+// when there are more) are evaluated again in FP64, Delta = 0 cells are FP64
+// in both sweeps already, and the tie rule picks among the checked cells by
+// their FP64 values.  Grid pointers are indexed by output set.
+constexpr int kVerifyMax = 32;
+constexpr double kFp32RelBound = 1e-7;           // stated |dOmega| / |Omega| of the FP32 sweep
+constexpr int kFp32FloorSites = 64 * 64;        // below this, plus 2^-20 N |Delta|
+
+struct VerifyArgs {
+    SweepArgs sw;          // model, lattice tables and points of the batch
+    int nb, n_q, n_delta;
+    const double *delta;   // [n_delta]
+    const double *grid;    // [n_pts][nb][n_q][n_delta] FP32-compensated Omega
+    const double *rowmin;  // [n_pts][nb][n_q]
+    double tie_rel;
+    const double *d2c;     // centre and half-width of the Delta^2 range (max Delta^2 =
+                           // their sum), for the small-lattice floor 2^-20 N max|Delta|
+    double Vs[3];
+    double n_k;
+    int n_vchunks;         // momentum chunks of one candidate's FP64 sum
+    int *cand;             // [G*nb][kVerifyMax] cell index iq * n_delta + id
+    int *cnt;              // [G*nb] candidates (Delta != 0)
+    double *thr;           // [G*nb] candidate threshold
+    double *vpart;         // [G*nb][kVerifyMax][n_vchunks] chunk sums
+    int32_t *idx;          // [n_pts][nb][2]
+    double *omin;          // [n_pts][nb]
+};
+
+hipError_t launch_verify(const VerifyArgs &v, int G, bool b3, hipStream_t s);
+
 // Gradient sweep over a batch of G points of one lattice size: grid
 // (chunk, band slot, g); one (Delta, Q) per point and slot.
 struct GradArgs {
@@ -232,7 +281,8 @@ struct GradArgs {
     int Lx, Ly, TX, TY, n_tiles, n_chunks, nb;
     const double *delta;   // [n_pts][nb] (all points of the call)
     const double *q;       // [n_pts][nb][2]
-    const double *qtrig;   // [n_pts][nb][4] cos/sin of q
+    const double *qtrig;   // [n_pts][nb][kQTrig] cos/sin of q and q/2
+    int eta_rel;           // form factor eta(k - q/2)
     const double *trig;
     double *part;          // [G][nb][n_chunks][5]
 };
@@ -259,7 +309,7 @@ struct ChiArgs {
     int Lx, Ly;
     int n_q, n_chunks, span;   // span: momenta per chunk
     const double *trig;
-    const double *qtrig;  // [n_q][4]
+    const double *qtrig;  // [n_q][kQTrig]
     const double *etab;   // three-band table [3][Lx][Ly]
     const int *qlat;      // three-band: lattice index of q, or -1
     double *part;
@@ -304,5 +354,41 @@ hipError_t launch_rows(const RowArgs &a, int G, hipStream_t s);
 hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s);
 hipError_t launch_grad(const GradArgs &a, int G, hipStream_t s);
 hipError_t launch_grad_finish(const GradFinishArgs &a, int G, hipStream_t s);
+
+// LO pairing (two plane waves, q and -q, of equal amplitude) of one point and
+// one pair momentum q on a lattice axis.  The momentum across q labels Ls
+// independent sectors; in each, c_{k up} of the chain index j couples to the
+// holes d_{j -+ s} (d_p = c^+_{-p down}, s the lattice index of q along the
+// chain), so the 2 Lc Nambu modes of a sector fall into g = gcd(2s, Lc)
+// cycles of n = 2 Lc / g modes, each a periodic tridiagonal matrix.  Grid
+// (sector * g + cycle, Delta, band slot); one workgroup diagonalises one
+// cycle (cyclic Jacobi in LDS) and writes the sum of -T ln(1 + e^{-E/T})
+// over its eigenvalues plus xi_down of its spin-up momenta.
+constexpr int kLoMaxCycle = 128;   // largest cycle the LO kernel takes
+struct LoArgs {
+    Hop hop;
+    double eps[2];        // band sign per output slot
+    double mu, h, T;
+    int Lx, Ly;
+    int along_y;          // 1: q = (0, qy), chains along ky, sectors kx
+    int Lc, Ls;           // chain length, sectors
+    int s;                // lattice index of q along the chain, in [0, Lc)
+    int g, n;             // cycles per sector, modes per cycle
+    int n_delta;
+    const double *delta;
+    double *part;         // [nb][n_delta][Ls * g]
+};
+struct LoFinishArgs {
+    const double *part;
+    const double *delta;
+    int n_delta, nb, n_parts;
+    double n_k;           // Lx * Ly
+    double w;             // sum_j |e^{iqR_j} + e^{-iqR_j}|^2 / N: 2, or 4 where 2q = 0
+    double Vs[2];
+    double *omega;        // output row of (point, slot 0, q); slot b at + b * slot_stride
+    size_t slot_stride;
+};
+hipError_t launch_lo(const LoArgs &a, int nb, hipStream_t s);
+hipError_t launch_lo_finish(const LoFinishArgs &a, hipStream_t s);
 
 }  // namespace omega

@@ -128,7 +128,7 @@ __device__ __forceinline__ double log1p_small(double z)
 // p <= sigma <= G; checked against a long-double reference over [0, 36]:
 // 2.4e-13 relative and 3.1e-14 absolute at most, without bias.  With the
 // factor T and at most two such terms per momentum, Omega moves by less than
-// 1e-13 T per momentum.  The caller guarantees a < 36 (1 + 4 eps) (|E| < 36 T with T zero
+// 1e-13 T per momentum.  The caller guarantees a < 30 (1 + 4 eps) (|E| < 30 T with T zero
 // or normal), so N <= kGTabN - 1 and the table read stays in range.
 __device__ __forceinline__ double log1p_exp_tab(double a, const double2 *gt)
 {
@@ -281,14 +281,14 @@ __device__ __forceinline__ void wave_reduce_halving(double (&acc)[TD], int lane)
 // Point records of a batch, from kernel arguments into the workspace.
 // Also zeroes the work-queue counters of the persistent sweep (queue may be
 // null), which runs after it on the stream.
-static_assert(kQueues <= kFillMax, "fill_points_kernel zeroes the queues");
+static_assert(kMaxQueues <= kFillMax, "fill_points_kernel zeroes the queues");
 __global__ void fill_points_kernel(const PointPack pk, PointRec *dst,
                                    unsigned long long *queue)
 {
     const int t = threadIdx.x;
     if (t < pk.n)
         dst[t] = pk.rec[t];
-    if (queue && t < kQueues)
+    if (queue && t < kMaxQueues)
         queue[(size_t)t * kQueueStride] = 0ull;
 }
 
@@ -381,18 +381,26 @@ hipError_t launch_delta2(const double *delta, int n_delta, int n_delta_pad,
     return hipGetLastError();
 }
 
-// cos and sin of both components of n pair momenta, [n][4] =
-// (cos qx, sin qx, cos qy, sin qy), once per call.
+// cos and sin of both components of n pair momenta and of their halves,
+// [n][kQTrig] = (cos qx, sin qx, cos qy, sin qy, cos qx/2, sin qx/2,
+// cos qy/2, sin qy/2), once per call.
 __device__ __forceinline__ void qtrig_at(int t, const double *q, int n, double *out)
 {
     if (t < n) {
         double s, c;
+        double *o = out + (size_t)kQTrig * t;
         sincos(q[2 * t], &s, &c);
-        out[4 * t] = c;
-        out[4 * t + 1] = s;
+        o[0] = c;
+        o[1] = s;
         sincos(q[2 * t + 1], &s, &c);
-        out[4 * t + 2] = c;
-        out[4 * t + 3] = s;
+        o[2] = c;
+        o[3] = s;
+        sincos(0.5 * q[2 * t], &s, &c);
+        o[4] = c;
+        o[5] = s;
+        sincos(0.5 * q[2 * t + 1], &s, &c);
+        o[6] = c;
+        o[7] = s;
     }
 }
 
@@ -583,9 +591,11 @@ __device__ __forceinline__ double ldg(const double *base, unsigned idx)
 // is computed at Q - k, with cos/sin of Q - k by angle subtraction: (A.4) in
 // closed form for the two-band model, by diagonalising for the three-band
 // model.
+// The form factor is eta(k) = cos kx cos ky, or with a.eta_rel eta(k - Q/2)
+// = cos(kx - qx/2) cos(ky - qy/2) from cos/sin of Q/2 (angle subtraction).
 template <bool B3>
-__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int mx, int my, int i,
-                                       int j, unsigned rowk, double eps, double mu_up,
+__device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int iq, int mx, int my,
+                                       int i, int j, unsigned rowk, double eps, double mu_up,
                                        double mu_dn, double cqx, double sqx, double cqy,
                                        double sqy)
 {
@@ -613,6 +623,11 @@ __device__ __forceinline__ KQ kq_setup(const SweepArgs &a, int slot, int mx, int
             Eq = band_energy(a.hop, eps, cpx, spx, cpy, spy);
         else
             Eq = eig3_band(a.hop3, cpx, spx, cpy, spy, b);
+    }
+    if (a.eta_rel) {
+        const double *qh = a.qtrig + kQTrig * iq + 4;   // cos, sin of qx/2 and qy/2
+        return kq_from(Ek, Eq, mu_up, mu_dn, fma(cx, qh[0], sx * qh[1]),
+                       fma(cy, qh[2], sy * qh[3]));
     }
     return kq_from(Ek, Eq, mu_up, mu_dn, cx, cy);
 }
@@ -866,16 +881,16 @@ typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
 
 // Per-unit constants of the queued sweep (sweep_kernel), in LDS: the tile's
 // Delta^2 range [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T and
-// the cut 36 T.
+// the cut 30 T.
 enum {
     kUcXlo, kUcXhi, kUcXc, kUcHt, kUcMuUp, kUcMuDn, kUcT, kUcInvT, kUcCutT, kUnitConsts
 };
 
-// Work queues of the persistent sweeps: kQueues 64-bit counters in the
-// workspace, zeroed by fill_points_kernel before every batch.  Units are
-// (chunk, Delta tile, row).  The groups g = (row, chunk) are dealt out to
-// the queues, g = q mod nq going to queue q (nq = kQueues, 1 for a grid of
-// fewer workgroups), and a queue hands out the Delta tiles of one group
+// Work queues of the persistent sweeps: nq = a.n_queues 64-bit counters in
+// the workspace (kMaxQueues of them zeroed by fill_points_kernel before every
+// batch).  Units are (chunk, Delta tile, row).  The groups g = (row, chunk)
+// are dealt out to the queues, g = q mod nq going to queue q (1 queue for a
+// grid of fewer workgroups than queues), and a queue hands out the Delta tiles of one group
 // one after the other: the waves that take them run on one XCD at about the
 // same time and share that chunk's tile list and band-table entries in its
 // L2.  Queue q is served by the workgroups with blockIdx.x = q mod nq, so
@@ -884,9 +899,9 @@ enum {
 // the whole zone.  take_unit returns the next unit of queue q as {chunk,
 // Delta tile, row}, with row -1 once the queue is empty; a wave stops at the
 // first -1, so every wave ends.
-__device__ __forceinline__ int sweep_queues()
+__device__ __forceinline__ int sweep_queues(const SweepArgs &a)
 {
-    return gridDim.x < (unsigned)kQueues ? 1 : kQueues;
+    return gridDim.x < (unsigned)a.n_queues ? 1 : a.n_queues;
 }
 
 __device__ __forceinline__ int3 take_unit(const SweepArgs &a, int q, int nq)
@@ -950,8 +965,8 @@ void series_kernel(const SweepArgs a, int fp64)
     const double cutT = kCutFp64 * T;
     const double x0 = a.d2[a.n_delta_pad];
     const double hw = a.d2[a.n_delta_pad + 1];
-    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+    const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
+    const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
     const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
     const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
     // the wave's list, staged here and written out behind the lists of the
@@ -978,7 +993,7 @@ void series_kernel(const SweepArgs a, int fp64)
             const int j = tj * kTileEdge + lj;
             bool direct = false;
             if (in_layout<FD>(kr, i, j)) {
-                const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
+                const KQ r = kq_setup<B3>(a, slot, iq, qmx, qmy, i, j,
                                           (unsigned)(ti * kTileEdge) * (unsigned)a.Ly + liLy, eps,
                                           mu_up, mu_dn, cqx, sqx, cqy, sqy);
                 const double w = mirror_weight_t<FD>(kr, i, j, a.Lx, a.Ly);
@@ -1084,16 +1099,21 @@ hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStrea
 }
 
 // Workgroups of a persistent launch: as many as stay resident at once on the
-// current device, but no more than there are units.
+// current device (or blocks_per_cu of them per CU, if fewer), but no more
+// than there are units.
 template <typename K>
-static int persistent_blocks(K kernel, unsigned long long units)
+static int persistent_blocks(K kernel, unsigned long long units, int blocks_per_cu)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
         hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
         return -1;
-    const unsigned long long n = (unsigned long long)cus * (per_cu > 0 ? per_cu : 1);
+    if (per_cu < 1)
+        per_cu = 1;
+    if (blocks_per_cu > 0 && blocks_per_cu < per_cu)
+        per_cu = blocks_per_cu;
+    const unsigned long long n = (unsigned long long)cus * per_cu;
     return (int)(n < units ? n : units);
 }
 
@@ -1173,7 +1193,7 @@ __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float 
 
 // The per-Delta FP64 loop of one term: acc[t] += w P(Delta_t), with
 // P = max(x, 0) + T ln((1 + u1)(1 + u2)), x = R - |d|, u1 = e^-|x|/T,
-// u2 = e^-(R + |d|)/T (each thermal part skipped beyond the cut 36 T);
+// u2 = e^-(R + |d|)/T (each thermal part skipped beyond the cut 30 T);
 // s2p = s^2 (floored), Delta^2 from dp[0..TD] (dp[TD] only read ahead).
 template <int TD>
 __device__ __forceinline__ void f64_steps(double (&acc)[TD], double s2p, double m,
@@ -1246,7 +1266,7 @@ void sweep_kernel(const SweepArgs args)
     }
     __syncthreads();
     int n_direct = 0;
-    const int nq = sweep_queues();
+    const int nq = sweep_queues(args);
     const int q = (int)(blockIdx.x % (unsigned)nq);
     for (;;) {
         ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1267,8 +1287,8 @@ void sweep_kernel(const SweepArgs args)
         const double eps = slot ? a.eps[1] : a.eps[0];
         const double qy = a.q[2 * iq + 1];
         const KRange kr = k_range(a, a.q[2 * iq], qy, chunk);
-        const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-        const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+        const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
+        const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
         int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
         int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
         // held in scalar registers for the unit, so that the tile walk does
@@ -1349,7 +1369,7 @@ void sweep_kernel(const SweepArgs args)
             KQ r;
             double w = 0.0, Rc2 = 0.0;
             if ((mk >> lane) & 1ull) {
-                r = kq_setup<B3>(a, slot, qmx, qmy, i, j,
+                r = kq_setup<B3>(a, slot, iq, qmx, qmy, i, j,
                                  (unsigned)i * (unsigned)a.Ly,
                                  eps, cp[kUcMuUp], cp[kUcMuDn], cqx, sqx, cqy, sqy);
                 w = mirror_weight(kr, i, j, a.Lx, a.Ly);
@@ -1358,7 +1378,7 @@ void sweep_kernel(const SweepArgs args)
                 Rc2 = fma(cp[kUcXc], r.eta2, r.s2);
                 // cold and positive over the tile, and the tile series converges
                 tser = fma(x_lo, r.eta2, r.s2) >= up * up && ht * r.eta2 <= kTileRho * Rc2;
-                // exactly zero over the tile where R(x_hi) <= |d| - 36 T
+                // exactly zero over the tile where R(x_hi) <= |d| - 30 T
                 loop = !tser && !(dn > 0.0 && fma(x_hi, r.eta2, r.s2) <= dn * dn);
             }
             if (tser) {
@@ -1489,7 +1509,7 @@ static hipError_t launch_persistent(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_kernel<TD, B3, F32>, units);
+    const int blocks = persistent_blocks(sweep_kernel<TD, B3, F32>, units, a.blocks_per_cu);
     if (blocks <= 0)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_kernel<TD, B3, F32>), dim3(blocks), dim3(kBlock), 0, s, a);
@@ -1516,7 +1536,7 @@ void sweep_f64_hot_kernel(const SweepArgs args)
     __syncthreads();
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
-    const int nq = sweep_queues();
+    const int nq = sweep_queues(args);
     const int q = (int)(blockIdx.x % (unsigned)nq);
     for (;;) {
         ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1543,8 +1563,8 @@ void sweep_f64_hot_kernel(const SweepArgs args)
         const double T = pt.T;
         const double invT = T > 0.0 ? 1.0 / T : 0.0;
         const double cutT = kCutFp64 * T;
-        const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-        const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+        const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
+        const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
         const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
         const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
 
@@ -1577,7 +1597,7 @@ void sweep_f64_hot_kernel(const SweepArgs args)
             asm volatile("" : "+v"(zoff));
             n_direct += __popcll(mk);
             if ((mk >> lane) & 1ull) {
-                const KQ r = kq_setup<B3>(a, slot, qmx, qmy, i, j, (unsigned)i * (unsigned)a.Ly,
+                const KQ r = kq_setup<B3>(a, slot, iq, qmx, qmy, i, j, (unsigned)i * (unsigned)a.Ly,
                                           eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
                 // R^2 >= 1e-300 keeps the reciprocal square root finite
                 f64_steps<TD>(acc, r.s2 + 1e-300, r.m, r.eta2,
@@ -1601,7 +1621,7 @@ static hipError_t launch_persistent_f64_hot(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_f64_hot_kernel<TD, B3>, units);
+    const int blocks = persistent_blocks(sweep_f64_hot_kernel<TD, B3>, units, a.blocks_per_cu);
     if (blocks <= 0)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_f64_hot_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
@@ -1656,7 +1676,7 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
     __shared__ float2 d2s[4][TD + 1];
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
-    const int nq = sweep_queues();
+    const int nq = sweep_queues(args);
     const int q = (int)(blockIdx.x % (unsigned)nq);
     for (;;) {
         ConstArgs ap = (ConstArgs)__builtin_amdgcn_kernarg_segment_ptr();
@@ -1683,8 +1703,8 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
         const double T = pt.T;
         const double invT = T > 0.0 ? 1.0 / T : 0.0;
 
-        const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-        const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+        const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
+        const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
         const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
         const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
 
@@ -1723,7 +1743,7 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
             const float2 *dp = d2s[wave] + zoff;
             n_direct += __popcll(mk);
             if ((mk >> lane) & 1ull) {
-                const KQ q64 = kq_setup<B3>(a, slot, qmx, qmy, i, j,
+                const KQ q64 = kq_setup<B3>(a, slot, iq, qmx, qmy, i, j,
                                             (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
                                                 (unsigned)li * (unsigned)a.Ly,
                                             eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
@@ -1774,7 +1794,7 @@ static hipError_t launch_persistent_f32c_hot(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_f32c_hot_kernel<TD, B3>, units);
+    const int blocks = persistent_blocks(sweep_f32c_hot_kernel<TD, B3>, units, a.blocks_per_cu);
     if (blocks <= 0)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_f32c_hot_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
@@ -1852,8 +1872,8 @@ __global__ __launch_bounds__(kBlock) void chi_kernel(const ChiArgs a)
     const int pair = pq / a.n_q;
     const int iq = pq - pair * a.n_q;
     const int ia = pair / a.nb, ib = pair - (pair / a.nb) * a.nb;
-    const double cqx = a.qtrig[4 * iq], sqx = a.qtrig[4 * iq + 1];
-    const double cqy = a.qtrig[4 * iq + 2], sqy = a.qtrig[4 * iq + 3];
+    const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
+    const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
     // three-band: lattice index of q, read once (-1 off the lattice)
     int qmx = -1, qmy = -1;
     if constexpr (B3) {
@@ -2213,6 +2233,280 @@ hipError_t launch_argmin(const ArgminArgs &a, int n_set, hipStream_t s)
     return hipGetLastError();
 }
 
+// ------------------------------------------ FP64 check of the FP32 search
+
+__device__ int block_int_sum(int v, int *sh)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        sh[wave] = v;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// One workgroup per (point, band) set of the batch: the candidate threshold
+// and the candidate cells with Delta != 0 (see VerifyArgs).  Where more than
+// kVerifyMax cells lie under the threshold, the threshold is lowered by
+// bisection until at most kVerifyMax do (the lowest-valued cells stay), and
+// cells are taken in key order (iDelta, iq) up to the capacity.
+__global__ __launch_bounds__(kBlock) void verify_cand_kernel(const VerifyArgs v)
+{
+    const int sl = blockIdx.x;
+    const int g = sl / v.nb;
+    const int slot = sl - g * v.nb;
+    const size_t oset = (size_t)v.sw.pts[g].out * v.nb + slot;
+    const int ncell = v.n_q * v.n_delta;
+    const double *G = v.grid + oset * (size_t)ncell;
+    const double *rm = v.rowmin + oset * (size_t)v.n_q;
+    __shared__ double shd[4];
+    __shared__ int shi[4];
+    double best = __longlong_as_double(0x7ff8000000000000LL);
+    for (int iq = threadIdx.x; iq < v.n_q; iq += kBlock)
+        best = nan_min(best, rm[iq]);
+    best = block_nan_min(best, shd);
+    if (!(best == best)) {
+        if (threadIdx.x == 0) {
+            v.cnt[sl] = 0;
+            v.thr[sl] = best;
+        }
+        return;
+    }
+    const double ab = fabs(best);
+    const double floor_abs =
+        v.n_k < (double)kFp32FloorSites ? ldexp(v.n_k * sqrt(v.d2c[0] + v.d2c[1]), -20) : 0.0;
+    const double e = kFp32RelBound * ab + floor_abs;
+    // a cell in the FP64 tie band has an FP32 value at most best + 2e +
+    // tie_rel |best| (to first order; the factor covers the second)
+    const double thr = best + (2.0 * e + v.tie_rel * ab) * (1.0 + 1e-6);
+    auto count_le = [&](double t) {
+        int c = 0;
+        for (int cell = threadIdx.x; cell < ncell; cell += kBlock) {
+            const int iq = cell / v.n_delta;
+            const double D = v.delta[cell - iq * v.n_delta];
+            c += (D * D != 0.0 && G[cell] <= t) ? 1 : 0;
+        }
+        return block_int_sum(c, shi);
+    };
+    double t = thr;
+    if (count_le(thr) > kVerifyMax) {
+        double lo = best, hi = thr;
+        for (int it = 0; it < 64 && lo < hi; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (mid <= lo || mid >= hi)
+                break;
+            if (count_le(mid) <= kVerifyMax)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        t = lo;
+    }
+    // cells under t in key order (iDelta n_q + iq), up to the capacity
+    __shared__ int wcnt[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int total = 0;
+    for (int k0 = 0; k0 < ncell && total < kVerifyMax; k0 += kBlock) {
+        const int key = k0 + threadIdx.x;
+        int cell = 0;
+        bool take = false;
+        if (key < ncell) {
+            const int id = key / v.n_q;
+            const int iq = key - id * v.n_q;
+            const double D = v.delta[id];
+            cell = iq * v.n_delta + id;
+            take = D * D != 0.0 && G[cell] <= t;
+        }
+        const unsigned long long b = __ballot(take);
+        __syncthreads();
+        if (lane == 0)
+            wcnt[wave] = __popcll(b);
+        __syncthreads();
+        int at = total;
+        for (int w = 0; w < wave; ++w)
+            at += wcnt[w];
+        at += __popcll(b & ((1ull << lane) - 1ull));
+        if (take && at < kVerifyMax)
+            v.cand[(size_t)sl * kVerifyMax + at] = cell;
+        total += ((wcnt[0] + wcnt[1]) + wcnt[2]) + wcnt[3];
+    }
+    if (threadIdx.x == 0) {
+        v.cnt[sl] = total < kVerifyMax ? total : kVerifyMax;
+        v.thr[sl] = thr;
+    }
+}
+
+// FP64 sum over one momentum chunk of the Eq. (5) terms of one candidate:
+// units (set, candidate, chunk), grid-stride over all of them; units of
+// empty candidate slots are skipped.  Each term is evaluated in full (no
+// series, no table, no folding): the Delta-independent part minus
+// max(R - |d|, 0) + T [G(|R - |d||/T) + G((R + |d|)/T)], G(a) = ln(1 + e^-a).
+template <bool B3>
+__global__ __launch_bounds__(kBlock) void verify_eval_kernel(const VerifyArgs v, int n_units)
+{
+    const SweepArgs &a = v.sw;
+    const long long n = (long long)a.Lx * a.Ly;
+    const long long span = (n + v.n_vchunks - 1) / v.n_vchunks;
+    __shared__ double red[4];
+    for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int chunk = u % v.n_vchunks;
+        const int ks = u / v.n_vchunks;
+        const int sl = ks / kVerifyMax;
+        const int kc = ks - sl * kVerifyMax;
+        if (kc >= v.cnt[sl])
+            continue;
+        const int cell = v.cand[(size_t)sl * kVerifyMax + kc];
+        const int iq = cell / v.n_delta;
+        const int id = cell - iq * v.n_delta;
+        const int g = sl / v.nb;
+        const int slot = sl - g * v.nb;
+        const double eps = slot ? a.eps[1] : a.eps[0];
+        const PointRec pt = a.pts[g];
+        const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
+        const double T = pt.T;
+        const double invT = T > 0.0 ? 1.0 / T : 0.0;
+        const double D = v.delta[id];
+        const double D2 = D * D;
+        const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
+        const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
+        const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
+        const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
+        const long long k0 = (long long)chunk * span;
+        const long long k1 = k0 + span < n ? k0 + span : n;
+        double s = 0.0, c = 0.0;
+        for (long long kk = k0 + threadIdx.x; kk < k1; kk += kBlock) {
+            const int i = (int)(kk / a.Ly);
+            const int j = (int)(kk - (long long)i * a.Ly);
+            const KQ r = kq_setup<B3>(a, slot, iq, qmx, qmy, i, j, (unsigned)i * (unsigned)a.Ly,
+                                      eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
+            const double R = sqrt_rn(fma(D2, r.eta2, r.s2));
+            const double x = R - r.m;
+            double P = fmax(x, 0.0);
+            if (T > 0.0) {
+                const double a1 = fmin(fabs(x) * invT, 700.0);
+                const double a2 = fmin((R + r.m) * invT, 700.0);
+                P = fma(T, log1p_small(exp_nonpos(-a1)) + log1p_small(exp_nonpos(-a2)), P);
+            }
+            neumaier(s, c, r.base - P);
+        }
+        const double w = wave_sum(s + c);
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = w;
+        __syncthreads();
+        if (threadIdx.x == 0)
+            v.vpart[(size_t)ks * v.n_vchunks + chunk] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
+}
+
+// One wave per set: FP64 Omega of the candidates (fixed-order chunk sums
+// plus N (-2 Delta^2 / V)), with the Delta = 0 cells under the threshold at
+// their grid values, then the tie rule over these checked cells.
+__global__ __launch_bounds__(64) void verify_pick_kernel(const VerifyArgs v)
+{
+    const int sl = blockIdx.x;
+    const int g = sl / v.nb;
+    const int slot = sl - g * v.nb;
+    const size_t oset = (size_t)v.sw.pts[g].out * v.nb + slot;
+    const double *G = v.grid + oset * (size_t)v.n_q * v.n_delta;
+    const int lane = threadIdx.x;
+    const int cnt = v.cnt[sl];
+    const double thr = v.thr[sl];
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    double val = nan;
+    int key = 0x7fffffff;
+    if (lane < cnt) {
+        const int cell = v.cand[(size_t)sl * kVerifyMax + lane];
+        const int iq = cell / v.n_delta;
+        const int id = cell - iq * v.n_delta;
+        const double D = v.delta[id];
+        val = ordered_sum(v.vpart + ((size_t)sl * kVerifyMax + lane) * v.n_vchunks, 1,
+                          v.n_vchunks) +
+              v.n_k * (-2.0 * D * D / v.Vs[slot]);
+        key = id * v.n_q + iq;
+    }
+    // the lowest checked value: candidates, then the Delta = 0 cells
+    double best = val;
+    for (int id = 0; id < v.n_delta; ++id) {
+        const double D = v.delta[id];
+        if (D * D != 0.0)
+            continue;
+        for (int iq = lane; iq < v.n_q; iq += 64) {
+            const double x = G[(size_t)iq * v.n_delta + id];
+            if (x <= thr)
+                best = nan_min(best, x);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        best = nan_min(best, __shfl_xor(best, off, 64));
+    int pick = 0x7fffffff;
+    double pv = nan;
+    if (best == best) {
+        const double t64 = tie_threshold(best, v.tie_rel);
+        if (key != 0x7fffffff && val <= t64) {
+            pick = key;
+            pv = val;
+        }
+        for (int id = 0; id < v.n_delta; ++id) {
+            const double D = v.delta[id];
+            if (D * D != 0.0)
+                continue;
+            for (int iq = lane; iq < v.n_q; iq += 64) {
+                const double x = G[(size_t)iq * v.n_delta + id];
+                const int k = id * v.n_q + iq;
+                if (x <= thr && x <= t64 && k < pick) {
+                    pick = k;
+                    pv = x;
+                }
+            }
+        }
+    }
+    int m = pick;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const int o = __shfl_xor(m, off, 64);
+        m = o < m ? o : m;
+    }
+    if (m == 0x7fffffff) {
+        if (lane == 0) {
+            v.idx[2 * oset] = -1;
+            v.idx[2 * oset + 1] = -1;
+            v.omin[oset] = nan;
+        }
+    } else if (pick == m) {
+        // one lane holds the smallest key (keys of different cells differ)
+        v.idx[2 * oset] = m / v.n_q;
+        v.idx[2 * oset + 1] = m % v.n_q;
+        v.omin[oset] = pv;
+    }
+}
+
+hipError_t launch_verify(const VerifyArgs &v, int G, bool b3, hipStream_t s)
+{
+    const int sets = G * v.nb;
+    hipLaunchKernelGGL(verify_cand_kernel, dim3(sets), dim3(kBlock), 0, s, v);
+    if (hipGetLastError() != hipSuccess)
+        return hipErrorLaunchFailure;
+    const long long units = (long long)sets * kVerifyMax * v.n_vchunks;
+    if (units > 0x7fffffffLL)
+        return hipErrorInvalidValue;
+    const int blocks = (int)(units < 4096 ? units : 4096);
+    if (b3)
+        hipLaunchKernelGGL(verify_eval_kernel<true>, dim3(blocks), dim3(kBlock), 0, s, v,
+                           (int)units);
+    else
+        hipLaunchKernelGGL(verify_eval_kernel<false>, dim3(blocks), dim3(kBlock), 0, s, v,
+                           (int)units);
+    if (hipGetLastError() != hipSuccess)
+        return hipErrorLaunchFailure;
+    hipLaunchKernelGGL(verify_pick_kernel, dim3(sets), dim3(64), 0, s, v);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ gradient
 
 // Gradient of (A.4) at p from cos/sin of its components; the non-smooth part
@@ -2279,10 +2573,10 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
     const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
-    const double cutT = kCutFp64 * T;
+    const double cutT = kCutGrad * T;
     const double D = a.delta[io];
-    const double cqx = a.qtrig[4 * io], sqx = a.qtrig[4 * io + 1];
-    const double cqy = a.qtrig[4 * io + 2], sqy = a.qtrig[4 * io + 3];
+    const double cqx = a.qtrig[kQTrig * io], sqx = a.qtrig[kQTrig * io + 1];
+    const double cqy = a.qtrig[kQTrig * io + 2], sqy = a.qtrig[kQTrig * io + 3];
     const double *cxt = a.trig, *sxt = a.trig + a.Lx;
     const double *cyt = a.trig + 2 * a.Lx, *syt = cyt + a.Ly;
     double s_[5] = {0, 0, 0, 0, 0}, c_[5] = {0, 0, 0, 0, 0};
@@ -2304,7 +2598,16 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
             band_grad(a.hop, eps, cpx, spx, cpy, spy, Eq, bx, by);
             double up = Ek - mu_up, dn = Eq - mu_dn;
             double s = 0.5 * (up + dn), d = 0.5 * (up - dn);
-            double eta = cx * cy;
+            // form factor and, at the relative momentum, its q derivatives
+            double ex = cx, ey = cy, dex = 0.0, dey = 0.0;
+            if (a.eta_rel) {
+                const double *qh = a.qtrig + kQTrig * io + 4;
+                ex = fma(cx, qh[0], sx * qh[1]);    // cos(kx - qx/2)
+                ey = fma(cy, qh[2], sy * qh[3]);
+                dex = 0.5 * fma(sx, qh[0], -(cx * qh[1])) * ey;   // sin(kx - qx/2) ey / 2
+                dey = 0.5 * ex * fma(sy, qh[2], -(cy * qh[3]));
+            }
+            double eta = ex * ey;
             double gap = D * eta;
             double R = sqrt_rn(fma(s, s, gap * gap));
             double Ep = d + R, Em = d - R;
@@ -2317,8 +2620,10 @@ __global__ __launch_bounds__(kBlock) void grad_kernel(const GradArgs a)
             double w = 0.5 * fp * (sr - 1.0) - 0.5 * fm * (sr + 1.0);
             neumaier(s_[0], c_[0], (tp.sp + tm.sp) + (Ek - mu_dn));
             neumaier(s_[1], c_[1], dr * (fp - fm));
-            neumaier(s_[2], c_[2], bx * w);
-            neumaier(s_[3], c_[3], by * w);
+            // dOmega_k / d eta = Delta (gap / R) (f+ - f-), through deta/dq
+            const double ge = D * gap * rR * (fp - fm);
+            neumaier(s_[2], c_[2], fma(ge, dex, bx * w));
+            neumaier(s_[3], c_[3], fma(ge, dey, by * w));
             neumaier(s_[4], c_[4], sr * (fm - fp));
         }
     }
@@ -2379,6 +2684,203 @@ __global__ void grad_finish_kernel(const GradFinishArgs a)
 hipError_t launch_grad_finish(const GradFinishArgs &a, int G, hipStream_t s)
 {
     hipLaunchKernelGGL(grad_finish_kernel, dim3(a.nb, G), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ LO pairing
+
+// One cycle of an LO sector (see LoArgs): the n x n matrix in LDS (row
+// stride n + 1), cyclic Jacobi with the round-robin ordering (n/2 disjoint
+// rotations per step, n - 1 steps per sweep; backward stable, eigenvalue
+// errors of order 1e-16 of the matrix norm) until the off-diagonal part
+// falls below 1e-32 of the whole (squared Frobenius norms), then the thermal
+// sum over the diagonal.  Nodes along the cycle: 2t is c_{(r - 2ts) mod Lc}
+// (diagonal E - mu - h), 2t + 1 is d_{(r - (2t+1)s) mod Lc} (diagonal
+// -(E - mu + h)); node 2t couples to its two neighbours with Delta eta of
+// its own momentum, node 2t + 1 to node 2t + 2 with Delta eta of that one's.
+template <int NMAX>
+__global__ __launch_bounds__(kBlock) void lo_cycle_kernel(const LoArgs a)
+{
+    constexpr int LD = NMAX + 1;
+    __shared__ double A[NMAX * LD];
+    __shared__ double cs[NMAX / 2][2];
+    __shared__ int pq[NMAX / 2][2];
+    __shared__ double red[4];
+    const int n = a.n;
+    const int sector = blockIdx.x / a.g;
+    const int r = blockIdx.x - sector * a.g;
+    const int id = blockIdx.y;
+    const int slot = blockIdx.z;
+    const double eps = slot ? a.eps[1] : a.eps[0];
+    const double D = a.delta[id];
+    const int tid = threadIdx.x;
+    double ssec, csec;
+    sincospi(2.0 * sector / a.Ls, &ssec, &csec);
+    for (int x = tid; x < n * LD; x += kBlock)
+        A[x] = 0.0;
+    __syncthreads();
+    // diagonal, couplings, and xi_down of the cycle's spin-up momenta
+    double cdn = 0.0;
+    for (int t = tid; t < n / 2; t += kBlock) {
+        const int jc = (int)(((long long)r - 2LL * t * a.s) % a.Lc + a.Lc) % a.Lc;
+        const int jd = (int)(((long long)r - (2LL * t + 1) * a.s) % a.Lc + a.Lc) % a.Lc;
+        const int jn = (int)(((long long)r - (2LL * t + 2) * a.s) % a.Lc + a.Lc) % a.Lc;
+        double sc, cc, sd, cd, sn, cn;
+        sincospi(2.0 * jc / a.Lc, &sc, &cc);
+        sincospi(2.0 * jd / a.Lc, &sd, &cd);
+        sincospi(2.0 * jn / a.Lc, &sn, &cn);
+        // (kx, ky) of a chain index: the chain runs along ky when along_y
+        const double Ec = a.along_y ? band_energy(a.hop, eps, csec, ssec, cc, sc)
+                                    : band_energy(a.hop, eps, cc, sc, csec, ssec);
+        const double Ed = a.along_y ? band_energy(a.hop, eps, csec, ssec, cd, sd)
+                                    : band_energy(a.hop, eps, cd, sd, csec, ssec);
+        const double eta_c = csec * cc, eta_n = csec * cn;
+        A[(2 * t) * LD + 2 * t] = Ec - (a.mu + a.h);
+        A[(2 * t + 1) * LD + 2 * t + 1] = -(Ed - (a.mu - a.h));
+        cdn += Ec - (a.mu - a.h);
+        if (n > 2) {
+            const int u = (2 * t + 2) % n;
+            A[(2 * t) * LD + 2 * t + 1] = D * eta_c;
+            A[(2 * t + 1) * LD + 2 * t] = D * eta_c;
+            A[(2 * t + 1) * LD + u] = D * eta_n;
+            A[u * LD + 2 * t + 1] = D * eta_n;
+        } else {
+            // both waves join the same two modes (2q = 0)
+            A[1] = 2.0 * D * eta_c;
+            A[LD] = 2.0 * D * eta_c;
+        }
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        // off-diagonal against total squared Frobenius norm
+        double off = 0.0, tot = 0.0;
+        for (int x = tid; x < n * n; x += kBlock) {
+            const int i = x / n, j = x - (x / n) * n;
+            const double v = A[i * LD + j];
+            tot += v * v;
+            off += i != j ? v * v : 0.0;
+        }
+        off = wave_sum(off);
+        tot = wave_sum(tot);
+        __shared__ double nrm[4][2];
+        if ((tid & 63) == 0) {
+            nrm[tid >> 6][0] = off;
+            nrm[tid >> 6][1] = tot;
+        }
+        __syncthreads();
+        const double offs = ((nrm[0][0] + nrm[1][0]) + nrm[2][0]) + nrm[3][0];
+        const double tots = ((nrm[0][1] + nrm[1][1]) + nrm[2][1]) + nrm[3][1];
+        __syncthreads();
+        if (!(offs > 1e-32 * tots))
+            break;
+        for (int step = 0; step < n - 1; ++step) {
+            // round robin: mode n - 1 meets mode step, (step + i, step - i) mod n - 1
+            for (int i = tid; i < n / 2; i += kBlock) {
+                int p, q;
+                if (i == 0) {
+                    p = step;
+                    q = n - 1;
+                } else {
+                    p = (step + i) % (n - 1);
+                    q = (step - i + (n - 1)) % (n - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                const double app = A[p * LD + p], aqq = A[q * LD + q], apq = A[p * LD + q];
+                double c = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    const double th = (aqq - app) / (2.0 * apq);
+                    const double t = copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+                    c = 1.0 / sqrt(fma(t, t, 1.0));
+                    sn = t * c;
+                }
+                cs[i][0] = c;
+                cs[i][1] = sn;
+                pq[i][0] = p;
+                pq[i][1] = q;
+            }
+            __syncthreads();
+            // rows p, q: (J^T A)
+            for (int x = tid; x < (n / 2) * n; x += kBlock) {
+                const int i = x / n, j = x - (x / n) * n;
+                const int p = pq[i][0], q = pq[i][1];
+                const double c = cs[i][0], sn = cs[i][1];
+                const double ap = A[p * LD + j], aq = A[q * LD + j];
+                A[p * LD + j] = c * ap - sn * aq;
+                A[q * LD + j] = sn * ap + c * aq;
+            }
+            __syncthreads();
+            // columns p, q: (J^T A) J
+            for (int x = tid; x < (n / 2) * n; x += kBlock) {
+                const int i = x / n, j = x - (x / n) * n;
+                const int p = pq[i][0], q = pq[i][1];
+                const double c = cs[i][0], sn = cs[i][1];
+                const double ap = A[j * LD + p], aq = A[j * LD + q];
+                A[j * LD + p] = c * ap - sn * aq;
+                A[j * LD + q] = sn * ap + c * aq;
+            }
+            __syncthreads();
+            for (int i = tid; i < n / 2; i += kBlock) {
+                const int p = pq[i][0], q = pq[i][1];
+                A[p * LD + q] = 0.0;
+                A[q * LD + p] = 0.0;
+            }
+            __syncthreads();
+        }
+    }
+    // -T ln(1 + e^{-E/T}) over the eigenvalues, as min(E, 0) - T log1p(e^{-|E|/T})
+    double sum = cdn, cmp = 0.0;
+    const double invT = a.T > 0.0 ? 1.0 / a.T : 0.0;
+    for (int i = tid; i < n; i += kBlock) {
+        const double E = A[i * LD + i];
+        double v = fmin(E, 0.0);
+        if (a.T > 0.0)
+            v -= a.T * log1p_small(exp_nonpos(-fmin(fabs(E) * invT, 700.0)));
+        neumaier(sum, cmp, v);
+    }
+    const double w = wave_sum(sum + cmp);
+    if ((tid & 63) == 0)
+        red[tid >> 6] = w;
+    __syncthreads();
+    if (tid == 0)
+        a.part[((size_t)slot * a.n_delta + id) * ((size_t)a.Ls * a.g) + blockIdx.x] =
+            ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+hipError_t launch_lo(const LoArgs &a, int nb, hipStream_t s)
+{
+    const dim3 grid(a.Ls * a.g, a.n_delta, nb);
+    if (a.n <= 32)
+        hipLaunchKernelGGL(lo_cycle_kernel<32>, grid, dim3(kBlock), 0, s, a);
+    else if (a.n <= 64)
+        hipLaunchKernelGGL(lo_cycle_kernel<64>, grid, dim3(kBlock), 0, s, a);
+    else if (a.n <= kLoMaxCycle)
+        hipLaunchKernelGGL(lo_cycle_kernel<kLoMaxCycle>, grid, dim3(kBlock), 0, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// Fixed-order sum of the cycle partials plus -(2/V) sum_j |Delta(R_j)|^2 =
+// -2 N w Delta^2 / V: one thread per (band slot, Delta).
+__global__ void lo_finish_kernel(const LoFinishArgs a)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.nb * a.n_delta)
+        return;
+    const int slot = t / a.n_delta, id = t - (t / a.n_delta) * a.n_delta;
+    const double D = a.delta[id];
+    const double v = ordered_sum(a.part + (size_t)t * a.n_parts, 1, a.n_parts);
+    a.omega[slot * a.slot_stride + id] = v + a.n_k * (-2.0 * a.w * D * D / a.Vs[slot]);
+}
+
+hipError_t launch_lo_finish(const LoFinishArgs &a, hipStream_t s)
+{
+    const int n = a.nb * a.n_delta;
+    hipLaunchKernelGGL(lo_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@
 
 int main(void)
 {
-    CHECK(omega_version() == 3);
+    CHECK(omega_version() == 4);
     CHECK(strcmp(omega_strerror(OMEGA_OK), "success") == 0);
     CHECK(strcmp(omega_strerror(OMEGA_E_WORKSPACE), "workspace too small") == 0);
 
@@ -45,12 +45,16 @@ int main(void)
     CHECK(omega_chi_workspace_bytes(&pt, 1, 4, OMEGA_BAND_BOTH) > 0);
 
     /* host-side validation fails before anything is enqueued */
-    omega_model m = {-1.0, 1.3, -0.85, -0.85, 1.54, {-16.0, -7.5}};
+    omega_model m = {-1.0, 1.3, -0.85, -0.85, 1.54, {-16.0, -7.5}, OMEGA_ETA_K, 0};
     void *fake = (void *)0x1000;
     CHECK(omega_grid(&m, &pt, 1, fake, 32, fake, 4, 0, OMEGA_FP64, fake, ws, fake, NULL) ==
           OMEGA_E_INVAL);
     CHECK(omega_grid(&m, &pt, 1, fake, 32, fake, 4, OMEGA_BAND_BOTH, OMEGA_FP64, fake, 16,
                      fake, NULL) == OMEGA_E_WORKSPACE);
+    m.form = 2;   /* no such form factor */
+    CHECK(omega_grid(&m, &pt, 1, fake, 32, fake, 4, OMEGA_BAND_BOTH, OMEGA_FP64, fake, ws,
+                     fake, NULL) == OMEGA_E_INVAL);
+    m.form = OMEGA_ETA_REL;
     m.V[1] = 0.0;
     CHECK(omega_grid(&m, &pt, 1, fake, 32, fake, 4, OMEGA_BAND_BOTH, OMEGA_FP64, fake, ws,
                      fake, NULL) == OMEGA_E_INVAL);

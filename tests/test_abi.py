@@ -33,7 +33,7 @@ def test_strerror_and_version():
     assert _abi.strerror(_abi.OMEGA_OK) == "success"
     assert _abi.strerror(_abi.OMEGA_E_WORKSPACE) == "workspace too small"
     assert _abi.strerror(12345) == "unknown error code"
-    assert _abi.load().omega_version() == 3
+    assert _abi.load().omega_version() == 4
 
 
 def _ws(pts, nd=8, nq=3, bands=3, prec=0, grad=0):
@@ -128,6 +128,18 @@ def test_argmin_and_grad_validation_errors():
                         FAKE, None) == _abi.OMEGA_E_INVAL
     assert L.omega_grad(ctypes.byref(m), p, 1, FAKE, FAKE, 3, FAKE, 8, FAKE, FAKE, FAKE,
                         FAKE, None) == _abi.OMEGA_E_WORKSPACE
+
+
+def test_form_factor_field_is_validated():
+    # a model with no such form factor is rejected before anything is enqueued
+    m = _abi.make_model(dict(W.DEFAULT_MODEL, form=2))
+    L = _abi.load()
+    p = _abi.make_points([(0.0, 0.01, 16, 16)])
+    assert L.omega_grid(ctypes.byref(m), p, 1, FAKE, 8, FAKE, 3, 3, 0, FAKE, 1 << 40, FAKE,
+                        None) == _abi.OMEGA_E_INVAL
+    m3 = _abi.make_model3(dict(W.DAGHOFER_MODEL, form=-1))
+    assert L.omega3_grid(ctypes.byref(m3), p, 1, FAKE, 8, FAKE, 3, 7, 0, FAKE, 1 << 40, FAKE,
+                         None) == _abi.OMEGA_E_INVAL
 
 
 def _grid3(model=None, pts=None, delta=FAKE, nd=8, q=FAKE, nq=3, bands=7, prec=0, ws=FAKE,

@@ -148,13 +148,14 @@ def test_captured_graph_replays_match_eager():
 
 def test_phase_diagram_fp32c_minima_match_fp64():
     """16 x 16 (h, T) points at L = 256 (h up to 0.4, T up to 0.05): the
-    FP32-compensated search picks the FP64 minimum, except at near-ties where
-    its choice is within its own error bound of the FP64 minimum."""
+    FP32-compensated search returns the FP64 global minimum at every point
+    and band (its candidates within the FP32 error band are re-evaluated in
+    FP64 before the tie rule picks one)."""
     cfg = W.phase_config(16, 16, fixed_L=256)
     pts, delta, q = cfg["pts"], cfg["delta"], cfg["q"]
     say(f"phase diagram {len(pts)} points at L=256, FP64 vs FP32c")
-    idx64, _, _, om64 = api.argmin(M, pts, delta, q, 3, OMEGA_FP64)
-    idx32, _, _, om32 = api.argmin(M, pts, delta, q, 3, OMEGA_FP32_COMP)
+    idx64, omin64, _, om64 = api.argmin(M, pts, delta, q, 3, OMEGA_FP64)
+    idx32, omin32, _, om32 = api.argmin(M, pts, delta, q, 3, OMEGA_FP32_COMP)
     torch.cuda.synchronize()
     idx64, idx32 = idx64.cpu().numpy(), idx32.cpu().numpy()
     om64, om32 = om64.cpu().numpy(), om32.cpu().numpy()
@@ -162,9 +163,5 @@ def test_phase_diagram_fp32c_minima_match_fp64():
     diff = np.argwhere((idx64 != idx32).any(axis=-1))
     say(f"max rel {rel:.2e}; {len(diff)} of {idx64.shape[0] * 2} minima differ")
     assert rel <= 1e-7
-    for p, b in diff:
-        g = om64[p, b]
-        best = g[idx64[p, b, 1], idx64[p, b, 0]]
-        alt = g[idx32[p, b, 1], idx32[p, b, 0]]
-        assert alt - best <= 2e-7 * abs(best), (p, b, alt, best)
-    assert len(diff) <= 0.05 * idx64.shape[0] * 2
+    assert len(diff) == 0, diff.tolist()
+    np.testing.assert_allclose(omin32.cpu().numpy(), omin64.cpu().numpy(), rtol=1e-12, atol=0)

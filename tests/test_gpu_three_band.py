@@ -3,10 +3,10 @@
 The library tabulates the eigenvalues of the App. B matrix per lattice (cyclic
 Jacobi in FP64) and reads E(Q - k) from the table for lattice Q, diagonalising
 at Q - k otherwise; the oracle diagonalises every momentum with numpy's
-eigvalsh.  Tolerances as for the two-band model: FP64 1e-12 relative (plus a
-1e-13 N floor), FP32-compensated 1e-7 relative plus 1e-8 N + 2^-20 N Delta
-(the FP32 part of each term, P_k(Delta) - P_k(0), is at most 2 Delta),
-argmin indices identical.
+eigvalsh.  Tolerances as for the two-band model (parity_tol): FP64 1e-12
+relative (plus a 1e-13 N floor), FP32-compensated 1e-7 relative, with a
+2^-20 N Delta floor on lattices below 64 x 64 only (the FP32 part of each
+term, P_k(Delta) - P_k(0), is at most 2 Delta); argmin indices identical.
 """
 import math
 import sys
@@ -20,6 +20,7 @@ import oracle  # noqa: E402
 from oracle import three_band as tb  # noqa: E402
 from paper_1412_8754_amd import OMEGA_FP32_COMP, OMEGA_FP64, api  # noqa: E402
 from paper_1412_8754_amd import workloads as W  # noqa: E402
+from parity_tol import assert_close as _close  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 M3 = W.DAGHOFER_MODEL
@@ -36,16 +37,8 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def assert_close(got, ref, pts, rel=1e-12, floor=1e-13, delta=None, dfloor=0.0):
-    N = np.array([p[2] * p[3] for p in pts], np.float64).reshape((-1,) + (1,) * (ref.ndim - 1))
-    err = np.abs(got - ref)
-    tol = rel * np.abs(ref) + floor * N
-    if dfloor:
-        tol = tol + dfloor * N * np.abs(np.asarray(delta, dtype=np.float64))
-    bad = err > tol
-    worst = np.max(err / (np.abs(ref) + 1e-300))
-    assert not bad.any(), f"{bad.sum()} mismatches, worst rel {worst:.3e}"
-    return worst
+def assert_close(got, ref, pts, fp32c=False, delta=None):
+    return _close(got, ref, pts, fp32c=fp32c, delta=delta)
 
 
 def run3(pts, delta, q, bands, prec=OMEGA_FP64):
@@ -75,10 +68,9 @@ def test_three_band_grid_lattice_and_off_lattice_q():
     q = np.array([[0.0, 0.0], [2 * np.pi / 24, 0.0], [0.1, 0.05],
                   [2 * np.pi * 3 / 16, 2 * np.pi * 2 / 16], [2 * np.pi / 24, 2 * np.pi / 20]])
     ref = tb.omega_grid(M3, pts, delta, q, tb.BAND_ALL)
-    for prec, rel, floor, dfloor in ((OMEGA_FP64, 1e-12, 1e-13, 0.0),
-                                     (OMEGA_FP32_COMP, 1e-7, 1e-8, 2.0 ** -20)):
+    for prec in (OMEGA_FP64, OMEGA_FP32_COMP):
         idx, omin, rows, om = run3(pts, delta, q, 7, prec)
-        worst = assert_close(om, ref, pts, rel=rel, floor=floor, delta=delta, dfloor=dfloor)
+        worst = assert_close(om, ref, pts, prec == OMEGA_FP32_COMP, delta)
         say(f"three-band grid prec={prec}: worst rel {worst:.3e}")
         if prec == OMEGA_FP64:
             ridx, romin, rrows = oracle.argmin_grid(ref)
@@ -112,6 +104,13 @@ def test_three_band_workload_sampled_rows():
     np.testing.assert_array_equal(rows[:, :, pick], rr)
     # every band has its minimum at Delta > 0 here (V puts them inside the range)
     assert (idx[0, :, 0] > 0).all()
+    # the FP32-compensated grid on the same rows: 1e-7 of the oracle, same
+    # row and global minima as FP64
+    idx32, _, rows32, om32 = run3(pts, delta, q, 7, OMEGA_FP32_COMP)
+    w32 = assert_close(om32[:, :, pick], ref, pts, True, delta)
+    say(f"three-band workload fp32c rows {pick}: worst rel {w32:.3e}")
+    np.testing.assert_array_equal(rows32[:, :, pick], rr)
+    np.testing.assert_array_equal(idx32, idx)
 
 
 def test_three_band_zone_from_symmetry_wedge():
