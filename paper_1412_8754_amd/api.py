@@ -17,8 +17,17 @@ from ._abi import (OMEGA3_BAND_ALL, OMEGA_BAND_BOTH, OMEGA_FP32_COMP,  # noqa: F
                    n_bands3)
 
 
-def _stream_ptr(stream) -> int:
-    s = stream if stream is not None else torch.cuda.current_stream()
+def _stream_ptr(stream, *tensors) -> int:
+    """The HIP stream handle of a call (the current stream unless one is
+    given).  On another stream, the call's device tensors (inputs, outputs,
+    workspace) are recorded as used there, so that the caching allocator does
+    not hand their memory out again before that stream's work is done."""
+    cur = torch.cuda.current_stream()
+    s = stream if stream is not None else cur
+    if s != cur:
+        for t in tensors:
+            if t is not None:
+                t.record_stream(s)
     return int(s.cuda_stream)
 
 
@@ -70,7 +79,8 @@ def grid(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = OM
     p = make_points(pts)
     rc = L.omega_grid(ctypes.byref(m), p, len(pts), d.data_ptr(), d.numel(), qq.data_ptr(),
                       qq.shape[0], int(bands), int(precision), ws.data_ptr(),
-                      ws.numel() * ws.element_size(), out.data_ptr(), _stream_ptr(stream))
+                      ws.numel() * ws.element_size(), out.data_ptr(),
+                      _stream_ptr(stream, d, qq, ws, out))
     _check(rc, "omega_grid")
     return out
 
@@ -114,7 +124,8 @@ def argmin(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, precision: int = 
                            ws.numel() * ws.element_size(), idx.data_ptr(), omin.data_ptr(),
                            row_idx.data_ptr() if row_idx is not None else None,
                            om.data_ptr() if om is not None else None,
-                           ctypes.byref(lo) if lo is not None else None, _stream_ptr(stream))
+                           ctypes.byref(lo) if lo is not None else None,
+                           _stream_ptr(stream, d, qq, ws, idx, omin, row_idx, om))
     _check(rc, "omega_argmin_ex")
     return idx, omin, row_idx, om
 
@@ -138,7 +149,8 @@ def grad(model, pts, delta, q, bands: int = OMEGA_BAND_BOTH, device="cuda", work
     p = make_points(pts)
     rc = L.omega_grad(ctypes.byref(m), p, n, d.data_ptr(), qq.data_ptr(), int(bands),
                       ws.data_ptr(), ws.numel() * ws.element_size(), om.data_ptr(),
-                      gd.data_ptr(), gq.data_ptr(), gm.data_ptr(), _stream_ptr(stream))
+                      gd.data_ptr(), gq.data_ptr(), gm.data_ptr(),
+                      _stream_ptr(stream, d, qq, ws, om, gd, gq, gm))
     _check(rc, "omega_grad")
     return om, gd, gq, gm
 
@@ -166,7 +178,8 @@ def lo_grid(model, pts, delta, q_index, bands: int = OMEGA_BAND_BOTH, device="cu
     m = make_model(model)
     rc = L.omega_lo_grid(ctypes.byref(m), p, len(pts), d.data_ptr(), d.numel(),
                          qi.ctypes.data, qi.shape[0], int(bands), ws.data_ptr(),
-                         ws.numel() * ws.element_size(), out.data_ptr(), _stream_ptr(stream))
+                         ws.numel() * ws.element_size(), out.data_ptr(),
+                         _stream_ptr(stream, d, ws, out))
     _check(rc, "omega_lo_grid")
     return out
 
@@ -180,7 +193,7 @@ def bands3(model, Lx: int, Ly: int, device="cuda", stream=None) -> torch.Tensor:
     ws = torch.empty(16 * (int(Lx) + int(Ly)), dtype=torch.uint8, device=device)
     m = make_model3(model)
     rc = L.omega3_bands(ctypes.byref(m), int(Lx), int(Ly), ws.data_ptr(), ws.numel(),
-                        out.data_ptr(), _stream_ptr(stream))
+                        out.data_ptr(), _stream_ptr(stream, ws, out))
     _check(rc, "omega3_bands")
     return out
 
@@ -213,7 +226,8 @@ def grid3(model, pts, delta, q, bands: int = OMEGA3_BAND_ALL, precision: int = O
     p = make_points(pts)
     rc = L.omega3_grid(ctypes.byref(m), p, len(pts), d.data_ptr(), d.numel(), qq.data_ptr(),
                        qq.shape[0], int(bands), int(precision), ws.data_ptr(),
-                       ws.numel() * ws.element_size(), out.data_ptr(), _stream_ptr(stream))
+                       ws.numel() * ws.element_size(), out.data_ptr(),
+                       _stream_ptr(stream, d, qq, ws, out))
     _check(rc, "omega3_grid")
     return out
 
@@ -238,7 +252,8 @@ def argmin3(model, pts, delta, q, bands: int = OMEGA3_BAND_ALL, precision: int =
                          int(bands), int(precision), float(tie_rel), ws.data_ptr(),
                          ws.numel() * ws.element_size(), idx.data_ptr(), omin.data_ptr(),
                          row_idx.data_ptr() if row_idx is not None else None,
-                         om.data_ptr() if om is not None else None, _stream_ptr(stream))
+                         om.data_ptr() if om is not None else None,
+                         _stream_ptr(stream, d, qq, ws, idx, omin, row_idx, om))
     _check(rc, "omega3_argmin")
     return idx, omin, row_idx, om
 
@@ -278,7 +293,7 @@ def pair_chi(model, pts, q, bands: int = OMEGA_BAND_BOTH, device="cuda", workspa
     m = make_model(model)
     rc = L.omega_pair_chi(ctypes.byref(m), p, len(pts), qq.data_ptr(), qq.shape[0], int(bands),
                           ws.data_ptr(), ws.numel() * ws.element_size(), out.data_ptr(),
-                          _stream_ptr(stream))
+                          _stream_ptr(stream, qq, ws, out))
     _check(rc, "omega_pair_chi")
     return out
 
@@ -298,6 +313,6 @@ def pair_chi3(model, pts, q, bands: int = OMEGA3_BAND_ALL, device="cuda", worksp
     m = make_model3(model)
     rc = L.omega3_pair_chi(ctypes.byref(m), p, len(pts), qq.data_ptr(), qq.shape[0],
                            int(bands), ws.data_ptr(), ws.numel() * ws.element_size(),
-                           out.data_ptr(), _stream_ptr(stream))
+                           out.data_ptr(), _stream_ptr(stream, qq, ws, out))
     _check(rc, "omega3_pair_chi")
     return out
