@@ -168,6 +168,30 @@ int omega_argmin_ex(const omega_model *model, const omega_point *pts, int n_pts,
                     int32_t *idx_dev, double *omin_dev, int32_t *row_idx_dev,
                     double *omega_dev, const omega_launch *launch, void *stream);
 
+/* omega_argmin for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation, results bitwise equal to omega_argmin's, with its
+ * scratch taken from an array of OMEGA_NOALLOC_SCRATCH_BYTES that the library
+ * holds statically on each device it runs on (allocated when the library's
+ * code is loaded on that device, kept until the process ends).  The caller
+ * still passes the inputs and outputs; the call allocates nothing, on the
+ * device or through any library.  Its device address is looked up on the
+ * first call on each device (make that first call outside graph capture).
+ *   Returns OMEGA_E_WORKSPACE when the call needs more scratch than the
+ *   array holds (omega_workspace_bytes(..., grad = 0) bytes, less the grid's
+ *   n_pts*nb*n_q*n_delta*8 bytes when omega_dev is given): e.g. the 1024 x
+ *   1024 lattice with 256 Delta x 64 Q x 2 bands needs about 75 MiB.
+ *   Every call on one device shares that device's array, and a call leaves
+ *   its contents behind (each call initialises what it reads): calls that
+ *   overlap on one device (two streams, or two host threads, without
+ *   ordering) race and give undefined results. */
+#define OMEGA_NOALLOC_SCRATCH_BYTES (128u << 20)
+int omega_argmin_noalloc(const omega_model *model, const omega_point *pts, int n_pts,
+                         const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                         int bands, int precision, double tie_rel, int32_t *idx_dev,
+                         double *omin_dev, int32_t *row_idx_dev, double *omega_dev,
+                         void *stream);
+
 /* Omega and its first derivatives at one (Delta, Q) per point and band,
  * obtained by differentiating Eqs. (4)-(5) by hand (dOmega/dE = Fermi
  * function; at R = sqrt(s^2 + Delta^2 eta^2) = 0 and at band-touching points

@@ -12,13 +12,14 @@ OMEGA_FP64, OMEGA_FP32_COMP = 0, 1
 OMEGA_OK, OMEGA_E_INVAL, OMEGA_E_WORKSPACE, OMEGA_E_HIP, OMEGA_E_UNSUPPORTED = 0, -1, -2, -3, -4
 
 OMEGA3_BAND_0, OMEGA3_BAND_1, OMEGA3_BAND_2, OMEGA3_BAND_ALL = 1, 2, 4, 7
+OMEGA_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 EXPORTS = ("omega_workspace_bytes", "omega_grid", "omega_argmin", "omega_grad",
            "omega_strerror", "omega_version", "omega_argmin_ex", "omega3_argmin_ex",
            "omega3_bands", "omega3_workspace_bytes",
            "omega3_grid", "omega3_argmin", "omega_chi_workspace_bytes", "omega_pair_chi",
            "omega3_chi_workspace_bytes", "omega3_pair_chi", "omega_q_wedge",
-           "omega_lo_workspace_bytes", "omega_lo_grid")
+           "omega_lo_workspace_bytes", "omega_lo_grid", "omega_argmin_noalloc")
 
 
 OMEGA_ETA_K, OMEGA_ETA_REL = 0, 1
@@ -94,6 +95,9 @@ def load() -> ctypes.CDLL:
     L.omega_argmin_ex.restype = i32
     L.omega_argmin_ex.argtypes = [mp, pp, i32, vp, i32, vp, i32, i32, i32, ctypes.c_double,
                                   vp, sz, vp, vp, vp, vp, lp, vp]
+    L.omega_argmin_noalloc.restype = i32
+    L.omega_argmin_noalloc.argtypes = [mp, pp, i32, vp, i32, vp, i32, i32, i32,
+                                       ctypes.c_double, vp, vp, vp, vp, vp]
     m3 = ctypes.POINTER(Model3)
     L.omega3_bands.restype = i32
     L.omega3_bands.argtypes = [m3, i32, i32, vp, sz, vp, vp]

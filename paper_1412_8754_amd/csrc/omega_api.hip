@@ -12,6 +12,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "omega.h"
@@ -801,6 +802,37 @@ size_t lo_bytes(const omega_point *pts, int n_pts, int n_delta, const int32_t *q
     return align_up(part);
 }
 
+// Scratch of omega_argmin_noalloc: one statically allocated array per
+// device (each device that runs the library holds its own copy until the
+// process ends).  In host code `scratch` names a host-side stand-in, not the
+// device array; its device address is taken once per device with
+// hipGetSymbolAddress and only that address is passed to the kernels.
+constexpr size_t kScratchBytes = (size_t)OMEGA_NOALLOC_SCRATCH_BYTES;
+static_assert(kScratchBytes % kAlign == 0, "scratch size keeps the workspace alignment");
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mutex;
+void *g_scratch_dev[kMaxDevices];
+
+// Device address of the current device's scratch array; taken on the first
+// call on that device, with the device current.
+int scratch_address(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return OMEGA_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return OMEGA_E_HIP;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return OMEGA_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -856,6 +888,28 @@ int omega_argmin_ex(const omega_model *model, const omega_point *pts, int n_pts,
     return run_argmin(describe(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
                       precision, tie_rel, ws_dev, ws_bytes, idx_dev, omin_dev, row_idx_dev,
                       omega_dev, lo, stream);
+}
+
+int omega_argmin_noalloc(const omega_model *model, const omega_point *pts, int n_pts,
+                         const double *delta_dev, int n_delta, const double *q_dev, int n_q,
+                         int bands, int precision, double tie_rel, int32_t *idx_dev,
+                         double *omin_dev, int32_t *row_idx_dev, double *omega_dev,
+                         void *stream)
+{
+    if (!model_ok(model) || !points_ok(pts, n_pts) || !sizes_ok(n_delta, n_q, bands, precision))
+        return OMEGA_E_INVAL;
+    const int nb = n_bands(bands);
+    const size_t need = plan_grid(pts, n_pts, n_delta, n_q, nb, false).sweep_bytes +
+                        (omega_dev ? 0 : grid_bytes(n_pts, n_delta, n_q, nb));
+    if (need > kScratchBytes)
+        return OMEGA_E_WORKSPACE;
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != OMEGA_OK)
+        return rc;
+    return run_argmin(describe(model, bands), pts, n_pts, delta_dev, n_delta, q_dev, n_q,
+                      precision, tie_rel, ws, kScratchBytes, idx_dev, omin_dev, row_idx_dev,
+                      omega_dev, Launch(), stream);
 }
 
 size_t omega_lo_workspace_bytes(const omega_point *pts, int n_pts, int n_delta,
