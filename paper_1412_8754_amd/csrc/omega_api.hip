@@ -301,7 +301,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_d2 = 0;
     p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 2));
     p.off_gtab = p.off_qtrig + align_up(sizeof(double) * kQTrig * (size_t)n_q);
-    p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabN);
+    p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabEntries);
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.off_base = p.off_part + align_up(part);

@@ -43,10 +43,14 @@ constexpr float kCutFp32 = 17.0f;
 // almost none is zero or on a tile series), in both precisions.
 constexpr double kInPlaceT = 0.005;
 
-// Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 30: entry N
-// holds (G(a0), 1/(1 + e^a0)) at a0 = N / kGStep.
+// Table of the FP64 thermal term G(a) = ln(1 + e^-a), 0 <= a <= 30, at
+// a0 = N / kGStep: the Taylor coefficients of G at a0 in the scaled variable
+// r = kGStep (a - a0), |r| <= 1/2, c_n = G^(n)(a0) / (n! kGStep^n).  Two
+// arrays of kGTabN double2 one behind the other: (c0, c1), then (c2, c3);
+// c4 follows from c2 (see log1p_exp_tab).
 constexpr int kGStep = 64;
 constexpr int kGTabN = 30 * kGStep + 1;
+constexpr int kGTabEntries = 2 * kGTabN;   // double2 entries of the table
 static_assert(kCutFp64 == 30.0, "the thermal table ends at the FP64 cut");
 
 // Series path of the sweep.  With x = Delta^2, the centre x0 and half-width
@@ -184,7 +188,7 @@ struct SweepArgs {
     const double *q;     // [n_q][2]
     const double *qtrig; // [n_q][kQTrig] cos/sin of qx, qy, qx/2, qy/2
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
-    const double2 *gtab; // [kGTabN] thermal table (FP64 sweeps; P(0) of the FP32-compensated series pass)
+    const double2 *gtab; // [kGTabEntries] thermal table (FP64 sweeps; P(0) of the FP32-compensated series pass)
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments

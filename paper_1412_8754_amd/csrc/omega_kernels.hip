@@ -118,44 +118,49 @@ __device__ __forceinline__ double log1p_small(double z)
     return fma(de, kLn2Hi, fma(de, kLn2Lo, lf));
 }
 
-// G(a) = ln(1 + e^-a) for 0 <= a <= 36 (the thermal term over T) from the
-// table at a0 = N / kGStep, |a - a0| <= 1/128.  With sigma = 1/(1 + e^a0),
-// p = sigma (1 - sigma) and b = 1 - 2 sigma, the derivatives of G at a0 are
+// G(a) = ln(1 + e^-a) for 0 <= a <= 30 (the thermal term over T) from the
+// table, given as = kGStep a.  With a0 = N / kGStep the nearest table point,
+// r = as - N (|r| <= 1/2, exact) and sigma = 1/(1 + e^a0), p = sigma (1 -
+// sigma), b = 1 - 2 sigma, the derivatives of G at a0 are
 //   G' = -sigma, G'' = p, G''' = -p b, G'''' = p (1 - 6p),
 //   G^(5) = -p b (1 - 12p)
-// (from sigma' = -p, p' = -p b, b' = 2p).  The Taylor polynomial of degree 4
-// leaves at most |G^(5)| (1/128)^5 / 120 <= 4.9e-13 G, as |G^(5)| <= 2p and
-// p <= sigma <= G; checked against a long-double reference over [0, 36]:
-// 2.4e-13 relative and 3.1e-14 absolute at most, without bias.  With the
-// factor T and at most two such terms per momentum, Omega moves by less than
-// 1e-13 T per momentum.  The caller guarantees a < 30 (1 + 4 eps) (|E| < 30 T with T zero
-// or normal), so N <= kGTabN - 1 and the table read stays in range.
-__device__ __forceinline__ double log1p_exp_tab(double a, const double2 *gt)
+// (from sigma' = -p, p' = -p b, b' = 2p).  The table holds the scaled Taylor
+// coefficients c_n = G^(n)(a0) / (n! kGStep^n), n = 0..3; c4 = p (1 - 6p) /
+// (24 kGStep^4) = c2 (1/49152 - c2) for kGStep = 64, since p = 8192 c2.  The
+// polynomial of degree 4 leaves at most |G^(5)| (1/128)^5 / 120 <= 4.9e-13 G,
+// as |G^(5)| <= 2p and p <= sigma <= G; checked against a long-double
+// reference over [0, 30]: 2.4e-13 relative and 3.1e-14 absolute at most,
+// without bias.  With the factor T and at most two such terms per momentum,
+// Omega moves by less than 1e-13 T per momentum.  The caller guarantees
+// a < 30 (1 + 4 eps) (|E| < 30 T with T zero or normal), so N <= kGTabN - 1
+// and the table reads stay in range.
+static_assert(kGStep == 64, "c4 from c2 below assumes kGStep = 64");
+__device__ __forceinline__ double log1p_exp_tab(double as, const double2 *gt)
 {
-    const double N = rint(a * kGStep);
-    const double r = fma(-N, 1.0 / kGStep, a);
-    const double2 c = gt[(int)N];
-    const double s = c.y;
-    const double p = fma(-s, s, s);
-    const double b = fma(-2.0, s, 1.0);
-    const double c4 = p * fma(p, -0.25, 1.0 / 24.0);
-    double g = fma(c4, r, (p * b) * (-1.0 / 6.0));
-    g = fma(g, r, 0.5 * p);
-    g = fma(g, r, -s);
-    return fma(g, r, c.x);
+    const double N = rint(as);
+    const double r = as - N;
+    const int n = (int)N;
+    const double2 c01 = gt[n];
+    const double2 c23 = gt[kGTabN + n];
+    const double c4 = c23.x * (1.0 / 49152.0 - c23.x);
+    double g = fma(c4, r, c23.y);
+    g = fma(g, r, c23.x);
+    g = fma(g, r, c01.y);
+    return fma(g, r, c01.x);
 }
 
 // Thermal part of the two quasiparticle branches, ln((1 + u1)(1 + u2)) =
 // G(ax/T) + G(y/T) with u1 = exp(-ax/T), u2 = exp(-y/T), from the thermal
 // table gt (the second term dropped beyond the cut; the caller has
-// ax < cutT).  Kept out of line: series_kernel needs it for few momenta and
-// would otherwise hold its registers across the tile loop.
-__device__ __attribute__((noinline)) double thermal_tab(double ax, double y, double invT,
+// ax < cutT); invTs = kGStep / T.  Kept out of line: series_kernel needs it
+// for few momenta and would otherwise hold its registers across the tile
+// loop.
+__device__ __attribute__((noinline)) double thermal_tab(double ax, double y, double invTs,
                                                         double cutT, const double2 *gt)
 {
-    double L = log1p_exp_tab(ax * invT, gt);
+    double L = log1p_exp_tab(ax * invTs, gt);
     if (y < cutT)
-        L += log1p_exp_tab(y * invT, gt);
+        L += log1p_exp_tab(y * invTs, gt);
     return L;
 }
 
@@ -418,12 +423,18 @@ hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s)
 // ------------------------------------------------------------------ sweep
 
 // Per (k, Q) invariants of one band.
-// Thermal table: entry N = (ln(1 + e^-a0), 1/(1 + e^a0)), a0 = N / kGStep.
+// Thermal table at a0 = n / kGStep: (c0, c1) at gt[n] and (c2, c3) at
+// gt[kGTabN + n], c_k = G^(k)(a0) / (k! kGStep^k) (see log1p_exp_tab).
 __device__ __forceinline__ void gtable_at(int n, double2 *gt)
 {
     if (n < kGTabN) {
         const double e = exp(-n * (1.0 / kGStep));
-        gt[n] = make_double2(log1p(e), e / (1.0 + e));
+        const double sg = e / (1.0 + e);              // sigma = 1/(1 + e^a0)
+        const double p = sg * (1.0 - sg);
+        const double b = 1.0 - 2.0 * sg;
+        const double s1 = 1.0 / kGStep;
+        gt[n] = make_double2(log1p(e), -sg * s1);
+        gt[kGTabN + n] = make_double2(p * (0.5 * s1 * s1), -(p * b) * (s1 * s1 * s1 / 6.0));
     }
 }
 
@@ -880,10 +891,11 @@ __device__ __forceinline__ void listed_tile(const TileList &t, int e, int &ti, i
 typedef const __attribute__((address_space(4))) SweepArgs *ConstArgs;
 
 // Per-unit constants of the queued sweep (sweep_kernel), in LDS: the tile's
-// Delta^2 range [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T and
-// the cut 30 T.
+// Delta^2 range [x_lo, x_hi] with centre and half-width, mu +- h, T, 1/T,
+// the cut 30 T and kGStep / T (the thermal table's argument scale).
 enum {
-    kUcXlo, kUcXhi, kUcXc, kUcHt, kUcMuUp, kUcMuDn, kUcT, kUcInvT, kUcCutT, kUnitConsts
+    kUcXlo, kUcXhi, kUcXc, kUcHt, kUcMuUp, kUcMuDn, kUcT, kUcInvT, kUcCutT, kUcInvTs,
+    kUnitConsts
 };
 
 // Work queues of the persistent sweeps: nq = a.n_queues 64-bit counters in
@@ -1004,7 +1016,7 @@ void series_kernel(const SweepArgs a, int fp64)
                     // from the thermal table (read through the cache)
                     double P0 = fmax(A0, 0.0);
                     if (fabs(A0) < cutT)
-                        P0 = fma(T, thermal_tab(fabs(A0), r.as + r.m, invT, cutT, a.gtab), P0);
+                        P0 = fma(T, thermal_tab(fabs(A0), r.as + r.m, kGStep * invT, cutT, a.gtab), P0);
                     base -= P0;
                 }
                 neumaier(bs, bc, w * base);
@@ -1102,12 +1114,12 @@ hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStrea
 // current device (or blocks_per_cu of them per CU, if fewer), but no more
 // than there are units.
 template <typename K>
-static int persistent_blocks(K kernel, unsigned long long units, int blocks_per_cu)
+static int persistent_blocks(K kernel, int threads, unsigned long long units, int blocks_per_cu)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
         return -1;
     if (per_cu < 1)
         per_cu = 1;
@@ -1194,10 +1206,11 @@ __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float 
 // The per-Delta FP64 loop of one term: acc[t] += w P(Delta_t), with
 // P = max(x, 0) + T ln((1 + u1)(1 + u2)), x = R - |d|, u1 = e^-|x|/T,
 // u2 = e^-(R + |d|)/T (each thermal part skipped beyond the cut 30 T);
-// s2p = s^2 (floored), Delta^2 from dp[0..TD] (dp[TD] only read ahead).
+// s2p = s^2 (floored), Delta^2 from dp[0..TD] (dp[TD] only read ahead),
+// invTs = kGStep / T (the thermal table's scaled argument).
 template <int TD>
 __device__ __forceinline__ void f64_steps(double (&acc)[TD], double s2p, double m,
-                                          double eta2, double w, double T, double invT,
+                                          double eta2, double w, double T, double invTs,
                                           double cutT, const double *dp, const double2 *gt)
 {
     const double wT = w * T;
@@ -1210,10 +1223,10 @@ __device__ __forceinline__ void f64_steps(double (&acc)[TD], double s2p, double 
         acc[t] = fma(w, fmax(x, 0.0), acc[t]);
         const double ax = fabs(x);
         if (ax < cutT) {
-            double L = log1p_exp_tab(ax * invT, gt);
+            double L = log1p_exp_tab(ax * invTs, gt);
             const double y = R + m;
             if (y < cutT)
-                L += log1p_exp_tab(y * invT, gt);
+                L += log1p_exp_tab(y * invTs, gt);
             acc[t] = fma(wT, L, acc[t]);
         }
         dcur = dnext;
@@ -1231,10 +1244,17 @@ __device__ __forceinline__ void f64_steps(double (&acc)[TD], double s2p, double 
 // loaded into LDS once.  F32 = true (the FP32-compensated sweep): the
 // classification and the tile series stay FP64, and the loop evaluates
 // P(Delta) - P(0) in FP32 (see KQf).
+// Waves per workgroup of the queued sweep: the FP64 sweep shares one LDS
+// copy of the thermal table among 12 waves (3 per SIMD, one workgroup per
+// CU); the FP32 sweep has no table and runs 4-wave workgroups.
+template <bool F32>
+constexpr int sweep_waves() { return F32 ? 4 : 12; }
+
 template <int TD, bool B3, bool F32>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(64 * sweep_waves<F32>()) __attribute__((amdgpu_waves_per_eu(3)))
 void sweep_kernel(const SweepArgs args)
 {
+    constexpr int NW = sweep_waves<F32>();
     const SweepArgs &a0 = args;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -1242,14 +1262,14 @@ void sweep_kernel(const SweepArgs args)
     // (one extra slot for the look-ahead read of the last iteration), and
     // the unit's constants (kept in LDS rather than in registers across the
     // tile loop); per workgroup: the thermal table
-    __shared__ double d2s[4][TD + 1];
+    __shared__ double d2s[NW][TD + 1];
     // FP32 sweep: the same Delta^2 as an unevaluated FP32 pair hi + lo
     // (rounding Delta^2 to one float would shift every momentum's term at
     // that Delta the same way, a systematic 6e-8 that the sum would not
     // average out)
-    __shared__ float2 d2f[4][F32 ? TD + 1 : 1];
-    __shared__ double uc[4][kUnitConsts];
-    __shared__ double2 gt[F32 ? 1 : kGTabN];
+    __shared__ float2 d2f[NW][F32 ? TD + 1 : 1];
+    __shared__ double uc[NW][kUnitConsts];
+    __shared__ double2 gt[F32 ? 1 : kGTabEntries];
     // per wave: queue of the (k, Q) terms that need the per-Delta loop and
     // their mirror weights; the loop runs on 64 of them at a time, so that
     // every lane of the wave has a term.  FP64: s^2 (floored), |d|, eta^2;
@@ -1258,10 +1278,10 @@ void sweep_kernel(const SweepArgs args)
         double d[3][2 * 64];
         float f[6][2 * 64];
     };
-    __shared__ Queue lq[4];
-    __shared__ float lqw[4][2 * 64];
+    __shared__ Queue lq[NW];
+    __shared__ float lqw[NW][2 * 64];
     if constexpr (!F32) {
-        for (int n = threadIdx.x; n < kGTabN; n += kBlock)
+        for (int n = threadIdx.x; n < kGTabEntries; n += 64 * NW)
             gt[n] = a0.gtab[n];
     }
     __syncthreads();
@@ -1323,6 +1343,7 @@ void sweep_kernel(const SweepArgs args)
             u[kUcT] = pt.T;
             u[kUcInvT] = pt.T > 0.0 ? 1.0 / pt.T : 0.0;
             u[kUcCutT] = kCutFp64 * pt.T;
+            u[kUcInvTs] = pt.T > 0.0 ? kGStep / pt.T : 0.0;
         }
         // the wave's LDS writes above are visible to all of its lanes
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1460,7 +1481,7 @@ void sweep_kernel(const SweepArgs args)
                     if constexpr (!F32)
                         f64_steps<TD>(acc, lq[wave].d[0][lane], lq[wave].d[1][lane],
                                       lq[wave].d[2][lane], (double)lqw[wave][lane], cp[kUcT],
-                                      cp[kUcInvT], cutT, dp, gt);
+                                      cp[kUcInvTs], cutT, dp, gt);
                 }
                 // terms beyond the first 64 move to the front of the queue
                 pending -= nb;
@@ -1509,10 +1530,12 @@ static hipError_t launch_persistent(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_kernel<TD, B3, F32>, units, a.blocks_per_cu);
+    constexpr int threads = 64 * sweep_waves<F32>();
+    const int blocks =
+        persistent_blocks(sweep_kernel<TD, B3, F32>, threads, units, a.blocks_per_cu);
     if (blocks <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_kernel<TD, B3, F32>), dim3(blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<TD, B3, F32>), dim3(blocks), dim3(threads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1523,15 +1546,21 @@ static hipError_t launch_persistent(const SweepArgs &a, hipStream_t s)
 // instead of 3; three-band: 3).
 // Persistent like sweep_kernel, with the same work queues and units, one
 // unit per wave at a time.
+// Waves per workgroup of the in-place FP64 sweep: one workgroup per CU
+// shares the LDS thermal table (two-band: 4 waves per SIMD; three-band: 3).
+template <bool B3>
+constexpr int hot_waves() { return B3 ? 12 : 16; }
+
 template <int TD, bool B3>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B3 ? 3 : 4)))
+__global__ __launch_bounds__(64 * hot_waves<B3>()) __attribute__((amdgpu_waves_per_eu(B3 ? 3 : 4)))
 void sweep_f64_hot_kernel(const SweepArgs args)
 {
+    constexpr int NW = hot_waves<B3>();
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    __shared__ double d2s[4][TD + 1];
-    __shared__ double2 gt[kGTabN];
-    for (int n = threadIdx.x; n < kGTabN; n += kBlock)
+    __shared__ double d2s[NW][TD + 1];
+    __shared__ double2 gt[kGTabEntries];
+    for (int n = threadIdx.x; n < kGTabEntries; n += 64 * NW)
         gt[n] = args.gtab[n];
     __syncthreads();
     int n_direct = 0;
@@ -1601,7 +1630,7 @@ void sweep_f64_hot_kernel(const SweepArgs args)
                                           eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
                 // R^2 >= 1e-300 keeps the reciprocal square root finite
                 f64_steps<TD>(acc, r.s2 + 1e-300, r.m, r.eta2,
-                              mirror_weight(kr, i, j, a.Lx, a.Ly), T, invT, cutT,
+                              mirror_weight(kr, i, j, a.Lx, a.Ly), T, kGStep * invT, cutT,
                               d2s[wave] + zoff, gt);
             }
         }
@@ -1621,10 +1650,12 @@ static hipError_t launch_persistent_f64_hot(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_f64_hot_kernel<TD, B3>, units, a.blocks_per_cu);
+    constexpr int threads = 64 * hot_waves<B3>();
+    const int blocks =
+        persistent_blocks(sweep_f64_hot_kernel<TD, B3>, threads, units, a.blocks_per_cu);
     if (blocks <= 0)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_f64_hot_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((sweep_f64_hot_kernel<TD, B3>), dim3(blocks), dim3(threads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1794,7 +1825,8 @@ static hipError_t launch_persistent_f32c_hot(const SweepArgs &a, hipStream_t s)
 {
     const unsigned long long units =
         (unsigned long long)a.n_chunks * a.n_dtiles * (unsigned long long)a.n_rows;
-    const int blocks = persistent_blocks(sweep_f32c_hot_kernel<TD, B3>, units, a.blocks_per_cu);
+    const int blocks =
+        persistent_blocks(sweep_f32c_hot_kernel<TD, B3>, kBlock, units, a.blocks_per_cu);
     if (blocks <= 0)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((sweep_f32c_hot_kernel<TD, B3>), dim3(blocks), dim3(kBlock), 0, s, a);
@@ -2342,14 +2374,17 @@ __global__ __launch_bounds__(kBlock) void verify_cand_kernel(const VerifyArgs v)
 // FP64 sum over one momentum chunk of the Eq. (5) terms of one candidate:
 // units (set, candidate, chunk), grid-stride over all of them; units of
 // empty candidate slots are skipped.  Each term is evaluated in full (no
-// series, no table, no folding): the Delta-independent part minus
-// max(R - |d|, 0) + T [G(|R - |d||/T) + G((R + |d|)/T)], G(a) = ln(1 + e^-a).
+// series), with the FP64 sweep's arithmetic for its Delta-dependent part:
+// the Delta-independent part minus max(R - |d|, 0) + T [G(|R - |d||/T) +
+// G((R + |d|)/T)], G(a) = ln(1 + e^-a) from the thermal table and dropped
+// beyond the cut 30 T.  Pair momenta on an axis sum the mirror-folded zone
+// (qy = 0: ky indices 0..Ly/2, weight 2 where the mirror is another index;
+// likewise qx = 0), as the sweep does: E and eta^2 are even in each
+// component for both models and both form factors.
 template <bool B3>
 __global__ __launch_bounds__(kBlock) void verify_eval_kernel(const VerifyArgs v, int n_units)
 {
     const SweepArgs &a = v.sw;
-    const long long n = (long long)a.Lx * a.Ly;
-    const long long span = (n + v.n_vchunks - 1) / v.n_vchunks;
     __shared__ double red[4];
     for (int u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int chunk = u % v.n_vchunks;
@@ -2367,30 +2402,41 @@ __global__ __launch_bounds__(kBlock) void verify_eval_kernel(const VerifyArgs v,
         const PointRec pt = a.pts[g];
         const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
         const double T = pt.T;
-        const double invT = T > 0.0 ? 1.0 / T : 0.0;
+        const double invTs = T > 0.0 ? kGStep / T : 0.0;
+        const double cutT = kCutFp64 * T;
         const double D = v.delta[id];
         const double D2 = D * D;
         const double cqx = a.qtrig[kQTrig * iq], sqx = a.qtrig[kQTrig * iq + 1];
         const double cqy = a.qtrig[kQTrig * iq + 2], sqy = a.qtrig[kQTrig * iq + 3];
         const int qmx = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq]);
         const int qmy = __builtin_amdgcn_readfirstlane(a.qlat[2 * iq + 1]);
+        const bool fx = a.q[2 * iq] == 0.0, fy = a.q[2 * iq + 1] == 0.0;
+        const int nx = fx ? a.Lx / 2 + 1 : a.Lx;
+        const int ny = fy ? a.Ly / 2 + 1 : a.Ly;
+        const long long n = (long long)nx * ny;
+        const long long span = (n + v.n_vchunks - 1) / v.n_vchunks;
         const long long k0 = (long long)chunk * span;
         const long long k1 = k0 + span < n ? k0 + span : n;
         double s = 0.0, c = 0.0;
         for (long long kk = k0 + threadIdx.x; kk < k1; kk += kBlock) {
-            const int i = (int)(kk / a.Ly);
-            const int j = (int)(kk - (long long)i * a.Ly);
+            const int i = (int)(kk / ny);
+            const int j = (int)(kk - (long long)i * ny);
+            const double w = ((fx && i != 0 && 2 * i != a.Lx) ? 2.0 : 1.0) *
+                             ((fy && j != 0 && 2 * j != a.Ly) ? 2.0 : 1.0);
             const KQ r = kq_setup<B3>(a, slot, iq, qmx, qmy, i, j, (unsigned)i * (unsigned)a.Ly,
                                       eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
             const double R = sqrt_rn(fma(D2, r.eta2, r.s2));
             const double x = R - r.m;
             double P = fmax(x, 0.0);
-            if (T > 0.0) {
-                const double a1 = fmin(fabs(x) * invT, 700.0);
-                const double a2 = fmin((R + r.m) * invT, 700.0);
-                P = fma(T, log1p_small(exp_nonpos(-a1)) + log1p_small(exp_nonpos(-a2)), P);
+            const double ax = fabs(x);
+            if (ax < cutT) {
+                double L = log1p_exp_tab(ax * invTs, a.gtab);
+                const double y = R + r.m;
+                if (y < cutT)
+                    L += log1p_exp_tab(y * invTs, a.gtab);
+                P = fma(T, L, P);
             }
-            neumaier(s, c, r.base - P);
+            neumaier(s, c, w * (r.base - P));
         }
         const double w = wave_sum(s + c);
         __syncthreads();
