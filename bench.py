@@ -37,31 +37,44 @@ sys.path.insert(0, ROOT)
 OPS_PER_EVAL = 14
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 
-# Hardware counters of the timed sweep kernel at the paper-scale workload,
-# from rocprofv3 runs of this script (the profile file named in "source"),
-# valid for the kernel build named there.  %VALU = (2 FMA + ADD + MUL +
-# TRANS) FP64 VALU instructions x 64 lanes / kernel time / FP64 peak.
-# traffic: HBM bytes per launch from FETCH_SIZE (x2.0) and WRITE_SIZE (x1.0),
-# each scaled by the same counter on a plain 256 MiB device copy.
-COUNTERS = {("paper", "fp64"): {
-    "source": "profiles/sweep_f64_paper_L1024.md",
-    "kernel_us": 1275.9, "valu_busy": [0.672, 0.700], "valu_utilization": 0.8487,
-    "fma_f64": 1.498e8, "add_f64": 3.248e7, "mul_f64": 9.436e7, "trans_f64": 1.454e7,
-    "wait_frac": 4.42e8 / 1.75e9, "traffic": (13616 * 2 + 26720) * 1024}}
+# Hardware counters of the timed sweep kernel, from rocprofv3 runs of this
+# script (the profile file named in "source"), valid for the kernel sources
+# whose digest is "src": once omega_kernels.hip or omega_internal.h differ
+# from it, the line reports the counters as stale and no traffic.
+# %VALU = (2 FMA + ADD + MUL + TRANS) VALU instructions of the kernel's
+# precision x 64 lanes / kernel time / that precision's peak.
+# traffic: HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled
+# by the same counter on a plain 256 MiB device copy (x2.0 and x1.0).
+COUNTERS = {}
 
 
-def counter_valu_frac(c):
-    """%VALU of the survey's definition from one counter record."""
-    ops = (2 * c["fma_f64"] + c["add_f64"] + c["mul_f64"] + c["trans_f64"]) * 64
-    return ops / (c["kernel_us"] * 1e-6) / (PEAK_TFLOPS["f64"] * 1e12)
+def kernel_src_digest():
+    """Digest of the sources the counters belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("omega_kernels.hip", "omega_internal.h"):
+        with open(os.path.join(ROOT, "paper_1412_8754_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_valu_frac(c, precision):
+    """%VALU of the survey's definition from one counter record: the VALU
+    operations of the kernel's precision (FP64, or FP32 for the
+    FP32-compensated sweep) against that precision's vector peak."""
+    ops = (2 * c["fma"] + c["add"] + c["mul"] + c["trans"]) * 64
+    dt = "f64" if precision == "fp64" else "f32"
+    return ops / (c["kernel_us"] * 1e-6) / (PEAK_TFLOPS[dt] * 1e12)
 
 
 def sweep_kernel_name(precision, three, T):
-    """The library's sweep kernel for one workload point (the FP32-compensated
-    path runs points at T >= 0.005 through its in-place kernel)."""
+    """The library's sweep kernel for one workload point (points at
+    T >= 0.005 run through the in-place kernels of either precision)."""
     b3 = "true" if three else "false"
-    if precision == "fp32c" and T >= 0.005:
-        return f"sweep_f32c_hot_kernel<32, {b3}>"
+    if T >= 0.005:
+        if precision == "fp32c":
+            return f"sweep_f32c_hot_kernel<32, {b3}>"
+        return f"sweep_f64_hot_kernel<32, {b3}>"
     return f"sweep_kernel<32, {b3}, {'true' if precision == 'fp32c' else 'false'}>"
 
 
@@ -75,8 +88,10 @@ def roofline_record(workload, precision, achieved, peak, three, T, sweep_ms, dir
            "ops_per_eval": OPS_PER_EVAL, "units": direct}
     c = COUNTERS.get((workload, precision))
     if c is not None:
-        rec["traffic"] = c["traffic"]
-        rec["counters"] = {"source": c["source"], "valu_frac": counter_valu_frac(c),
+        fresh = c["src"] == kernel_src_digest()
+        rec["traffic"] = c["traffic"] if fresh else None
+        rec["counters"] = {"source": c["source"], "src": c["src"], "stale": not fresh,
+                           "valu_frac": counter_valu_frac(c, precision),
                            "valu_busy": c["valu_busy"],
                            "valu_utilization": c["valu_utilization"],
                            "wait_frac": c["wait_frac"], "kernel_us": c["kernel_us"]}

@@ -301,7 +301,7 @@ GridPlan plan_grid(const omega_point *pts, int n_pts, int n_delta, int n_q, int 
     p.off_d2 = 0;
     p.off_qtrig = p.off_d2 + align_up(sizeof(double) * (p.n_delta_pad + 2));
     p.off_gtab = p.off_qtrig + align_up(sizeof(double) * kQTrig * (size_t)n_q);
-    p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabEntries);
+    p.off_trig = p.off_gtab + align_up(sizeof(double2) * kGTabEntries + sizeof(float4) * kG32N);
     p.off_table = p.off_trig + align_up(trig);
     p.off_part = p.off_table + align_up(table);
     p.off_base = p.off_part + align_up(part);
@@ -452,6 +452,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     double *d2 = (double *)(ws + P.off_d2);
     double *qtrig = (double *)(ws + P.off_qtrig);
     double2 *gtab = (double2 *)(ws + P.off_gtab);
+    float4 *gtab32 = (float4 *)(ws + P.off_gtab + sizeof(double2) * kGTabEntries);
     double *trig = (double *)(ws + P.off_trig);
     PointRec *table = (PointRec *)(ws + P.off_table);
     double *part = (double *)(ws + P.off_part);
@@ -463,7 +464,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     int *tcnt = (int *)(ws + P.off_tcnt);
     double *tpart = (double *)(ws + P.off_tpart);
     unsigned long long *queue = (unsigned long long *)(ws + P.off_queue);
-    if (launch_call_tables(delta, n_delta, P.n_delta_pad, d2, q, n_q, qtrig, gtab, s) !=
+    if (launch_call_tables(delta, n_delta, P.n_delta_pad, d2, q, n_q, qtrig, gtab, gtab32, s) !=
         hipSuccess)
         return OMEGA_E_HIP;
 
@@ -486,6 +487,7 @@ int enqueue_grid(const ModelDesc &md, const omega_point *pts, int n_pts,
     a.qtrig = qtrig;
     a.trig = trig;
     a.gtab = gtab;
+    a.gtab32 = gtab32;
     a.part = part;
     a.base_part = base;
     a.mpart = mom;

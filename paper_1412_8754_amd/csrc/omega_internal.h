@@ -35,9 +35,14 @@ constexpr double kCutFp64 = 30.0;
 // The gradient sweep keeps the Fermi function to 2.3e-16: it drops the
 // thermal parts beyond 36 T.
 constexpr double kCutGrad = 36.0;
-// Same for the FP32 sweep: exp(-17) = 4.1e-8 is below the FP32 resolution of
-// the terms it would be added to.
-constexpr float kCutFp32 = 17.0f;
+// The FP32 loop of the FP32-compensated path drops T ln(1 + exp(-|E|/T))
+// beyond 20 T: each branch then moves by less than T e^-20 = 2.1e-9 T,
+// one-signed, so Omega by less than 4.2e-9 T N: below 7e-9 of
+// |Omega| >= 0.03 N up to T = 0.05, well inside the stated 1e-7.  Its
+// classification of terms (exactly zero / cold over a Delta tile or the
+// whole Delta range / per-Delta loop) and its FP64 base term keep the FP64
+// cut, so that Omega at Delta = 0 stays the FP64 value.
+constexpr float kCutFp32 = 20.0f;
 // From this temperature on, a point's marked terms run the per-Delta loop in
 // place rather than being classified per Delta tile and queued (at higher T
 // almost none is zero or on a tile series), in both precisions.
@@ -52,6 +57,14 @@ constexpr int kGStep = 64;
 constexpr int kGTabN = 30 * kGStep + 1;
 constexpr int kGTabEntries = 2 * kGTabN;   // double2 entries of the table
 static_assert(kCutFp64 == 30.0, "the thermal table ends at the FP64 cut");
+
+// FP32 table of the same G for the FP32-compensated loop, 0 <= a <= 20 at
+// a0 = N / kG32Step: float4 (c0, c1, c2, c3), c_n = G^(n)(a0) / (n! kG32Step^n)
+// (rounded from FP64); degree 3 in r = kG32Step (a - a0), |r| <= 1/2, leaves
+// at most |G''''| (1/64)^4 / 24 <= 2.5e-9 G (|G''''| <= p <= G).
+constexpr int kG32Step = 32;
+constexpr int kG32N = 20 * kG32Step + 1;
+static_assert(kCutFp32 == 20.0f, "the FP32 thermal table ends at the FP32 cut");
 
 // Series path of the sweep.  With x = Delta^2, the centre x0 and half-width
 // hw of the call's Delta^2 range, R0 = sqrt(s^2 + x0 eta^2) and
@@ -189,6 +202,7 @@ struct SweepArgs {
     const double *qtrig; // [n_q][kQTrig] cos/sin of qx, qy, qx/2, qy/2
     const double *trig;  // cos kx [Lx], sin kx [Lx], cos ky [Ly], sin ky [Ly]
     const double2 *gtab; // [kGTabEntries] thermal table (FP64 sweeps; P(0) of the FP32-compensated series pass)
+    const float4 *gtab32; // [kG32N] FP32 thermal table (FP32-compensated sweeps)
     double *part;        // [G*nbq][n_chunks][n_delta_pad] sums of Delta parts
     double *base_part;   // [G*nbq][n_chunks] sums of Delta-independent parts
     double *mpart;       // [G*nbq][n_chunks][kMomentSlots] series moments
@@ -333,10 +347,10 @@ hipError_t launch_fill_points(const PointPack &pk, PointRec *dst, unsigned long 
 hipError_t launch_trig(int Lx, int Ly, double *trig, hipStream_t s);
 hipError_t launch_qtrig(const double *q, int n, double *out, hipStream_t s);
 hipError_t launch_gtable(double2 *gtab, hipStream_t s);
-// delta2 + qtrig + gtable in one launch
+// delta2 + qtrig + both thermal tables in one launch
 hipError_t launch_call_tables(const double *delta, int n_delta, int n_delta_pad, double *d2,
                               const double *q, int n_q, double *qtrig, double2 *gt,
-                              hipStream_t s);
+                              float4 *gt32, hipStream_t s);
 // trig + qlat in one launch
 hipError_t launch_group_tables(int Lx, int Ly, double *trig, const double *q, int n_q,
                                int *qlat, hipStream_t s);

@@ -438,38 +438,57 @@ __device__ __forceinline__ void gtable_at(int n, double2 *gt)
     }
 }
 
+// FP32 thermal table at a0 = n / kG32Step: (c0, c1, c2, c3), c_k =
+// G^(k)(a0) / (k! kG32Step^k), computed in FP64 and rounded.
+__device__ __forceinline__ void gtable32_at(int n, float4 *gt)
+{
+    if (n < kG32N) {
+        const double e = exp(-n * (1.0 / kG32Step));
+        const double sg = e / (1.0 + e);
+        const double p = sg * (1.0 - sg);
+        const double b = 1.0 - 2.0 * sg;
+        const double s1 = 1.0 / kG32Step;
+        gt[n] = make_float4((float)log1p(e), (float)(-sg * s1), (float)(p * (0.5 * s1 * s1)),
+                            (float)(-(p * b) * (s1 * s1 * s1 / 6.0)));
+    }
+}
+
 __global__ void gtable_kernel(double2 *gt)
 {
     gtable_at(blockIdx.x * blockDim.x + threadIdx.x, gt);
 }
 
 // The per-call tables of a grid call in one launch: Delta^2 (with its
-// range), cos/sin of Q and the thermal table, in consecutive workgroup
-// ranges.
+// range), cos/sin of Q and the FP64 and FP32 thermal tables, in consecutive
+// workgroup ranges.
 __global__ __launch_bounds__(kBlock) void call_tables_kernel(const double *delta, int n_delta,
                                                              int n_delta_pad, double *d2,
                                                              const double *q, int n_q,
-                                                             double *qtrig, double2 *gt)
+                                                             double *qtrig, double2 *gt,
+                                                             float4 *gt32)
 {
     const int nd = (n_delta_pad + kBlock - 1) / kBlock;
     const int nqb = (n_q + kBlock - 1) / kBlock;
+    const int ngb = (kGTabN + kBlock - 1) / kBlock;
     const int b = blockIdx.x;
     if (b < nd)
         delta2_block(b, delta, n_delta, n_delta_pad, d2);
     else if (b < nd + nqb)
         qtrig_at((b - nd) * kBlock + threadIdx.x, q, n_q, qtrig);
-    else
+    else if (b < nd + nqb + ngb)
         gtable_at((b - nd - nqb) * kBlock + threadIdx.x, gt);
+    else
+        gtable32_at((b - nd - nqb - ngb) * kBlock + threadIdx.x, gt32);
 }
 
 hipError_t launch_call_tables(const double *delta, int n_delta, int n_delta_pad, double *d2,
                               const double *q, int n_q, double *qtrig, double2 *gt,
-                              hipStream_t s)
+                              float4 *gt32, hipStream_t s)
 {
     const int blocks = (n_delta_pad + kBlock - 1) / kBlock + (n_q + kBlock - 1) / kBlock +
-                       (kGTabN + kBlock - 1) / kBlock;
+                       (kGTabN + kBlock - 1) / kBlock + (kG32N + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(call_tables_kernel, dim3(blocks), dim3(kBlock), 0, s, delta, n_delta,
-                       n_delta_pad, d2, q, n_q, qtrig, gt);
+                       n_delta_pad, d2, q, n_q, qtrig, gt, gt32);
     return hipGetLastError();
 }
 
@@ -956,9 +975,9 @@ __device__ constexpr bool is_series_level(int m)
 // Grid (chunk, band*Q + nbq*g).
 // Two-band: 4 waves/SIMD (a few spills outside the moment loop beat the
 // 3-wave occupancy its registers would otherwise give); three-band: 3.
-template <bool B3>
+template <bool B3, bool F64>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(B3 ? 3 : 4)))
-void series_kernel(const SweepArgs a, int fp64)
+void series_kernel(const SweepArgs a)
 {
     const int chunk = blockIdx.x;
     const int g = blockIdx.y / a.nbq;
@@ -974,6 +993,8 @@ void series_kernel(const SweepArgs a, int fp64)
     const double mu_up = a.mu + pt.h, mu_dn = a.mu - pt.h;
     const double T = pt.T;
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
+    // the FP32-compensated path classifies with its own (FP32) cut
+    constexpr bool fp64 = F64;
     const double cutT = kCutFp64 * T;
     const double x0 = a.d2[a.n_delta_pad];
     const double hw = a.d2[a.n_delta_pad + 1];
@@ -1011,7 +1032,7 @@ void series_kernel(const SweepArgs a, int fp64)
                 const double w = mirror_weight_t<FD>(kr, i, j, a.Lx, a.Ly);
                 const double A0 = r.as - r.m;
                 double base = r.base;
-                if (!fp64) {
+                if constexpr (!fp64) {
                     // P(0) for the FP32-compensated sweep, its thermal part
                     // from the thermal table (read through the cache)
                     double P0 = fmax(A0, 0.0);
@@ -1103,10 +1124,14 @@ void series_kernel(const SweepArgs a, int fp64)
 hipError_t launch_series(const SweepArgs &a, int G, bool fp64, bool b3, hipStream_t s)
 {
     const dim3 grid(a.n_chunks, a.nbq * G);
-    if (b3)
-        hipLaunchKernelGGL(series_kernel<true>, grid, dim3(kBlock), 0, s, a, fp64 ? 1 : 0);
+    if (b3 && fp64)
+        hipLaunchKernelGGL((series_kernel<true, true>), grid, dim3(kBlock), 0, s, a);
+    else if (b3)
+        hipLaunchKernelGGL((series_kernel<true, false>), grid, dim3(kBlock), 0, s, a);
+    else if (fp64)
+        hipLaunchKernelGGL((series_kernel<false, true>), grid, dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL(series_kernel<false>, grid, dim3(kBlock), 0, s, a, fp64 ? 1 : 0);
+        hipLaunchKernelGGL((series_kernel<false, false>), grid, dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1148,16 +1173,32 @@ struct KQf {
     float P0;      // T * L(0) in FP32, through the Delta loop's own arithmetic
 };
 
-// FP32 thermal logarithm of the Delta loop, ln((1 + u1)(1 + u2)).
-__device__ __forceinline__ float thermal_log_f32(float ax, float y, float invT,
-                                                 float cutT)
+// G(a) = ln(1 + e^-a) in FP32 from the FP32 table, given as = kG32Step a
+// with 0 <= a < 20 (1 + 2^-22): r = as - N is exact and |r| <= 1/2, and
+// N <= kG32N - 1.
+__device__ __forceinline__ float log1p_exp_tab32(float as, const float4 *gt)
 {
-    float u1 = __expf(-ax * invT);
-    float u2 = (y < cutT) ? __expf(-y * invT) : 0.0f;
-    return __logf(1.0f + (u1 + u2 + u1 * u2));
+    const float N = __builtin_rintf(as);
+    const float r = as - N;
+    const float4 c = gt[(int)N];
+    return fmaf(fmaf(fmaf(c.w, r, c.z), r, c.y), r, c.x);
 }
 
-__device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
+// FP32 thermal logarithm of the Delta loop, ln((1 + u1)(1 + u2)) =
+// G(ax/T) + G(y/T), u1 = e^-ax/T, u2 = e^-y/T, the second dropped beyond the
+// cut (the caller has ax < cutT); invTs = kG32Step / T.
+__device__ __forceinline__ float thermal_log_f32(float ax, float y, float invTs, float cutT,
+                                                 const float4 *gt)
+{
+    float L = log1p_exp_tab32(ax * invTs, gt);
+    if (y < cutT)
+        L += log1p_exp_tab32(y * invTs, gt);
+    return L;
+}
+
+// invT = 1/T; gt the FP32 thermal table.
+__device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT,
+                                            const float4 *gt)
 {
     KQf r;
     r.s2 = (float)q.s2;
@@ -1170,17 +1211,18 @@ __device__ __forceinline__ KQf kq_setup_f32(const KQ &q, double T, double invT)
     const float ax0 = fabsf(r.A0);
     r.P0 = ax0 < cutTf
                ? Tf * thermal_log_f32(ax0, __builtin_amdgcn_sqrtf(r.s2) + r.m,
-                                      (float)invT, cutTf)
+                                      (float)(kG32Step * invT), cutTf, gt)
                : 0.0f;
     return r;
 }
 
 // The per-Delta FP32 loop of one term: acc[t] += w (P(Delta_t) - P(0)),
-// Delta^2 from the hi/lo pairs dp[0..TD] (dp[TD] only read ahead).
+// Delta^2 from the hi/lo pairs dp[0..TD] (dp[TD] only read ahead); invTs =
+// kG32Step / T, gt the FP32 thermal table.
 template <int TD>
 __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float wf,
-                                          const float2 *dp, float Tf, float invTf,
-                                          float cutTf)
+                                          const float2 *dp, float Tf, float invTs,
+                                          float cutTf, const float4 *gt)
 {
     const bool hot0 = f.P0 != 0.0f;
     const bool pos = f.A0 >= 0.0f;
@@ -1195,7 +1237,7 @@ __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float 
         float piece = pos ? del : fmaxf(x, 0.0f);
         const float ax = fabsf(x);
         if (ax < cutTf || hot0) {
-            const float L = ax < cutTf ? thermal_log_f32(ax, R + f.m, invTf, cutTf) : 0.0f;
+            const float L = ax < cutTf ? thermal_log_f32(ax, R + f.m, invTs, cutTf, gt) : 0.0f;
             piece += fmaf(Tf, L, -f.P0);
         }
         acc[t] = fmaf(wf, piece, acc[t]);
@@ -1270,6 +1312,7 @@ void sweep_kernel(const SweepArgs args)
     __shared__ float2 d2f[NW][F32 ? TD + 1 : 1];
     __shared__ double uc[NW][kUnitConsts];
     __shared__ double2 gt[F32 ? 1 : kGTabEntries];
+    __shared__ float4 gt32[F32 ? kG32N : 1];
     // per wave: queue of the (k, Q) terms that need the per-Delta loop and
     // their mirror weights; the loop runs on 64 of them at a time, so that
     // every lane of the wave has a term.  FP64: s^2 (floored), |d|, eta^2;
@@ -1283,6 +1326,9 @@ void sweep_kernel(const SweepArgs args)
     if constexpr (!F32) {
         for (int n = threadIdx.x; n < kGTabEntries; n += 64 * NW)
             gt[n] = a0.gtab[n];
+    } else {
+        for (int n = threadIdx.x; n < kG32N; n += 64 * NW)
+            gt32[n] = a0.gtab32[n];
     }
     __syncthreads();
     int n_direct = 0;
@@ -1416,7 +1462,8 @@ void sweep_kernel(const SweepArgs args)
                     const float ax0 = (float)fabs(A0);
                     const float P0f =
                         ax0 < cutTf ? Tf * thermal_log_f32(ax0, (float)(r.as + r.m),
-                                                           (float)cp[kUcInvT], cutTf)
+                                                           (float)(kG32Step * cp[kUcInvT]),
+                                                           cutTf, gt32)
                                     : 0.0f;
                     c0 -= fmax(A0, 0.0) + (double)P0f;
                 }
@@ -1438,7 +1485,7 @@ void sweep_kernel(const SweepArgs args)
                                              (unsigned)(lb >> 32),
                                              __builtin_amdgcn_mbcnt_lo((unsigned)lb, 0u));
                 if constexpr (F32) {
-                    const KQf f = kq_setup_f32(r, cp[kUcT], cp[kUcInvT]);
+                    const KQf f = kq_setup_f32(r, cp[kUcT], cp[kUcInvT], gt32);
                     float(*lf)[2 * 64] = lq[wave].f;
                     lf[0][at] = f.s2;
                     lf[1][at] = f.as;
@@ -1476,7 +1523,7 @@ void sweep_kernel(const SweepArgs args)
                     const float Tf = (float)cp[kUcT];
                     if constexpr (F32)
                         f32_steps<TD>(acc, f, lqw[wave][lane], d2f[wave] + zoff, Tf,
-                                      (float)cp[kUcInvT], kCutFp32 * Tf);
+                                      (float)(kG32Step * cp[kUcInvT]), kCutFp32 * Tf, gt32);
                 } else if (!F32 && lane < nb) {
                     if constexpr (!F32)
                         f64_steps<TD>(acc, lq[wave].d[0][lane], lq[wave].d[1][lane],
@@ -1705,6 +1752,10 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
     // term at that Delta the same way, a systematic 6e-8 that the sum would
     // not average out)
     __shared__ float2 d2s[4][TD + 1];
+    __shared__ float4 gt32[kG32N];
+    for (int n = threadIdx.x; n < kG32N; n += kBlock)
+        gt32[n] = args.gtab32[n];
+    __syncthreads();
     int n_direct = 0;
     const int li = lane >> 3, lj = lane & 7;
     const int nq = sweep_queues(args);
@@ -1753,7 +1804,7 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
 #pragma unroll
         for (int t = 0; t < TD; ++t)
             acc[t] = 0.0f;
-        const float Tf = (float)T, invTf = (float)invT, cutTf = kCutFp32 * Tf;
+        const float Tf = (float)T, invTs = (float)(kG32Step * invT), cutTf = kCutFp32 * Tf;
 
         const TileList tl = tile_list(a, bz, chunk);
         // the next entry of the walk is fetched one tile ahead
@@ -1778,7 +1829,7 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
                                             (unsigned)(ti * kTileEdge) * (unsigned)a.Ly +
                                                 (unsigned)li * (unsigned)a.Ly,
                                             eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
-                const KQf r = kq_setup_f32(q64, T, invT);
+                const KQf r = kq_setup_f32(q64, T, invT, gt32);
                 const float wf = (float)mirror_weight(kr, i, j, a.Lx, a.Ly);
                 const bool hot0 = r.P0 != 0.0f;
                 const bool pos = r.A0 >= 0.0f;
@@ -1793,8 +1844,9 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
                     float piece = pos ? del : fmaxf(x, 0.0f);
                     float ax = fabsf(x);
                     if (ax < cutTf || hot0) {
-                        float L = ax < cutTf ? thermal_log_f32(ax, R + r.m, invTf, cutTf)
-                                             : 0.0f;
+                        float L = ax < cutTf
+                                      ? thermal_log_f32(ax, R + r.m, invTs, cutTf, gt32)
+                                      : 0.0f;
                         piece += fmaf(Tf, L, -r.P0);
                     }
                     acc[t] = fmaf(wf, piece, acc[t]);
@@ -2285,6 +2337,11 @@ __device__ int block_int_sum(int v, int *sh)
 // kVerifyMax cells lie under the threshold, the threshold is lowered by
 // bisection until at most kVerifyMax do (the lowest-valued cells stay), and
 // cells are taken in key order (iDelta, iq) up to the capacity.
+// The cells under the threshold are gathered into LDS in one pass over the
+// rows whose minimum lies under it (no other row holds such a cell), and the
+// bisection counts there; only if more than kCandCap cells qualify does it
+// count over the whole grid.  Both give the same threshold and cells.
+constexpr int kCandCap = 2048;
 __global__ __launch_bounds__(kBlock) void verify_cand_kernel(const VerifyArgs v)
 {
     const int sl = blockIdx.x;
@@ -2294,8 +2351,14 @@ __global__ __launch_bounds__(kBlock) void verify_cand_kernel(const VerifyArgs v)
     const int ncell = v.n_q * v.n_delta;
     const double *G = v.grid + oset * (size_t)ncell;
     const double *rm = v.rowmin + oset * (size_t)v.n_q;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __shared__ double shd[4];
     __shared__ int shi[4];
+    __shared__ double cv[kCandCap];   // values of the gathered cells
+    __shared__ int ck[kCandCap];      // their keys iDelta n_q + iq
+    __shared__ int n_gath;
+    __shared__ int sel[kVerifyMax];   // keys of the chosen cells
+    __shared__ int n_sel;
     double best = __longlong_as_double(0x7ff8000000000000LL);
     for (int iq = threadIdx.x; iq < v.n_q; iq += kBlock)
         best = nan_min(best, rm[iq]);
@@ -2311,20 +2374,83 @@ __global__ __launch_bounds__(kBlock) void verify_cand_kernel(const VerifyArgs v)
     const double floor_abs =
         v.n_k < (double)kFp32FloorSites ? ldexp(v.n_k * sqrt(v.d2c[0] + v.d2c[1]), -20) : 0.0;
     const double e = kFp32RelBound * ab + floor_abs;
+    // Delta = 0 cells hold FP64 values (the FP32 difference vanishes there):
+    // the lowest of them, from up to 8 such columns
+    __shared__ int zc[8];
+    __shared__ int nzc;
+    if (threadIdx.x == 0)
+        nzc = 0;
+    __syncthreads();
+    for (int id = threadIdx.x; id < v.n_delta; id += kBlock) {
+        const double D = v.delta[id];
+        if (D * D == 0.0) {
+            const int at = atomicAdd(&nzc, 1);
+            if (at < 8)
+                zc[at] = id;
+        }
+    }
+    __syncthreads();
+    const int nz = nzc;
+    double zb = __longlong_as_double(0x7ff8000000000000LL);
+    if (nz <= 8)
+        for (int k = 0; k < nz; ++k)
+            for (int iq = threadIdx.x; iq < v.n_q; iq += kBlock)
+                zb = nan_min(zb, G[(size_t)iq * v.n_delta + zc[k]]);
+    zb = block_nan_min(zb, shd);
     // a cell in the FP64 tie band has an FP32 value at most best + 2e +
-    // tie_rel |best| (to first order; the factor covers the second)
-    const double thr = best + (2.0 * e + v.tie_rel * ab) * (1.0 + 1e-6);
+    // tie_rel |best| (to first order; the factor covers the second); e
+    // instead of 2e where the lowest value is an FP64 one (at Delta = 0)
+    const double we = (nz <= 8 && zb <= best) ? 1.0 : 2.0;
+    const double thr = best + (we * e + v.tie_rel * ab) * (1.0 + 1e-6);
+
+    // gather: one wave per row whose minimum is under the threshold
+    if (threadIdx.x == 0)
+        n_gath = 0;
+    __syncthreads();
+    for (int iq = wave; iq < v.n_q; iq += kBlock / 64) {
+        if (!(rm[iq] <= thr))
+            continue;
+        for (int id = lane; id - lane < v.n_delta; id += 64) {
+            bool take = false;
+            double x = 0.0;
+            if (id < v.n_delta) {
+                const double D = v.delta[id];
+                x = G[(size_t)iq * v.n_delta + id];
+                take = D * D != 0.0 && x <= thr;
+            }
+            const unsigned long long b = __ballot(take);
+            if (b) {
+                int base = 0;
+                if (lane == 0)
+                    base = atomicAdd(&n_gath, __popcll(b));
+                base = __shfl(base, 0, 64);
+                const int at = base + (int)__popcll(b & ((1ull << lane) - 1ull));
+                if (take && at < kCandCap) {
+                    cv[at] = x;
+                    ck[at] = id * v.n_q + iq;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int ng = n_gath;
+    const bool in_lds = ng <= kCandCap;
     auto count_le = [&](double t) {
         int c = 0;
-        for (int cell = threadIdx.x; cell < ncell; cell += kBlock) {
-            const int iq = cell / v.n_delta;
-            const double D = v.delta[cell - iq * v.n_delta];
-            c += (D * D != 0.0 && G[cell] <= t) ? 1 : 0;
+        if (in_lds) {
+            for (int k = threadIdx.x; k < ng; k += kBlock)
+                c += cv[k] <= t ? 1 : 0;
+        } else {
+            for (int cell = threadIdx.x; cell < ncell; cell += kBlock) {
+                const int iq = cell / v.n_delta;
+                const double D = v.delta[cell - iq * v.n_delta];
+                c += (D * D != 0.0 && G[cell] <= t) ? 1 : 0;
+            }
         }
         return block_int_sum(c, shi);
     };
     double t = thr;
-    if (count_le(thr) > kVerifyMax) {
+    if (ng > kVerifyMax) {
         double lo = best, hi = thr;
         for (int it = 0; it < 64 && lo < hi; ++it) {
             const double mid = 0.5 * (lo + hi);
@@ -2337,36 +2463,63 @@ __global__ __launch_bounds__(kBlock) void verify_cand_kernel(const VerifyArgs v)
         }
         t = lo;
     }
-    // cells under t in key order (iDelta n_q + iq), up to the capacity
-    __shared__ int wcnt[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int total = 0;
-    for (int k0 = 0; k0 < ncell && total < kVerifyMax; k0 += kBlock) {
-        const int key = k0 + threadIdx.x;
-        int cell = 0;
-        bool take = false;
-        if (key < ncell) {
-            const int id = key / v.n_q;
-            const int iq = key - id * v.n_q;
-            const double D = v.delta[id];
-            cell = iq * v.n_delta + id;
-            take = D * D != 0.0 && G[cell] <= t;
+    // more than kVerifyMax cells at t itself (exact ties) take the scan of
+    // the whole grid in key order below
+    if (in_lds && count_le(t) <= kVerifyMax) {
+        // at most kVerifyMax gathered cells lie under t: their keys, then
+        // each one's place in key order
+        if (threadIdx.x == 0)
+            n_sel = 0;
+        __syncthreads();
+        for (int k = threadIdx.x; k < ng; k += kBlock) {
+            if (cv[k] <= t) {
+                const int at = atomicAdd(&n_sel, 1);
+                if (at < kVerifyMax)
+                    sel[at] = ck[k];
+            }
         }
-        const unsigned long long b = __ballot(take);
         __syncthreads();
-        if (lane == 0)
-            wcnt[wave] = __popcll(b);
-        __syncthreads();
-        int at = total;
-        for (int w = 0; w < wave; ++w)
-            at += wcnt[w];
-        at += __popcll(b & ((1ull << lane) - 1ull));
-        if (take && at < kVerifyMax)
-            v.cand[(size_t)sl * kVerifyMax + at] = cell;
-        total += ((wcnt[0] + wcnt[1]) + wcnt[2]) + wcnt[3];
+        total = n_sel < kVerifyMax ? n_sel : kVerifyMax;
+        if (threadIdx.x < total) {
+            const int key = sel[threadIdx.x];
+            int pos = 0;
+            for (int k = 0; k < total; ++k)
+                pos += sel[k] < key ? 1 : 0;
+            const int iq = key % v.n_q;
+            v.cand[(size_t)sl * kVerifyMax + pos] = iq * v.n_delta + key / v.n_q;
+        }
+    } else {
+        // cells under t in key order (iDelta n_q + iq), up to the capacity
+        __shared__ int wcnt[4];
+        for (int k0 = 0; k0 < ncell && total < kVerifyMax; k0 += kBlock) {
+            const int key = k0 + threadIdx.x;
+            int cell = 0;
+            bool take = false;
+            if (key < ncell) {
+                const int id = key / v.n_q;
+                const int iq = key - id * v.n_q;
+                const double D = v.delta[id];
+                cell = iq * v.n_delta + id;
+                take = D * D != 0.0 && G[cell] <= t;
+            }
+            const unsigned long long b = __ballot(take);
+            __syncthreads();
+            if (lane == 0)
+                wcnt[wave] = __popcll(b);
+            __syncthreads();
+            int at = total;
+            for (int w = 0; w < wave; ++w)
+                at += wcnt[w];
+            at += __popcll(b & ((1ull << lane) - 1ull));
+            if (take && at < kVerifyMax)
+                v.cand[(size_t)sl * kVerifyMax + at] = cell;
+            total += ((wcnt[0] + wcnt[1]) + wcnt[2]) + wcnt[3];
+        }
+        total = total < kVerifyMax ? total : kVerifyMax;
     }
     if (threadIdx.x == 0) {
-        v.cnt[sl] = total < kVerifyMax ? total : kVerifyMax;
+        v.cnt[sl] = total;
         v.thr[sl] = thr;
     }
 }
@@ -2474,18 +2627,32 @@ __global__ __launch_bounds__(64) void verify_pick_kernel(const VerifyArgs v)
               v.n_k * (-2.0 * D * D / v.Vs[slot]);
         key = id * v.n_q + iq;
     }
+    // calls f(id) for every Delta = 0 column in increasing id (found 64
+    // columns at a time)
+    auto zero_columns = [&](auto f) {
+        for (int id0 = 0; id0 < v.n_delta; id0 += 64) {
+            bool z = false;
+            if (id0 + lane < v.n_delta) {
+                const double D = v.delta[id0 + lane];
+                z = D * D == 0.0;
+            }
+            unsigned long long b = __ballot(z);
+            while (b) {
+                const int k = __ffsll((unsigned long long)b) - 1;
+                b &= b - 1ull;
+                f(id0 + k);
+            }
+        }
+    };
     // the lowest checked value: candidates, then the Delta = 0 cells
     double best = val;
-    for (int id = 0; id < v.n_delta; ++id) {
-        const double D = v.delta[id];
-        if (D * D != 0.0)
-            continue;
+    zero_columns([&](int id) {
         for (int iq = lane; iq < v.n_q; iq += 64) {
             const double x = G[(size_t)iq * v.n_delta + id];
             if (x <= thr)
                 best = nan_min(best, x);
         }
-    }
+    });
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1)
         best = nan_min(best, __shfl_xor(best, off, 64));
@@ -2497,10 +2664,7 @@ __global__ __launch_bounds__(64) void verify_pick_kernel(const VerifyArgs v)
             pick = key;
             pv = val;
         }
-        for (int id = 0; id < v.n_delta; ++id) {
-            const double D = v.delta[id];
-            if (D * D != 0.0)
-                continue;
+        zero_columns([&](int id) {
             for (int iq = lane; iq < v.n_q; iq += 64) {
                 const double x = G[(size_t)iq * v.n_delta + id];
                 const int k = id * v.n_q + iq;
@@ -2509,7 +2673,7 @@ __global__ __launch_bounds__(64) void verify_pick_kernel(const VerifyArgs v)
                     pv = x;
                 }
             }
-        }
+        });
     }
     int m = pick;
 #pragma unroll

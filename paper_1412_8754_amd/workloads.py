@@ -74,6 +74,8 @@ def config(name: str) -> dict:
     precision  L=2048, 512 Delta, 128 q = j pi / 1024, h=0.1, T=0.002
     three_band App. B model, L=512, 128 Delta in [0,0.1] eV, 32 q = 2 pi j / 512,
                h=0.01 eV, T=0.0005 eV, all three bands
+    phase_hot  one point of the phase diagram's shape at high temperature:
+               L=1024, 128 Delta, 32 q = j pi / 256, h=0.2, T=0.02
     """
     if name == "small":
         return {"name": name, "pts": [(0.0, 0.001, 64, 64)], "delta": delta_grid(128),
@@ -88,6 +90,9 @@ def config(name: str) -> dict:
         return {"name": name, "pts": [(0.01, 0.0005, 512, 512)],
                 "delta": delta_grid(128, 0.1), "q": q_axis(32, 2.0 * math.pi / 512),
                 "bands": BAND3_ALL, "model": DAGHOFER_MODEL}
+    if name == "phase_hot":
+        return {"name": name, "pts": [(0.2, 0.02, 1024, 1024)], "delta": delta_grid(128),
+                "q": q_axis(32, math.pi / 256), "bands": BAND_BOTH}
     raise KeyError(name)
 
 
