@@ -45,7 +45,28 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # precision x 64 lanes / kernel time / that precision's peak.
 # traffic: HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled
 # by the same counter on a plain 256 MiB device copy (x2.0 and x1.0).
-COUNTERS = {}
+COUNTERS = {
+    ("paper", "fp64"): {
+        "source": "profiles/sweep_f64_paper_L1024.md", "src": "8f7c9fa2d05fc0a4",
+        "fma": 1.1503e8, "add": 3.7788e7, "mul": 6.5294e7, "trans": 1.393e7,
+        "valu_busy": 0.6595, "valu_utilization": 0.8496, "wait_frac": 3.4844e8 / 1.5294e9,
+        "traffic": (13698 * 2 + 26744) * 1024},
+    ("paper", "fp32c"): {
+        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "8f7c9fa2d05fc0a4",
+        "fma": 7.4565e7, "add": 4.1958e7, "mul": 3.3746e7, "trans": 2.5213e7,
+        "valu_busy": 0.7120, "valu_utilization": 0.8156, "wait_frac": 2.1759e8 / 1.5500e9,
+        "traffic": (13499 * 2 + 26744) * 1024},
+    ("phase_hot", "fp64"): {
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "8f7c9fa2d05fc0a4",
+        "fma": 2.0094e8, "add": 6.7071e7, "mul": 8.4577e7, "trans": 1.65e7,
+        "valu_busy": 0.6696, "valu_utilization": 0.9171, "wait_frac": 7.8608e8 / 2.2518e9,
+        "traffic": (22797 * 2 + 4768) * 1024},
+    ("phase_hot", "fp32c"): {
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "8f7c9fa2d05fc0a4",
+        "fma": 1.2693e8, "add": 6.2318e7, "mul": 4.9528e7, "trans": 3.3473e7,
+        "valu_busy": 0.8286, "valu_utilization": 0.9111, "wait_frac": 3.2966e8 / 1.7359e9,
+        "traffic": (56029 * 2 + 39426) * 1024},
+}
 
 
 def kernel_src_digest():
@@ -58,13 +79,14 @@ def kernel_src_digest():
     return h.hexdigest()[:16]
 
 
-def counter_valu_frac(c, precision):
-    """%VALU of the survey's definition from one counter record: the VALU
-    operations of the kernel's precision (FP64, or FP32 for the
-    FP32-compensated sweep) against that precision's vector peak."""
+def counter_valu_frac(c, precision, kernel_ms):
+    """%VALU of the survey's definition: the VALU operations of the kernel's
+    precision (FP64, or FP32 for the FP32-compensated sweep) per launch, from
+    the counter record (instruction counts do not depend on timing), over
+    this run's kernel time, against that precision's vector peak."""
     ops = (2 * c["fma"] + c["add"] + c["mul"] + c["trans"]) * 64
     dt = "f64" if precision == "fp64" else "f32"
-    return ops / (c["kernel_us"] * 1e-6) / (PEAK_TFLOPS[dt] * 1e12)
+    return ops / (kernel_ms * 1e-3) / (PEAK_TFLOPS[dt] * 1e12)
 
 
 def sweep_kernel_name(precision, three, T):
@@ -91,10 +113,10 @@ def roofline_record(workload, precision, achieved, peak, three, T, sweep_ms, dir
         fresh = c["src"] == kernel_src_digest()
         rec["traffic"] = c["traffic"] if fresh else None
         rec["counters"] = {"source": c["source"], "src": c["src"], "stale": not fresh,
-                           "valu_frac": counter_valu_frac(c, precision),
+                           "valu_frac": counter_valu_frac(c, precision, sweep_ms),
                            "valu_busy": c["valu_busy"],
                            "valu_utilization": c["valu_utilization"],
-                           "wait_frac": c["wait_frac"], "kernel_us": c["kernel_us"]}
+                           "wait_frac": c["wait_frac"]}
     return rec
 
 

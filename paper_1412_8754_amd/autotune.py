@@ -92,6 +92,11 @@ def tune(model, pts, delta, q, bands: int = 3, precision: int = 0, reps: int = 3
     ws = torch.empty(api.workspace_bytes(pts, d.numel(), qq.shape[0], bands, precision),
                      dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    # warm-up before any timing, so that the first candidate does not carry
+    # the first call's one-time costs
+    for _ in range(2):
+        api.argmin(model, pts, d, qq, bands, precision, workspace=ws, keep_grid=False)
+    torch.cuda.synchronize()
     times = {}
     for (b, nq) in (candidates or CANDIDATES):
         launch = {"sweep_blocks_per_cu": b, "sweep_queues": nq}
