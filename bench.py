@@ -622,6 +622,7 @@ def main():
         out["autotune"] = {"sweep_blocks_per_cu": tune["sweep_blocks_per_cu"],
                            "sweep_queues": tune["sweep_queues"], "tuned_call_ms": tune["ms"],
                            "default_call_ms": tune["default_ms"],
+                           "candidates_ms": tune["times_ms"],
                            "note": "launch options only; results are bitwise those of the "
                                    "default options"}
     om_first = om.cpu().numpy()

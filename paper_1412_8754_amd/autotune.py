@@ -80,8 +80,9 @@ def lookup(pts, n_delta: int, n_q: int, bands: int, precision: int, arch: str | 
 
 def tune(model, pts, delta, q, bands: int = 3, precision: int = 0, reps: int = 3,
          candidates=None, save: bool = True) -> dict:
-    """Time every candidate on this call (after one untimed call each) and
-    keep the fastest; returns its options with the per-candidate times."""
+    """Time every candidate on this call (after one untimed call each; best
+    of `reps` rounds over all candidates) and keep the fastest; returns its
+    options with the per-candidate times."""
     import torch
 
     from . import api
@@ -97,13 +98,17 @@ def tune(model, pts, delta, q, bands: int = 3, precision: int = 0, reps: int = 3
     for _ in range(2):
         api.argmin(model, pts, d, qq, bands, precision, workspace=ws, keep_grid=False)
     torch.cuda.synchronize()
+    # every candidate once per round, best of the rounds: clock and cache
+    # drift over the tuning then affects all candidates alike, instead of
+    # penalising the ones timed first
+    cands = list(candidates or CANDIDATES)
+    for (b, nq) in cands:
+        api.argmin(model, pts, d, qq, bands, precision, workspace=ws,
+                   launch={"sweep_blocks_per_cu": b, "sweep_queues": nq}, keep_grid=False)
     times = {}
-    for (b, nq) in (candidates or CANDIDATES):
-        launch = {"sweep_blocks_per_cu": b, "sweep_queues": nq}
-        api.argmin(model, pts, d, qq, bands, precision, workspace=ws, launch=launch,
-                   keep_grid=False)
-        best = None
-        for _ in range(reps):
+    for _ in range(reps):
+        for (b, nq) in cands:
+            launch = {"sweep_blocks_per_cu": b, "sweep_queues": nq}
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -112,8 +117,8 @@ def tune(model, pts, delta, q, bands: int = 3, precision: int = 0, reps: int = 3
             e1.record(stream)
             e1.synchronize()
             ms = e0.elapsed_time(e1)
-            best = ms if best is None else min(best, ms)
-        times[f"{b},{nq}"] = best
+            key = f"{b},{nq}"
+            times[key] = ms if key not in times else min(times[key], ms)
     (b, nq) = min((tuple(int(x) for x in k.split(",")) for k in times),
                   key=lambda k: times[f"{k[0]},{k[1]}"])
     entry = {"sweep_blocks_per_cu": b, "sweep_queues": nq, "ms": times[f"{b},{nq}"],
