@@ -1224,7 +1224,6 @@ __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float 
                                           const float2 *dp, float Tf, float invTs,
                                           float cutTf, const float4 *gt)
 {
-    const bool hot0 = f.P0 != 0.0f;
     const bool pos = f.A0 >= 0.0f;
     float2 dcur = dp[0];
 #pragma unroll
@@ -1236,10 +1235,11 @@ __device__ __forceinline__ void f32_steps(float (&acc)[TD], const KQf &f, float 
         const float x = f.A0 + del;
         float piece = pos ? del : fmaxf(x, 0.0f);
         const float ax = fabsf(x);
-        if (ax < cutTf || hot0) {
-            const float L = ax < cutTf ? thermal_log_f32(ax, R + f.m, invTs, cutTf, gt) : 0.0f;
-            piece += fmaf(Tf, L, -f.P0);
-        }
+        // beyond the cut only -P(0) is left of the thermal part
+        if (ax < cutTf)
+            piece += fmaf(Tf, thermal_log_f32(ax, R + f.m, invTs, cutTf, gt), -f.P0);
+        else
+            piece -= f.P0;
         acc[t] = fmaf(wf, piece, acc[t]);
         dcur = dnext;
     }
@@ -1831,7 +1831,6 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
                                             eps, mu_up, mu_dn, cqx, sqx, cqy, sqy);
                 const KQf r = kq_setup_f32(q64, T, invT, gt32);
                 const float wf = (float)mirror_weight(kr, i, j, a.Lx, a.Ly);
-                const bool hot0 = r.P0 != 0.0f;
                 const bool pos = r.A0 >= 0.0f;
                 float2 dcur = dp[0];
 #pragma unroll
@@ -1843,12 +1842,10 @@ void sweep_f32c_hot_kernel(const SweepArgs args)
                     float x = r.A0 + del;
                     float piece = pos ? del : fmaxf(x, 0.0f);
                     float ax = fabsf(x);
-                    if (ax < cutTf || hot0) {
-                        float L = ax < cutTf
-                                      ? thermal_log_f32(ax, R + r.m, invTs, cutTf, gt32)
-                                      : 0.0f;
-                        piece += fmaf(Tf, L, -r.P0);
-                    }
+                    if (ax < cutTf)
+                        piece += fmaf(Tf, thermal_log_f32(ax, R + r.m, invTs, cutTf, gt32), -r.P0);
+                    else
+                        piece -= r.P0;
                     acc[t] = fmaf(wf, piece, acc[t]);
                     dcur = dnext;
                 }
