@@ -47,25 +47,25 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # by the same counter on a plain 256 MiB device copy (x2.0 and x1.0).
 COUNTERS = {
     ("paper", "fp64"): {
-        "source": "profiles/sweep_f64_paper_L1024.md", "src": "8f7c9fa2d05fc0a4",
+        "source": "profiles/sweep_f64_paper_L1024.md", "src": "e71010d004030952",
         "fma": 1.1503e8, "add": 3.7788e7, "mul": 6.5294e7, "trans": 1.393e7,
-        "valu_busy": 0.6595, "valu_utilization": 0.8496, "wait_frac": 3.4844e8 / 1.5294e9,
-        "traffic": (13698 * 2 + 26744) * 1024},
+        "valu_busy": 0.6630, "valu_utilization": 0.8496, "wait_frac": 3.4843e8 / 1.5298e9,
+        "traffic": (13702 * 2 + 26744) * 1024},
     ("paper", "fp32c"): {
-        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "8f7c9fa2d05fc0a4",
-        "fma": 7.4565e7, "add": 4.1958e7, "mul": 3.3746e7, "trans": 2.5213e7,
-        "valu_busy": 0.7120, "valu_utilization": 0.8156, "wait_frac": 2.1759e8 / 1.5500e9,
-        "traffic": (13499 * 2 + 26744) * 1024},
+        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "e71010d004030952",
+        "fma": 6.9851e7, "add": 4.9527e7, "mul": 3.3746e7, "trans": 2.5213e7,
+        "valu_busy": 0.7229, "valu_utilization": 0.8199, "wait_frac": 2.1707e8 / 1.5125e9,
+        "traffic": (13502 * 2 + 26744) * 1024},
     ("phase_hot", "fp64"): {
-        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "8f7c9fa2d05fc0a4",
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "e71010d004030952",
         "fma": 2.0094e8, "add": 6.7071e7, "mul": 8.4577e7, "trans": 1.65e7,
-        "valu_busy": 0.6696, "valu_utilization": 0.9171, "wait_frac": 7.8608e8 / 2.2518e9,
-        "traffic": (22797 * 2 + 4768) * 1024},
+        "valu_busy": 0.6717, "valu_utilization": 0.9171, "wait_frac": 7.8599e8 / 2.2514e9,
+        "traffic": (22874 * 2 + 4768) * 1024},
     ("phase_hot", "fp32c"): {
-        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "8f7c9fa2d05fc0a4",
-        "fma": 1.2693e8, "add": 6.2318e7, "mul": 4.9528e7, "trans": 3.3473e7,
-        "valu_busy": 0.8286, "valu_utilization": 0.9111, "wait_frac": 3.2966e8 / 1.7359e9,
-        "traffic": (56029 * 2 + 39426) * 1024},
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "e71010d004030952",
+        "fma": 1.2650e8, "add": 7.8373e7, "mul": 4.9528e7, "trans": 3.3473e7,
+        "valu_busy": 0.8661, "valu_utilization": 0.8870, "wait_frac": 3.3882e8 / 1.7162e9,
+        "traffic": (44701 * 2 + 32542) * 1024},
 }
 
 
