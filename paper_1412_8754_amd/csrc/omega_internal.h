@@ -135,11 +135,15 @@ struct SeriesLevelRho {
 // (R(x_lo) >= |d| + 30 T: R - |d| >= 30 T for every Delta of the tile, no
 // thermal part) has R - |d| = (Rc - |d|) + Rc sum_{n>=1} c_n z^n with
 // Rc^2 = s^2 + xc eta^2 and z = (x - xc) eta^2 / Rc^2.  Where
-// ht eta^2 <= kTileRho Rc^2 it is summed through kTileSlots moments per tile
-// (C0 = sum w (Rc - |d|), M_n = sum w Rc (eta^2/Rc^2)^n, n <= kTileTerms);
-// the truncation is below |c_16| 0.15^16 / 0.85 = 3.5e-16 of Rc.  Terms with
-// R(x_hi) <= |d| - 30 T are exactly zero over the tile.
-constexpr double kTileRho = 0.15;
+// u = ht eta^2 / Rc^2 <= kTileRho it is summed through kTileSlots moments per
+// tile (C0 = sum w (Rc - |d|), M_n = sum w Rc (eta^2/Rc^2)^n, n <=
+// kTileTerms); the truncation is below |c_16| u^16 / (1 - u) Rc, at most
+// 6.7e-15 Rc.  With Rc = (ht eta^2 / u)^(1/2) that is at most
+// (ht)^(1/2) |c_16| 0.18^15.5 / 0.82 = 3.2e-15 per term for Delta^2 tiles of
+// half-width ht <= 0.042 (Delta up to 0.6 in 8 tiles), 1.1e-13 of the scale
+// |Omega| >= 0.03 N.  Terms with R(x_hi) <= |d| - 30 T are exactly zero over
+// the tile.
+constexpr double kTileRho = 0.18;
 constexpr int kTileTerms = 15;
 constexpr int kTileSlots = 16;
 constexpr int kTileBatch = 64;   // Delta tiles per LDS batch of the rows kernel
