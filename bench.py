@@ -47,25 +47,25 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # by the same counter on a plain 256 MiB device copy (x2.0 and x1.0).
 COUNTERS = {
     ("paper", "fp64"): {
-        "source": "profiles/sweep_f64_paper_L1024.md", "src": "e71010d004030952",
-        "fma": 1.1503e8, "add": 3.7788e7, "mul": 6.5294e7, "trans": 1.393e7,
-        "valu_busy": 0.6630, "valu_utilization": 0.8496, "wait_frac": 3.4843e8 / 1.5298e9,
-        "traffic": (13702 * 2 + 26744) * 1024},
+        "source": "profiles/sweep_f64_paper_L1024.md", "src": "a44cbe2087187e6d",
+        "fma": 1.0535e8, "add": 3.4742e7, "mul": 6.0912e7, "trans": 1.1491e7,
+        "valu_busy": 0.6384, "valu_utilization": 0.8464, "wait_frac": 3.1935e8 / 1.4153e9,
+        "traffic": (13697 * 2 + 26744) * 1024},
     ("paper", "fp32c"): {
-        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "e71010d004030952",
-        "fma": 6.9851e7, "add": 4.9527e7, "mul": 3.3746e7, "trans": 2.5213e7,
-        "valu_busy": 0.7229, "valu_utilization": 0.8199, "wait_frac": 2.1707e8 / 1.5125e9,
-        "traffic": (13502 * 2 + 26744) * 1024},
+        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "a44cbe2087187e6d",
+        "fma": 6.1685e7, "add": 4.1568e7, "mul": 2.8404e7, "trans": 2.0007e7,
+        "valu_busy": 0.6931, "valu_utilization": 0.8097, "wait_frac": 2.0591e8 / 1.4034e9,
+        "traffic": (13497 * 2 + 26744) * 1024},
     ("phase_hot", "fp64"): {
-        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "e71010d004030952",
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "a44cbe2087187e6d",
         "fma": 2.0094e8, "add": 6.7071e7, "mul": 8.4577e7, "trans": 1.65e7,
-        "valu_busy": 0.6717, "valu_utilization": 0.9171, "wait_frac": 7.8599e8 / 2.2514e9,
-        "traffic": (22874 * 2 + 4768) * 1024},
+        "valu_busy": 0.6487, "valu_utilization": 0.9171, "wait_frac": 7.8584e8 / 2.2514e9,
+        "traffic": (22811 * 2 + 4768) * 1024},
     ("phase_hot", "fp32c"): {
-        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "e71010d004030952",
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "a44cbe2087187e6d",
         "fma": 1.2650e8, "add": 7.8373e7, "mul": 4.9528e7, "trans": 3.3473e7,
-        "valu_busy": 0.8661, "valu_utilization": 0.8870, "wait_frac": 3.3882e8 / 1.7162e9,
-        "traffic": (44701 * 2 + 32542) * 1024},
+        "valu_busy": 0.8481, "valu_utilization": 0.8870, "wait_frac": 3.3861e8 / 1.7148e9,
+        "traffic": (44851 * 2 + 32587) * 1024},
 }
 
 
@@ -107,7 +107,9 @@ def roofline_record(workload, precision, achieved, peak, three, T, sweep_ms, dir
     rec = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
            "frac": achieved / peak, "traffic": None,
            "kernel": sweep_kernel_name(precision, three, T), "kernel_ms": sweep_ms,
-           "ops_per_eval": OPS_PER_EVAL, "units": direct}
+           "ops_per_eval": OPS_PER_EVAL, "units": direct,
+           "units_note": "(k, Delta) terms the kernel evaluates one by one; terms it sums "
+                         "through Delta-tile series are not counted"}
     c = COUNTERS.get((workload, precision))
     if c is not None:
         fresh = c["src"] == kernel_src_digest()
