@@ -3057,13 +3057,233 @@ __global__ __launch_bounds__(kBlock) void lo_cycle_kernel(const LoArgs a)
             ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// Cycles of at most 64 modes: one wave per cycle, kLoWaves cycles per
+// workgroup, no workgroup barrier.  The symmetric matrix is kept once, as
+// its upper triangle packed by rows in LDS.  Each step applies the n/2
+// disjoint rotations of the round-robin ordering (the same pairs and the
+// same c, s as lo_cycle_kernel) as 2 x 2 block updates: the block of rows
+// (p_a, q_a) and columns (p_b, q_b) of each pair of pairs a <= b becomes
+// R_a^T B R_b (rows first, then columns, as in lo_cycle_kernel), and the
+// pivot element of a diagonal block is set to zero.  Every matrix element
+// is read and written once per step.
+constexpr int kLoWaves = 4;
+
+__device__ __forceinline__ int lo_tri(int i, int j, int n)
+{
+    // (i, j) with i <= j in the packed upper triangle
+    return i * n - ((i * (i - 1)) >> 1) + (j - i);
+}
+
+__device__ __forceinline__ int lo_sym(int i, int j, int n)
+{
+    return i <= j ? lo_tri(i, j, n) : lo_tri(j, i, n);
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(64 * kLoWaves) void lo_wave_kernel(const LoArgs a)
+{
+    constexpr int PACK = NMAX * (NMAX + 1) / 2;
+    __shared__ double Aw[kLoWaves][PACK];
+    __shared__ double csw[kLoWaves][NMAX / 2][2];
+    __shared__ int pqw[kLoWaves][NMAX / 2][2];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = a.n;
+    const int h = n / 2;
+    const int n_cyc = a.Ls * a.g;
+    const int cyc = blockIdx.x * kLoWaves + wave;
+    if (cyc >= n_cyc)
+        return;
+    double *A = Aw[wave];
+    double(*cs)[2] = csw[wave];
+    int(*pq)[2] = pqw[wave];
+    const int sector = cyc / a.g;
+    const int r = cyc - sector * a.g;
+    const int id = blockIdx.y;
+    const int slot = blockIdx.z;
+    const double eps = slot ? a.eps[1] : a.eps[0];
+    const double D = a.delta[id];
+    double ssec, csec;
+    sincospi(2.0 * sector / a.Ls, &ssec, &csec);
+    const int npack = n * (n + 1) / 2;
+    for (int x = lane; x < npack; x += 64)
+        A[x] = 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // diagonal, couplings, and xi_down of the cycle's spin-up momenta (the
+    // node layout of lo_cycle_kernel)
+    double cdn = 0.0;
+    for (int t = lane; t < h; t += 64) {
+        const int jc = (int)(((long long)r - 2LL * t * a.s) % a.Lc + a.Lc) % a.Lc;
+        const int jd = (int)(((long long)r - (2LL * t + 1) * a.s) % a.Lc + a.Lc) % a.Lc;
+        const int jn = (int)(((long long)r - (2LL * t + 2) * a.s) % a.Lc + a.Lc) % a.Lc;
+        double sc, cc, sd, cd, sn, cn;
+        sincospi(2.0 * jc / a.Lc, &sc, &cc);
+        sincospi(2.0 * jd / a.Lc, &sd, &cd);
+        sincospi(2.0 * jn / a.Lc, &sn, &cn);
+        const double Ec = a.along_y ? band_energy(a.hop, eps, csec, ssec, cc, sc)
+                                    : band_energy(a.hop, eps, cc, sc, csec, ssec);
+        const double Ed = a.along_y ? band_energy(a.hop, eps, csec, ssec, cd, sd)
+                                    : band_energy(a.hop, eps, cd, sd, csec, ssec);
+        const double eta_c = csec * cc, eta_n = csec * cn;
+        A[lo_tri(2 * t, 2 * t, n)] = Ec - (a.mu + a.h);
+        A[lo_tri(2 * t + 1, 2 * t + 1, n)] = -(Ed - (a.mu - a.h));
+        cdn += Ec - (a.mu - a.h);
+        if (n > 2) {
+            A[lo_tri(2 * t, 2 * t + 1, n)] = D * eta_c;
+            A[lo_sym(2 * t + 1, (2 * t + 2) % n, n)] = D * eta_n;
+        } else {
+            // both waves join the same two modes (2q = 0)
+            A[lo_tri(0, 1, n)] = 2.0 * D * eta_c;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // pairs of pairs a <= b, folded so that consecutive indices fill rows
+    // r and H - 1 - r (H = h rounded up to even; pair index h, if any, is a
+    // placeholder and skipped); at most (NMAX/2 + 1) NMAX/4 of them
+    // this lane's blocks, (a | b << 8) or -1, fixed for the whole cycle
+    constexpr int NB = ((NMAX / 2 + 1) * (NMAX / 4) + 63) / 64;
+    int blk[NB];
+    {
+        const int H = h + (h & 1);
+        const int nblk = (H / 2) * (H + 1);
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            const int k = lane + 64 * m;
+            int code = -1;
+            if (k < nblk) {
+                const int rr = k / (H + 1);
+                const int e = k - rr * (H + 1);
+                int ia, ib;
+                if (e < H - rr) {
+                    ia = rr;
+                    ib = rr + e;
+                } else {
+                    ia = H - 1 - rr;
+                    ib = ia + (e - (H - rr));
+                }
+                if (ib < h)
+                    code = ia | (ib << 8);
+            }
+            blk[m] = code;
+        }
+    }
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        // off-diagonal against total squared Frobenius norm
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const int row = lo_tri(i, i, n);
+            for (int j = i + 1 + lane; j < n; j += 64) {
+                const double v = A[row + (j - i)];
+                off += v * v;
+            }
+        }
+        for (int i = lane; i < n; i += 64) {
+            const double v = A[lo_tri(i, i, n)];
+            dia += v * v;
+        }
+        // both triangles off the diagonal, and the whole matrix
+        const double offs = 2.0 * wave_sum(off);
+        const double tots = offs + wave_sum(dia);
+        if (!(offs > 1e-32 * tots))
+            break;
+        for (int step = 0; step < n - 1; ++step) {
+            // round robin: mode n - 1 meets mode step, (step + i, step - i) mod n - 1
+            for (int i = lane; i < h; i += 64) {
+                int p, q;
+                if (i == 0) {
+                    p = step;
+                    q = n - 1;
+                } else {
+                    p = (step + i) % (n - 1);
+                    q = (step - i + (n - 1)) % (n - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                const double app = A[lo_tri(p, p, n)], aqq = A[lo_tri(q, q, n)],
+                             apq = A[lo_tri(p, q, n)];
+                double c = 1.0, sn = 0.0;
+                if (apq != 0.0) {
+                    const double th = (aqq - app) / (2.0 * apq);
+                    const double t = copysign(1.0, th) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+                    c = 1.0 / sqrt(fma(t, t, 1.0));
+                    sn = t * c;
+                }
+                cs[i][0] = c;
+                cs[i][1] = sn;
+                pq[i][0] = p;
+                pq[i][1] = q;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                if (blk[m] < 0)
+                    continue;
+                const int ia = blk[m] & 255, ib = blk[m] >> 8;
+                const int pa = pq[ia][0], qa = pq[ia][1];
+                const double ca = cs[ia][0], sa = cs[ia][1];
+                if (ia == ib) {
+                    const int ip = lo_tri(pa, pa, n), iq = lo_tri(qa, qa, n),
+                              ipq = lo_tri(pa, qa, n);
+                    const double app = A[ip], aqq = A[iq], apq = A[ipq];
+                    // rows p, q, then columns p, q; the pivot becomes 0
+                    const double xpp = ca * app - sa * apq, xqp = sa * app + ca * apq;
+                    const double xpq = ca * apq - sa * aqq, xqq = sa * apq + ca * aqq;
+                    A[ip] = ca * xpp - sa * xpq;
+                    A[iq] = sa * xqp + ca * xqq;
+                    A[ipq] = 0.0;
+                } else {
+                    const int pb = pq[ib][0], qb = pq[ib][1];
+                    const double cb = cs[ib][0], sb = cs[ib][1];
+                    const int i00 = lo_sym(pa, pb, n), i01 = lo_sym(pa, qb, n),
+                              i10 = lo_sym(qa, pb, n), i11 = lo_sym(qa, qb, n);
+                    const double b00 = A[i00], b01 = A[i01], b10 = A[i10], b11 = A[i11];
+                    // rows (p_a, q_a) by R_a
+                    const double x00 = ca * b00 - sa * b10, x10 = sa * b00 + ca * b10;
+                    const double x01 = ca * b01 - sa * b11, x11 = sa * b01 + ca * b11;
+                    // columns (p_b, q_b) by R_b
+                    A[i00] = cb * x00 - sb * x01;
+                    A[i01] = sb * x00 + cb * x01;
+                    A[i10] = cb * x10 - sb * x11;
+                    A[i11] = sb * x10 + cb * x11;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    // -T ln(1 + e^{-E/T}) over the eigenvalues, as min(E, 0) - T log1p(e^{-|E|/T})
+    double sum = cdn, cmp = 0.0;
+    const double invT = a.T > 0.0 ? 1.0 / a.T : 0.0;
+    for (int i = lane; i < n; i += 64) {
+        const double E = A[lo_tri(i, i, n)];
+        double v = fmin(E, 0.0);
+        if (a.T > 0.0)
+            v -= a.T * log1p_small(exp_nonpos(-fmin(fabs(E) * invT, 700.0)));
+        neumaier(sum, cmp, v);
+    }
+    const double w = wave_sum(sum + cmp);
+    if (lane == 0)
+        a.part[((size_t)slot * a.n_delta + id) * (size_t)n_cyc + cyc] = w;
+}
+
 hipError_t launch_lo(const LoArgs &a, int nb, hipStream_t s)
 {
     const dim3 grid(a.Ls * a.g, a.n_delta, nb);
+    const dim3 wgrid((a.Ls * a.g + kLoWaves - 1) / kLoWaves, a.n_delta, nb);
     if (a.n <= 32)
-        hipLaunchKernelGGL(lo_cycle_kernel<32>, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(lo_wave_kernel<32>, wgrid, dim3(64 * kLoWaves), 0, s, a);
     else if (a.n <= 64)
-        hipLaunchKernelGGL(lo_cycle_kernel<64>, grid, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL(lo_wave_kernel<64>, wgrid, dim3(64 * kLoWaves), 0, s, a);
     else if (a.n <= kLoMaxCycle)
         hipLaunchKernelGGL(lo_cycle_kernel<kLoMaxCycle>, grid, dim3(kBlock), 0, s, a);
     else
