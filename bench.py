@@ -47,25 +47,25 @@ PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # MI355X dense vector peaks
 # by the same counter on a plain 256 MiB device copy (x2.0 and x1.0).
 COUNTERS = {
     ("paper", "fp64"): {
-        "source": "profiles/sweep_f64_paper_L1024.md", "src": "a44cbe2087187e6d",
-        "fma": 1.0535e8, "add": 3.4742e7, "mul": 6.0912e7, "trans": 1.1491e7,
-        "valu_busy": 0.6384, "valu_utilization": 0.8464, "wait_frac": 3.1935e8 / 1.4153e9,
-        "traffic": (13697 * 2 + 26744) * 1024},
+        "source": "profiles/sweep_f64_paper_L1024.md", "src": "a9baab64d3d53cd5",
+        "fma": 1.0535e+08, "add": 3.4742e+07, "mul": 6.0912e+07, "trans": 1.1491e+07,
+        "valu_busy": 0.6411, "valu_utilization": 0.8464, "wait_frac": 3.1926e+08 / 1.4157e+09,
+        "traffic": (13703 * 2 + 26744) * 1024},
     ("paper", "fp32c"): {
-        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "a44cbe2087187e6d",
-        "fma": 6.1685e7, "add": 4.1568e7, "mul": 2.8404e7, "trans": 2.0007e7,
-        "valu_busy": 0.6931, "valu_utilization": 0.8097, "wait_frac": 2.0591e8 / 1.4034e9,
-        "traffic": (13497 * 2 + 26744) * 1024},
+        "source": "profiles/sweep_f32c_paper_L1024.md", "src": "a9baab64d3d53cd5",
+        "fma": 6.1685e+07, "add": 4.1568e+07, "mul": 2.8404e+07, "trans": 2.0007e+07,
+        "valu_busy": 0.6986, "valu_utilization": 0.8097, "wait_frac": 2.0595e+08 / 1.4041e+09,
+        "traffic": (13503 * 2 + 26744) * 1024},
     ("phase_hot", "fp64"): {
-        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "a44cbe2087187e6d",
-        "fma": 2.0094e8, "add": 6.7071e7, "mul": 8.4577e7, "trans": 1.65e7,
-        "valu_busy": 0.6487, "valu_utilization": 0.9171, "wait_frac": 7.8584e8 / 2.2514e9,
-        "traffic": (22811 * 2 + 4768) * 1024},
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "a9baab64d3d53cd5",
+        "fma": 2.0094e+08, "add": 6.7071e+07, "mul": 8.4577e+07, "trans": 1.6500e+07,
+        "valu_busy": 0.6720, "valu_utilization": 0.9171, "wait_frac": 7.8624e+08 / 2.2509e+09,
+        "traffic": (23100 * 2 + 4768) * 1024},
     ("phase_hot", "fp32c"): {
-        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "a44cbe2087187e6d",
-        "fma": 1.2650e8, "add": 7.8373e7, "mul": 4.9528e7, "trans": 3.3473e7,
-        "valu_busy": 0.8481, "valu_utilization": 0.8870, "wait_frac": 3.3861e8 / 1.7148e9,
-        "traffic": (44851 * 2 + 32587) * 1024},
+        "source": "profiles/sweep_hot_phase_point_L1024.md", "src": "a9baab64d3d53cd5",
+        "fma": 1.2650e+08, "add": 7.8373e+07, "mul": 4.9528e+07, "trans": 3.3473e+07,
+        "valu_busy": 0.8563, "valu_utilization": 0.8870, "wait_frac": 3.3815e+08 / 1.7141e+09,
+        "traffic": (46369 * 2 + 32571) * 1024},
 }
 
 
