@@ -80,7 +80,7 @@ def kernel_src_digest():
 
 
 def counter_valu_frac(c, precision, kernel_ms):
-    """%VALU of the survey's definition: the VALU operations of the kernel's
+    """%VALU by instruction counters: the VALU operations of the kernel's
     precision (FP64, or FP32 for the FP32-compensated sweep) per launch, from
     the counter record (instruction counts do not depend on timing), over
     this run's kernel time, against that precision's vector peak."""
