@@ -19,12 +19,15 @@ from ._abi import (OMEGA3_BAND_ALL, OMEGA_BAND_BOTH, OMEGA_FP32_COMP,  # noqa: F
 
 def _stream_ptr(stream, *tensors) -> int:
     """The HIP stream handle of a call (the current stream unless one is
-    given).  On another stream, the call's device tensors (inputs, outputs,
-    workspace) are recorded as used there, so that the caching allocator does
-    not hand their memory out again before that stream's work is done."""
+    given).  On another stream, the call first waits for the work queued on
+    the current stream (where its inputs were copied and its outputs and
+    workspace allocated), and the call's device tensors are recorded as used
+    there, so that the caching allocator does not hand their memory out again
+    before that stream's work is done."""
     cur = torch.cuda.current_stream()
     s = stream if stream is not None else cur
     if s != cur:
+        s.wait_stream(cur)
         for t in tensors:
             if t is not None:
                 t.record_stream(s)

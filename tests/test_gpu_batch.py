@@ -109,6 +109,24 @@ def test_batched_gradients_against_oracle():
             assert (np.abs(got - ref) <= 1e-12 * np.abs(ref) + 1e-13 * N).all(), (got, ref)
 
 
+def test_call_on_a_side_stream_matches_the_current_stream():
+    """A call given another stream waits for the current stream's work (its
+    inputs, outputs and workspace are made there) and returns what the same
+    call on the current stream returns, bitwise, for device and host inputs."""
+    pts = mixed_points(4, 11)
+    delta = torch.linspace(0, 0.6, 33, dtype=torch.float64, device="cuda")
+    q = torch.tensor([[0.0, 0.0], [0.2, 0.0]], dtype=torch.float64, device="cuda")
+    say("case: argmin on a side stream, 4 points, 33 Delta, 2 Q")
+    ref = api.argmin(M, pts, delta, q, 3, OMEGA_FP64)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    for dl, qq in ((delta, q), (delta.cpu().numpy(), q.cpu().numpy())):
+        got = api.argmin(M, pts, dl, qq, 3, OMEGA_FP64, stream=s)
+        s.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b)
+
+
 def test_captured_graph_replays_match_eager():
     pts = mixed_points(5, 9)
     dev = "cuda"
